@@ -1,0 +1,177 @@
+/*
+ * isg.h - C ABI of the MI355X (gfx950) image-space gridding / nonrigid SENSE
+ * library.
+ *
+ * The library computes, on one GPU, the operators of Jang, Malave and
+ * Nishimura, "Image-Space Gridding for Nonrigid Motion-Corrected MR Image
+ * Reconstruction" (arXiv:2501.16713):
+ *
+ *   T_d    forward image-space gridding, the warp m(r + d(r))   (Eq. 5, Eq. 9)
+ *   T_d^H  adjoint image-space gridding                          (Eq. 7, Eq. 8)
+ *   A_p    nonrigid SENSE operator G_p S T_{d_p}                 (Eq. 10, Figs. 2-3)
+ *   A_p^H  its adjoint T_{d_p}^H S^H G_p^H                       (Fig. 3b)
+ *   N      sum_p A_p^H A_p + lambda I, the l2 normal operator of Eq. 11
+ *   CG     conjugate gradients on N x = sum_p A_p^H y_p
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Every call returns an isg_status; ISG_OK is 0.  No C++ exception crosses
+ * the ABI.  On any other status isg_last_error() returns a message for the
+ * calling thread.  Arguments are validated before anything is enqueued, so a
+ * validation error leaves every output untouched.
+ *
+ * Device buffers are plain device pointers owned by the caller; they must stay
+ * valid until the plan's stream has passed the call.  The library owns plans,
+ * motions, trajectories and everything derived from them (tap tables, tile
+ * bins, FFT twiddles, deapodization tables, scratch grids) and frees them in
+ * the matching *_destroy call.
+ *
+ * Apply calls (warp, warp_adjoint, warp_grad_d, sense_*, normal) are
+ * asynchronous on the plan's stream.  *_create calls are synchronous with
+ * respect to their input buffers: the caller may reuse them on return.
+ * isg_cg_solve synchronizes the stream before it returns.
+ *
+ * A plan is not thread-safe.  Different plans may run concurrently on
+ * different streams.  A device error makes the plan fail every later call
+ * with ISG_ERR_STATE until it is destroyed.
+ *
+ * Layouts (C order, slowest index first)
+ *   image  x      complex64 (interleaved float re, im) [n0][n1][n2]   (2D: [n0][n1])
+ *   field  d      float32 [ndim][n0][n1][n2], in voxels; component i
+ *                 displaces along array axis i; pull convention: the warped
+ *                 image at voxel r is the object at r + d(r)              (Eq. 5)
+ *   coils  S      complex64 [C][n0][n1][n2]
+ *   traj   k      float32 [M][ndim] in cycles/voxel, in [-0.5, 0.5);
+ *                 component i is along array axis i; image voxel index j
+ *                 sits at the centred position j - n/2
+ *   data   y      complex64, states packed one after another; state p holds
+ *                 [M_p][C] (sample-major, coils contiguous).
+ *
+ * Numerics: Kaiser-Bessel kernel of width 4 on a 2x oversampled periodic
+ * grid, beta = pi*sqrt(4*(1.5)^2 - 0.8); FP32 arithmetic (FP64 for the
+ * k-space coordinates at plan time and for the CG inner products and
+ * scalars).  The k-space pair is scaled so that G approximates the
+ * orthonormal NDFT |N|^{-1/2} sum_x z[x] exp(-2 pi i k.x); T is scaled so that
+ * T_0 approximates the identity.
+ */
+#ifndef ISG_H
+#define ISG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ISG_OK = 0,
+  ISG_ERR_INVALID_ARG = 1,       /* null pointer, bad count, bad enum, size mismatch */
+  ISG_ERR_UNSUPPORTED_SHAPE = 2, /* n_i not even, < 8, > 512, or with a prime factor > 5 */
+  ISG_ERR_OUT_OF_MEMORY = 3,     /* a device or host allocation failed */
+  ISG_ERR_DEVICE = 4,            /* no usable GPU, or a HIP runtime error */
+  ISG_ERR_NOT_FINITE = 5,        /* NaN/Inf in a displacement field or trajectory */
+  ISG_ERR_CG_BREAKDOWN = 6,      /* Re<p, N p> <= 0 or non-finite during CG */
+  ISG_ERR_STATE = 7              /* plan previously hit a device error */
+} isg_status;
+
+/* element type of the coil-expanded oversampled k-space grids */
+typedef enum {
+  ISG_STORE_FP32 = 0,
+  ISG_STORE_BF16 = 1,
+  ISG_STORE_FP16 = 2
+} isg_storage;
+
+typedef struct isg_plan isg_plan;     /* shape, tables, scratch; library-owned */
+typedef struct isg_motion isg_motion; /* prepared displacement field d_p       */
+typedef struct isg_traj isg_traj;     /* prepared trajectory k_p               */
+
+typedef struct {
+  int ndim;            /* 2 or 3 */
+  int64_t n[3];        /* image shape; n[2] ignored when ndim == 2 */
+  int ncoils;          /* C >= 1 (1..32) */
+  int nphases;         /* P >= 1: most states one call may pass */
+  isg_storage storage; /* storage of the coil-expanded k-space grids */
+  void* stream;        /* hipStream_t to enqueue on; NULL = the null stream */
+} isg_plan_desc;
+
+/* Library version string, e.g. "isg 0.1 gfx950".  Never fails. */
+const char* isg_version(void);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char* isg_last_error(void);
+
+/* Number of visible GPUs in *count (0 on a host without one: ISG_OK). */
+isg_status isg_device_count(int* count);
+
+/* Create a plan: validates the shape, builds twiddle and deapodization
+ * tables and allocates the scratch the operators need.  Errors:
+ * INVALID_ARG, UNSUPPORTED_SHAPE, DEVICE (no GPU), OUT_OF_MEMORY. */
+isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** plan);
+isg_status isg_plan_destroy(isg_plan* plan);
+/* Change the stream later calls enqueue on. */
+isg_status isg_plan_set_stream(isg_plan* plan, void* stream);
+/* Device bytes the plan currently holds. */
+isg_status isg_plan_device_bytes(const isg_plan* plan, int64_t* bytes);
+
+/* Prepare a displacement field d (device float32 [ndim][n...], voxels) for
+ * T_d / T_d^H (Eq. 5): tap bases and tile bins for the spreading adjoint.
+ * NOT_FINITE if d holds NaN/Inf. */
+isg_status isg_motion_create(isg_plan* plan, const float* d, isg_motion** motion);
+isg_status isg_motion_destroy(isg_motion* motion);
+
+/* Prepare a trajectory k (device float32 [M][ndim], cycles/voxel) for the
+ * k-space pair (Eq. 1-3): grid coordinates G*k in FP64, split into an integer
+ * tap base and an FP32 fraction, and tile bins for the spread.  Points outside
+ * [-0.5, 0.5) wrap periodically.  M >= 1.  NOT_FINITE on NaN/Inf. */
+isg_status isg_traj_create(isg_plan* plan, const float* k, int64_t M, isg_traj** traj);
+isg_status isg_traj_destroy(isg_traj* traj);
+isg_status isg_traj_count(const isg_traj* traj, int64_t* M);
+
+/* y = T_d x, forward image-space gridding (Eq. 9).  x, y: device complex64
+ * images; out-of-place (x != y). */
+isg_status isg_warp(isg_plan* plan, const isg_motion* d, const void* x, void* y);
+
+/* x = T_d^H y, adjoint image-space gridding (Eq. 7-8); out-of-place. */
+isg_status isg_warp_adjoint(isg_plan* plan, const isg_motion* d, const void* y, void* x);
+
+/* grad[i][r] = Re(conj(v[r]) * d(T_d x)[r] / d d_i[r]): the gradient of
+ * Re<v, T_d x> with respect to the displacement field, which is what a
+ * registration or motion-refinement loss needs by the chain rule.
+ * x, v: device complex64 images; grad: device float32 [ndim][n...]. */
+isg_status isg_warp_grad_d(isg_plan* plan, const isg_motion* d, const void* x, const void* v,
+                           float* grad);
+
+/* y = [A_0; ...; A_{P-1}] x, the stacked nonrigid SENSE model (Eq. 10):
+ * for each state p, coil c and sample j, y_p[j][c] = (G_p (S_c . T_{d_p} x))_j.
+ * d, k: arrays of P handles; S: device complex64 [C][n...]; y: device,
+ * sum_p M_p * C complex64 values. */
+isg_status isg_sense_forward(isg_plan* plan, int nphases, const void* x,
+                             const isg_motion* const* d, const void* S,
+                             const isg_traj* const* k, void* y);
+
+/* x = sum_p A_p^H y_p = sum_p T_{d_p}^H sum_c conj(S_c) . G_p^H y_{p,c} (Fig. 3b). */
+isg_status isg_sense_adjoint(isg_plan* plan, int nphases, const void* y,
+                             const isg_motion* const* d, const void* S,
+                             const isg_traj* const* k, void* x);
+
+/* out = sum_p A_p^H A_p x + lambda x (l2 form of Eq. 11); out != x. */
+isg_status isg_normal(isg_plan* plan, int nphases, const void* x, double lambda,
+                      const isg_motion* const* d, const void* S,
+                      const isg_traj* const* k, void* out);
+
+/* Conjugate gradients on (sum_p A_p^H A_p + lambda I) x = sum_p A_p^H y_p:
+ * exactly `iters` Hestenes-Stiefel iterations from the x passed in (x is
+ * read as x0 and overwritten with x_iters), FP64 inner products and scalars
+ * kept on the device.  resnorm (host, may be NULL) receives iters + 1 values
+ * ||r_0|| .. ||r_iters||.  Synchronizes the stream.  CG_BREAKDOWN if
+ * Re<p, N p> <= 0 or is not finite (x then holds the last good iterate). */
+isg_status isg_cg_solve(isg_plan* plan, int nphases, const void* y,
+                        const isg_motion* const* d, const void* S,
+                        const isg_traj* const* k, double lambda, int iters,
+                        void* x, double* resnorm);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISG_H */

@@ -1,0 +1,111 @@
+// Shared device helpers: complex arithmetic on float2 and the Kaiser-Bessel
+// interpolation kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+namespace isg {
+
+constexpr int kWidth = 4;   // kernel width in oversampled-grid cells
+constexpr int kAlpha = 2;   // oversampling factor
+constexpr int kPolyDeg = 17;
+
+// ---------------------------------------------------------------------------
+// complex64 helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by s*i (s = +-1): (s i)(x + i y) = s(-y + i x)
+__device__ __forceinline__ float2 cmul_si(float2 a, float s) { return make_float2(-s * a.y, s * a.x); }
+
+// ---------------------------------------------------------------------------
+// Kaiser-Bessel kernel c(u) = I0(beta sqrt(1 - (2u/W)^2)), |u| < W/2.
+//
+// With t = 1 - (u/2)^2 (W = 4), I0(beta sqrt(t)) = sum_k a_k t^k with
+// a_k = (beta^2/4)^k / (k!)^2 (the power series of I0).  All a_k are
+// positive and t is in [0, 1], so Horner's rule is well conditioned.  The
+// host fills the coefficients in FP64 (degree 17: truncation < 1e-9
+// relative) and passes them by value.
+// ---------------------------------------------------------------------------
+struct KbPoly {
+  float a[kPolyDeg + 1];   // c as a polynomial in t
+  float da[kPolyDeg];      // dc/dt
+};
+
+__device__ __forceinline__ float kb_poly(const KbPoly& k, float t) {
+  float s = k.a[kPolyDeg];
+#pragma unroll
+  for (int i = kPolyDeg - 1; i >= 0; --i) s = fmaf(s, t, k.a[i]);
+  return s;
+}
+
+__device__ __forceinline__ float kb_dpoly(const KbPoly& k, float t) {
+  float s = k.da[kPolyDeg - 1];
+#pragma unroll
+  for (int i = kPolyDeg - 2; i >= 0; --i) s = fmaf(s, t, k.da[i]);
+  return s;
+}
+
+// Weights of the four taps g = floor(y) - 1 + m, m = 0..3, for a coordinate
+// with fractional part f = y - floor(y) in [0, 1).  The tap offset is
+// u_m = f + 1 - m and t_m = 1 - u_m^2/4 = (1 - f + m)(3 + f - m)/4, written
+// as a product so that no cancellation happens near the support edge.  The
+// last tap sits at u = -2 when f == 0, where the open-support kernel is 0.
+__device__ __forceinline__ void kb_weights(const KbPoly& k, float f, float w[4]) {
+  w[0] = kb_poly(k, (1.0f - f) * (3.0f + f) * 0.25f);
+  w[1] = kb_poly(k, (2.0f - f) * (2.0f + f) * 0.25f);
+  w[2] = kb_poly(k, (3.0f - f) * (1.0f + f) * 0.25f);
+  w[3] = (f > 0.0f) ? kb_poly(k, (4.0f - f) * f * 0.25f) : 0.0f;
+}
+
+// Weights and their derivatives with respect to the coordinate y:
+// dc/du = dc/dt * dt/du with dt/du = -u/2.
+__device__ __forceinline__ void kb_weights_deriv(const KbPoly& k, float f, float w[4], float dw[4]) {
+  float t0 = (1.0f - f) * (3.0f + f) * 0.25f;
+  float t1 = (2.0f - f) * (2.0f + f) * 0.25f;
+  float t2 = (3.0f - f) * (1.0f + f) * 0.25f;
+  float t3 = (4.0f - f) * f * 0.25f;
+  w[0] = kb_poly(k, t0);
+  w[1] = kb_poly(k, t1);
+  w[2] = kb_poly(k, t2);
+  w[3] = (f > 0.0f) ? kb_poly(k, t3) : 0.0f;
+  dw[0] = kb_dpoly(k, t0) * (-(f + 1.0f) * 0.5f);
+  dw[1] = kb_dpoly(k, t1) * (-f * 0.5f);
+  dw[2] = kb_dpoly(k, t2) * (-(f - 1.0f) * 0.5f);
+  dw[3] = (f > 0.0f) ? kb_dpoly(k, t3) * (-(f - 2.0f) * 0.5f) : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// grid element storage: complex64, or a pair of bf16 / fp16 halves
+// ---------------------------------------------------------------------------
+enum Storage { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
+
+template <int S> struct Elem;
+template <> struct Elem<kFP32> {
+  using T = float2;
+  __device__ static __forceinline__ float2 load(const T* p) { return *p; }
+  __device__ static __forceinline__ void store(T* p, float2 v) { *p = v; }
+};
+template <> struct Elem<kBF16> {
+  using T = __hip_bfloat162;
+  __device__ static __forceinline__ float2 load(const T* p) { return __bfloat1622float2(*p); }
+  __device__ static __forceinline__ void store(T* p, float2 v) { *p = __float22bfloat162_rn(v); }
+};
+template <> struct Elem<kFP16> {
+  using T = __half2;
+  __device__ static __forceinline__ float2 load(const T* p) { return __half22float2(*p); }
+  __device__ static __forceinline__ void store(T* p, float2 v) { *p = __float22half2_rn(v); }
+};
+
+}  // namespace isg

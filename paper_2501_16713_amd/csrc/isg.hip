@@ -1,0 +1,1338 @@
+// C ABI of the image-space gridding / nonrigid SENSE library (see isg.h):
+// plans, plan-time preparation of displacement fields and trajectories, and
+// the sequencing of the HIP kernels that make up each operator.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/isg.h"
+#include "common.h"
+#include "fft.h"
+#include "gridding.h"
+#include "passes.h"
+#include "solver.h"
+
+using namespace isg;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static isg_status fail(isg_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+struct HipError {
+  hipError_t e;
+  std::string where;
+};
+
+#define HIP_OK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess) throw HipError{_e, std::string(#expr) + " @" + std::to_string(__LINE__)}; \
+  } while (0)
+
+#define LAUNCH_OK() HIP_OK(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// host-side helpers
+// ---------------------------------------------------------------------------
+static FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.s = s;
+  f.m = (uint32_t)((((1ull << 32) * ((1ull << s) - d)) / d) + 1);
+  return f;
+}
+
+static bool factor_235(int L, std::vector<int>& R) {
+  R.clear();
+  int m = L;
+  while (m % 8 == 0 && m > 4) { R.push_back(8); m /= 8; }
+  while (m % 4 == 0) { R.push_back(4); m /= 4; }
+  while (m % 2 == 0) { R.push_back(2); m /= 2; }
+  while (m % 5 == 0) { R.push_back(5); m /= 5; }
+  while (m % 3 == 0) { R.push_back(3); m /= 3; }
+  return m == 1 && (int)R.size() <= kMaxStages;
+}
+
+// continuous Fourier transform of the Kaiser-Bessel kernel:
+// W sinh(z)/z with z = sqrt(beta^2 - (pi W f)^2) (sin branch past the root)
+static double kb_transform(double f, double beta) {
+  const double W = kWidth;
+  const double z2 = beta * beta - (M_PI * W * f) * (M_PI * W * f);
+  if (z2 > 0) {
+    const double z = std::sqrt(z2);
+    return W * std::sinh(z) / z;
+  }
+  if (z2 < 0) {
+    const double z = std::sqrt(-z2);
+    return W * std::sin(z) / z;
+  }
+  return W;
+}
+
+static double kb_beta() {
+  const double W = kWidth, a = kAlpha;
+  return M_PI * std::sqrt((W / a) * (W / a) * (a - 0.5) * (a - 0.5) - 0.8);
+}
+
+// I0(beta sqrt(t)) = sum_k (beta^2/4)^k t^k / (k!)^2
+static KbPoly make_kbpoly(double beta) {
+  KbPoly p;
+  const double q = beta * beta / 4.0;
+  double a = 1.0;
+  double coef[kPolyDeg + 1];
+  for (int k = 0; k <= kPolyDeg; ++k) {
+    if (k) a *= q / ((double)k * k);
+    coef[k] = a;
+    p.a[k] = (float)a;
+  }
+  for (int k = 1; k <= kPolyDeg; ++k) p.da[k - 1] = (float)(coef[k] * k);
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// plan objects
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct isg_plan {
+  int ndim = 0;
+  int n[3] = {1, 1, 1};
+  int G[3] = {1, 1, 1};
+  int64_t N = 0, NG = 0;
+  int C = 1, P = 1;
+  int storage = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool failed = false;
+  double beta = 0;
+  KbPoly kb;
+  Dims dims;
+  TileDims wtile;   // image-space spread tiles
+  KTile ktile;      // k-space spread tiles
+  // tables
+  float* dk[3] = {nullptr, nullptr, nullptr};  // 1/C(k/G), DFT bin order, times nothing
+  float* dx[3] = {nullptr, nullptr, nullptr};  // 1/C(x/G), centred positions
+  std::map<int, LinePlan> lines;
+  std::vector<void*> owned;
+  // scratch
+  float2* ugrid = nullptr;  // [NG]
+  float2* bufA = nullptr;   // [N]
+  float2* bufB = nullptr;   // [G0][n1][n2]
+  float2* bufC = nullptr;   // [G0][G1][n2]
+  float2* mbuf = nullptr;   // [N]
+  float2* wbuf = nullptr;   // [P][N]
+  void* kgrid = nullptr;    // [NG][C]
+  void* k1buf = nullptr;
+  void* k2buf = nullptr;
+  DevBuf ybuf;              // normal-operator data, grown on demand
+  DevBuf partial;           // spread partial tiles, grown on demand
+  // CG
+  float2 *cg_r = nullptr, *cg_p = nullptr, *cg_q = nullptr;
+  double* cg_part = nullptr;
+  CgScalars* cg_sc = nullptr;
+  DevBuf cg_hist;
+  int64_t bytes = 0;
+};
+
+struct isg_motion {
+  isg_plan* plan = nullptr;
+  float* d = nullptr;       // [ndim][N]
+  int* tile_off = nullptr;  // [ntiles + 1]
+  int* vox = nullptr;
+  int64_t nentries = 0;
+};
+
+struct isg_traj {
+  isg_plan* plan = nullptr;
+  int64_t M = 0;
+  KTap* taps = nullptr;
+  int* order = nullptr;
+  KUnit* units = nullptr;
+  int nunits = 0;
+  KSplit* splits = nullptr;
+  int nsplits = 0;
+  int nslots = 0;
+};
+
+static void* dmalloc(isg_plan* pl, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+  }
+  pl->bytes += (int64_t)bytes;
+  return p;
+}
+
+static void* plan_alloc(isg_plan* pl, size_t bytes) {
+  void* p = dmalloc(pl, bytes);
+  pl->owned.push_back(p);
+  return p;
+}
+
+static void grow(isg_plan* pl, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes) return;
+  if (b.p) {
+    HIP_OK(hipStreamSynchronize(pl->stream));
+    HIP_OK(hipFree(b.p));
+    pl->bytes -= (int64_t)b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  b.p = dmalloc(pl, bytes);
+  b.bytes = bytes;
+}
+
+static const LinePlan& line_plan(isg_plan* pl, int L) {
+  auto it = pl->lines.find(L);
+  if (it != pl->lines.end()) return it->second;
+  std::vector<int> R;
+  factor_235(L, R);
+  LinePlan lp;
+  memset(&lp, 0, sizeof(lp));
+  lp.L = L;
+  lp.nst = (int)R.size();
+  int Ns = 1;
+  for (int s = 0; s < lp.nst; ++s) {
+    lp.R[s] = R[s];
+    lp.step[s] = L / (Ns * R[s]);
+    lp.ns[s] = make_fastdiv((uint32_t)Ns);
+    Ns *= R[s];
+  }
+  std::vector<float2> tw(L);
+  for (int q = 0; q < L; ++q) {
+    const double th = 2.0 * M_PI * (double)q / (double)L;
+    tw[q] = make_float2((float)std::cos(th), (float)-std::sin(th));
+  }
+  float2* dtw = (float2*)plan_alloc(pl, sizeof(float2) * L);
+  HIP_OK(hipMemcpy(dtw, tw.data(), sizeof(float2) * L, hipMemcpyHostToDevice));
+  lp.tw = dtw;
+  return pl->lines.emplace(L, lp).first->second;
+}
+
+// ---------------------------------------------------------------------------
+// FFT pass launcher
+// ---------------------------------------------------------------------------
+static TileGeom make_geom(int64_t A, int64_t B, int Lmax, int nb_fixed) {
+  TileGeom g;
+  const int max_lines = std::max(1, std::min(64, std::min((kFftThreads * kMaxPerThread) / Lmax, 8192 / (Lmax + 1))));
+  if (nb_fixed > 0) {
+    g.nb = nb_fixed;
+    g.na = (int)std::max<int64_t>(1, std::min<int64_t>(A, max_lines / nb_fixed));
+  } else if (B == 1) {
+    g.nb = 1;
+    g.na = (int)std::min<int64_t>(A, std::min(16, max_lines));
+  } else {
+    g.nb = (int)std::min<int64_t>(B, std::min(16, max_lines));
+    g.na = 1;
+  }
+  g.A = A;
+  g.B = B;
+  g.tiles_b = (B + g.nb - 1) / g.nb;
+  g.LS = Lmax + 1;
+  return g;
+}
+
+template <class K>
+static void allow_lds(K kernel, size_t bytes) {
+  static std::map<const void*, size_t> done;  // largest size already allowed per kernel
+  if (bytes <= 65536) return;
+  size_t& have = done[(const void*)kernel];
+  if (have >= bytes) return;
+  HIP_OK(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  have = bytes;
+}
+
+template <class Ld, class Mid, class St>
+static void run_pass(isg_plan* pl, const Ld& ld, const Mid& mid, const St& st, const TileGeom& g,
+                     const LinePlan& l1, float s1, const LinePlan* l2, float s2) {
+  PassDesc pd;
+  memset(&pd, 0, sizeof(pd));
+  pd.g = g;
+  pd.l1 = l1;
+  pd.s1 = s1;
+  pd.two = l2 ? 1 : 0;
+  if (l2) pd.l2 = *l2;
+  pd.s2 = s2;
+  const int nl = g.na * g.nb;
+  {  // every butterfly and every mid-step element must fit the per-thread arrays
+    const int tpl = kFftThreads / nl;
+    auto fits = [&](const LinePlan& lp) {
+      for (int s = 0; s < lp.nst; ++s) {
+        const int R = lp.R[s];
+        const int per = (lp.L / R + tpl - 1) / tpl;
+        if (per > (kMaxPerThread + R - 1) / R) return false;
+      }
+      return (lp.L + tpl - 1) / tpl <= kMaxPerThread && lp.L < g.LS;
+    };
+    if (nl < 1 || nl > kFftThreads || !fits(l1) || (l2 && !fits(*l2)))
+      throw HipError{hipErrorInvalidConfiguration, "FFT pass tiling does not fit the per-thread arrays"};
+  }
+  const size_t lds = sizeof(float2) * ((size_t)l1.L + (l2 ? l2->L : 0) + (size_t)nl * g.LS);
+  const int64_t tiles = ((g.A + g.na - 1) / g.na) * g.tiles_b;
+  auto kern = fft_pass_kernel<Ld, Mid, St>;
+  allow_lds(kern, lds);
+  const int64_t gx = std::min<int64_t>(tiles, 1 << 30);
+  const int64_t gy = (tiles + gx - 1) / gx;
+  hipLaunchKernelGGL(kern, dim3((unsigned)gx, (unsigned)gy), dim3(kFftThreads), lds, pl->stream, ld, mid, st, pd);
+  LAUNCH_OK();
+}
+
+template <int S>
+static LdStrided<S> ld_strided(const void* p, int64_t sa, int64_t sj, int n, int L, int map, const TileGeom& g) {
+  LdStrided<S> l;
+  l.p = (const typename Elem<S>::T*)p;
+  l.sa = sa;
+  l.sj = sj;
+  l.n = n;
+  l.L = L;
+  l.map = map;
+  l.nbd = make_fastdiv(g.nb);
+  l.nd = make_fastdiv(n);
+  return l;
+}
+
+template <int S>
+static StStrided<S> st_strided(void* p, int64_t sa, int64_t sj, int n, int L, int map, const TileGeom& g) {
+  StStrided<S> s;
+  s.p = (typename Elem<S>::T*)p;
+  s.sa = sa;
+  s.sj = sj;
+  s.n = n;
+  s.L = L;
+  s.map = map;
+  s.nbd = make_fastdiv(g.nb);
+  s.nd = make_fastdiv(n);
+  return s;
+}
+
+static AxisTabs tabs(float* const t[3]) {
+  AxisTabs a;
+  for (int i = 0; i < 3; ++i) a.t[i] = t[i];
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// image-space gridding front end (Eq. 9 up to the gather):
+// u = F^H_G Z (1/C*) F_N x / |N|  on the oversampled grid
+// ---------------------------------------------------------------------------
+static void upsample(isg_plan* pl, const float2* x, float2* u) {
+  const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
+  const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
+  UpMid mid;
+  mid.tab = tabs(pl->dk);
+  mid.scale = (float)(1.0 / (double)pl->N);
+  mid.n = n0;
+  mid.G = G0;
+  if (pl->ndim == 3) {
+    mid.n_inner = n2;
+    mid.three_d = 1;
+    {  // F along axis 2
+      TileGeom g = make_geom((int64_t)n0 * n1, 1, n2, 0);
+      run_pass(pl, ld_strided<kFP32>(x, n2, 1, n2, n2, kDense, g), NoMid(),
+               st_strided<kFP32>(pl->bufA, n2, 1, n2, n2, kDense, g), g, line_plan(pl, n2), -1.f, nullptr, 0.f);
+    }
+    {  // F along axis 1, in place
+      TileGeom g = make_geom(n0, n2, n1, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
+               st_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), g, line_plan(pl, n1), -1.f,
+               nullptr, 0.f);
+    }
+    {  // F along axis 0, deapodize, pad, F^H of length G0
+      TileGeom g = make_geom(1, (int64_t)n1 * n2, G0, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufA, 0, (int64_t)n1 * n2, n0, n0, kDense, g), mid,
+               st_strided<kFP32>(pl->bufB, 0, (int64_t)n1 * n2, G0, G0, kDense, g), g, line_plan(pl, n0), -1.f,
+               &line_plan(pl, G0), +1.f);
+    }
+    {  // F^H along axis 1 with the spectral pad
+      TileGeom g = make_geom(G0, n2, G1, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufB, (int64_t)n1 * n2, n2, n1, G1, kSpectral, g), NoMid(),
+               st_strided<kFP32>(pl->bufC, (int64_t)G1 * n2, n2, G1, G1, kDense, g), g, line_plan(pl, G1), +1.f,
+               nullptr, 0.f);
+    }
+    {  // F^H along axis 2 with the spectral pad
+      TileGeom g = make_geom((int64_t)G0 * G1, 1, G2, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufC, n2, 1, n2, G2, kSpectral, g), NoMid(),
+               st_strided<kFP32>(u, G2, 1, G2, G2, kDense, g), g, line_plan(pl, G2), +1.f, nullptr, 0.f);
+    }
+  } else {
+    mid.n_inner = 1;
+    mid.three_d = 0;
+    {
+      TileGeom g = make_geom(n0, 1, n1, 0);
+      run_pass(pl, ld_strided<kFP32>(x, n1, 1, n1, n1, kDense, g), NoMid(),
+               st_strided<kFP32>(pl->bufA, n1, 1, n1, n1, kDense, g), g, line_plan(pl, n1), -1.f, nullptr, 0.f);
+    }
+    {
+      TileGeom g = make_geom(1, n1, G0, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufA, 0, n1, n0, n0, kDense, g), mid,
+               st_strided<kFP32>(pl->bufB, 0, n1, G0, G0, kDense, g), g, line_plan(pl, n0), -1.f, &line_plan(pl, G0),
+               +1.f);
+    }
+    {
+      TileGeom g = make_geom(G0, 1, G1, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufB, n1, 1, n1, G1, kSpectral, g), NoMid(),
+               st_strided<kFP32>(u, G1, 1, G1, G1, kDense, g), g, line_plan(pl, G1), +1.f, nullptr, 0.f);
+    }
+  }
+}
+
+// adjoint of upsample (Eq. 8 after the spread): x = F^H_N (1/C) Z^H F_G U / |N|
+static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
+  const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
+  const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
+  UpHMid mid;
+  mid.tab = tabs(pl->dk);
+  mid.scale = (float)(1.0 / (double)pl->N);
+  mid.n = n0;
+  mid.G = G0;
+  if (pl->ndim == 3) {
+    mid.n_inner = n2;
+    mid.three_d = 1;
+    {  // F along axis 2, crop
+      TileGeom g = make_geom((int64_t)G0 * G1, 1, G2, 0);
+      run_pass(pl, ld_strided<kFP32>(U, G2, 1, G2, G2, kDense, g), NoMid(),
+               st_strided<kFP32>(pl->bufC, n2, 1, n2, G2, kSpectral, g), g, line_plan(pl, G2), -1.f, nullptr, 0.f);
+    }
+    {  // F along axis 1, crop
+      TileGeom g = make_geom(G0, n2, G1, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufC, (int64_t)G1 * n2, n2, G1, G1, kDense, g), NoMid(),
+               st_strided<kFP32>(pl->bufB, (int64_t)n1 * n2, n2, n1, G1, kSpectral, g), g, line_plan(pl, G1), -1.f,
+               nullptr, 0.f);
+    }
+    {  // F along axis 0, crop, deapodize, F^H of length n0
+      TileGeom g = make_geom(1, (int64_t)n1 * n2, G0, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufB, 0, (int64_t)n1 * n2, G0, G0, kDense, g), mid,
+               st_strided<kFP32>(pl->bufA, 0, (int64_t)n1 * n2, n0, n0, kDense, g), g, line_plan(pl, G0), -1.f,
+               &line_plan(pl, n0), +1.f);
+    }
+    {  // F^H along axis 1, in place
+      TileGeom g = make_geom(n0, n2, n1, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
+               st_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), g, line_plan(pl, n1), +1.f,
+               nullptr, 0.f);
+    }
+    {  // F^H along axis 2
+      TileGeom g = make_geom((int64_t)n0 * n1, 1, n2, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufA, n2, 1, n2, n2, kDense, g), NoMid(),
+               st_strided<kFP32>(out, n2, 1, n2, n2, kDense, g), g, line_plan(pl, n2), +1.f, nullptr, 0.f);
+    }
+  } else {
+    mid.n_inner = 1;
+    mid.three_d = 0;
+    {
+      TileGeom g = make_geom(G0, 1, G1, 0);
+      run_pass(pl, ld_strided<kFP32>(U, G1, 1, G1, G1, kDense, g), NoMid(),
+               st_strided<kFP32>(pl->bufB, n1, 1, n1, G1, kSpectral, g), g, line_plan(pl, G1), -1.f, nullptr, 0.f);
+    }
+    {
+      TileGeom g = make_geom(1, n1, G0, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufB, 0, n1, G0, G0, kDense, g), mid,
+               st_strided<kFP32>(pl->bufA, 0, n1, n0, n0, kDense, g), g, line_plan(pl, G0), -1.f, &line_plan(pl, n0),
+               +1.f);
+    }
+    {
+      TileGeom g = make_geom(n0, 1, n1, 0);
+      run_pass(pl, ld_strided<kFP32>(pl->bufA, n1, 1, n1, n1, kDense, g), NoMid(),
+               st_strided<kFP32>(out, n1, 1, n1, n1, kDense, g), g, line_plan(pl, n1), +1.f, nullptr, 0.f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// image-space gather / spread
+// ---------------------------------------------------------------------------
+static unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+static void warp_gather(isg_plan* pl, const float2* u, const isg_motion* mo, float2* out) {
+  if (pl->ndim == 3)
+    hipLaunchKernelGGL(warp_gather_kernel<3>, dim3(blocks_for(pl->N, kGridThreads)), dim3(kGridThreads), 0,
+                       pl->stream, u, mo->d, out, pl->dims, pl->kb);
+  else
+    hipLaunchKernelGGL(warp_gather_kernel<2>, dim3(blocks_for(pl->N, kGridThreads)), dim3(kGridThreads), 0,
+                       pl->stream, u, mo->d, out, pl->dims, pl->kb);
+  LAUNCH_OK();
+}
+
+static int warp_ntiles(const isg_plan* pl) {
+  int t = 1;
+  for (int i = 0; i < pl->ndim; ++i) t *= pl->wtile.nt[i];
+  return t;
+}
+
+// U = sum_p P_{d_p} w_p over the given states
+static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const float2* const* w, float2* U) {
+  const size_t lds = sizeof(float2) * (size_t)pl->wtile.TS[0] * pl->wtile.TS[1] * pl->wtile.TS[2];
+  for (int p0 = 0; p0 < P; p0 += kMaxPhasesPerLaunch) {
+    WarpSpreadPhases ph;
+    memset(&ph, 0, sizeof(ph));
+    ph.P = std::min(kMaxPhasesPerLaunch, P - p0);
+    for (int i = 0; i < ph.P; ++i) {
+      ph.tile_off[i] = mo[p0 + i]->tile_off;
+      ph.vox[i] = mo[p0 + i]->vox;
+      ph.d[i] = mo[p0 + i]->d;
+      ph.w[i] = w[p0 + i];
+    }
+    const int acc = p0 > 0 ? 1 : 0;
+    if (pl->ndim == 3)
+      hipLaunchKernelGGL(warp_spread_kernel<3>, dim3(warp_ntiles(pl)), dim3(kGridThreads), lds, pl->stream, ph, U,
+                         acc, pl->dims, pl->wtile, pl->kb);
+    else
+      hipLaunchKernelGGL(warp_spread_kernel<2>, dim3(warp_ntiles(pl)), dim3(kGridThreads), lds, pl->stream, ph, U,
+                         acc, pl->dims, pl->wtile, pl->kb);
+    LAUNCH_OK();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// coil-expanded k-space front end and back end
+// ---------------------------------------------------------------------------
+template <int S>
+static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void* grid) {
+  const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
+  const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
+  const int C = pl->C;
+  const float scale = (float)(1.0 / std::sqrt((double)pl->N));
+  if (pl->ndim == 3) {
+    {  // S_c m / c(x/G) |N|^{-1/2}, centred pad, F along axis 2
+      TileGeom g = make_geom((int64_t)n0 * n1, C, G2, C);
+      LdCoilExpand ld;
+      ld.m = m;
+      ld.S = Sm;
+      ld.dx = tabs(pl->dx);
+      ld.scale = scale;
+      ld.N = pl->N;
+      ld.n = n2;
+      ld.L = G2;
+      ld.C = C;
+      ld.n1 = n1;
+      ld.nd = make_fastdiv(n2);
+      ld.cd = make_fastdiv(C);
+      run_pass(pl, ld, NoMid(), st_strided<S>(pl->k1buf, (int64_t)G2 * C, C, G2, G2, kDense, g), g,
+               line_plan(pl, G2), -1.f, nullptr, 0.f);
+    }
+    {  // centred pad, F along axis 1
+      TileGeom g = make_geom(n0, (int64_t)G2 * C, G1, 0);
+      run_pass(pl, ld_strided<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g), NoMid(),
+               st_strided<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g), g,
+               line_plan(pl, G1), -1.f, nullptr, 0.f);
+    }
+    {  // centred pad, F along axis 0
+      TileGeom g = make_geom(1, (int64_t)G1 * G2 * C, G0, 0);
+      run_pass(pl, ld_strided<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g), NoMid(),
+               st_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g), g, line_plan(pl, G0), -1.f, nullptr,
+               0.f);
+    }
+  } else {
+    {
+      TileGeom g = make_geom(n0, C, G1, C);
+      LdCoilExpand ld;
+      ld.m = m;
+      ld.S = Sm;
+      ld.dx = tabs(pl->dx);
+      ld.scale = scale;
+      ld.N = pl->N;
+      ld.n = n1;
+      ld.L = G1;
+      ld.C = C;
+      ld.n1 = 0;
+      ld.nd = make_fastdiv(n1);
+      ld.cd = make_fastdiv(C);
+      run_pass(pl, ld, NoMid(), st_strided<S>(pl->k1buf, (int64_t)G1 * C, C, G1, G1, kDense, g), g,
+               line_plan(pl, G1), -1.f, nullptr, 0.f);
+    }
+    {
+      TileGeom g = make_geom(1, (int64_t)G1 * C, G0, 0);
+      run_pass(pl, ld_strided<S>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g), NoMid(),
+               st_strided<S>(grid, 0, (int64_t)G1 * C, G0, G0, kDense, g), g, line_plan(pl, G0), -1.f, nullptr, 0.f);
+    }
+  }
+}
+
+template <int S>
+static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, float2* w) {
+  const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
+  const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
+  const int C = pl->C;
+  const float scale = (float)(1.0 / std::sqrt((double)pl->N));
+  if (pl->ndim == 3) {
+    {  // F^H along axis 0, centred crop
+      TileGeom g = make_geom(1, (int64_t)G1 * G2 * C, G0, 0);
+      run_pass(pl, ld_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g), NoMid(),
+               st_strided<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g), g, line_plan(pl, G0), +1.f,
+               nullptr, 0.f);
+    }
+    {  // F^H along axis 1, centred crop
+      TileGeom g = make_geom(n0, (int64_t)G2 * C, G1, 0);
+      run_pass(pl, ld_strided<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g), NoMid(),
+               st_strided<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g), g,
+               line_plan(pl, G1), +1.f, nullptr, 0.f);
+    }
+    {  // F^H along axis 2, centred crop, 1/c(x/G) |N|^{-1/2}, conj(S_c), coil sum
+      TileGeom g = make_geom((int64_t)n0 * n1, C, G2, C);
+      StCoilReduce st;
+      st.out = w;
+      st.S = Sm;
+      st.dx = tabs(pl->dx);
+      st.scale = scale;
+      st.N = pl->N;
+      st.n = n2;
+      st.L = G2;
+      st.C = C;
+      st.n1 = n1;
+      st.nd = make_fastdiv(n2);
+      run_pass(pl, ld_strided<S>(pl->k1buf, (int64_t)G2 * C, C, G2, G2, kDense, g), NoMid(), st, g,
+               line_plan(pl, G2), +1.f, nullptr, 0.f);
+    }
+  } else {
+    {
+      TileGeom g = make_geom(1, (int64_t)G1 * C, G0, 0);
+      run_pass(pl, ld_strided<S>(grid, 0, (int64_t)G1 * C, G0, G0, kDense, g), NoMid(),
+               st_strided<S>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g), g, line_plan(pl, G0), +1.f,
+               nullptr, 0.f);
+    }
+    {
+      TileGeom g = make_geom(n0, C, G1, C);
+      StCoilReduce st;
+      st.out = w;
+      st.S = Sm;
+      st.dx = tabs(pl->dx);
+      st.scale = scale;
+      st.N = pl->N;
+      st.n = n1;
+      st.L = G1;
+      st.C = C;
+      st.n1 = 0;
+      st.nd = make_fastdiv(n1);
+      run_pass(pl, ld_strided<S>(pl->k1buf, (int64_t)G1 * C, C, G1, G1, kDense, g), NoMid(), st, g,
+               line_plan(pl, G1), +1.f, nullptr, 0.f);
+    }
+  }
+}
+
+template <int S>
+static void kgather_t(isg_plan* pl, const void* grid, const isg_traj* tr, float2* y) {
+  auto grd = (const typename Elem<S>::T*)grid;
+  if (pl->ndim == 3)
+    hipLaunchKernelGGL((kgather_kernel<3, S>), dim3(blocks_for(tr->M, kGridThreads)), dim3(kGridThreads), 0,
+                       pl->stream, grd, tr->taps, tr->M, y, pl->C, pl->dims, pl->kb);
+  else
+    hipLaunchKernelGGL((kgather_kernel<2, S>), dim3(blocks_for(tr->M, kGridThreads)), dim3(kGridThreads), 0,
+                       pl->stream, grd, tr->taps, tr->M, y, pl->C, pl->dims, pl->kb);
+  LAUNCH_OK();
+}
+
+template <int S>
+static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* y, void* grid) {
+  auto grd = (typename Elem<S>::T*)grid;
+  const size_t lds = sizeof(float2) * (size_t)pl->ktile.vol * pl->C;
+  const size_t volC = (size_t)pl->ktile.vol * pl->C;
+  if (tr->nslots) grow(pl, pl->partial, sizeof(float2) * volC * tr->nslots);
+  float2* part = (float2*)pl->partial.p;
+  if (pl->ndim == 3) {
+    auto k = kspread_kernel<3, S>;
+    allow_lds(k, lds);
+    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kGridThreads), lds, pl->stream, tr->units, tr->order, tr->taps, y,
+                       pl->C, grd, part, pl->dims, pl->ktile, pl->kb);
+    LAUNCH_OK();
+    if (tr->nsplits) {
+      hipLaunchKernelGGL((kspread_reduce_kernel<3, S>), dim3(tr->nsplits), dim3(kGridThreads), 0, pl->stream,
+                         tr->splits, part, pl->C, grd, pl->dims, pl->ktile);
+      LAUNCH_OK();
+    }
+  } else {
+    auto k = kspread_kernel<2, S>;
+    allow_lds(k, lds);
+    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kGridThreads), lds, pl->stream, tr->units, tr->order, tr->taps, y,
+                       pl->C, grd, part, pl->dims, pl->ktile, pl->kb);
+    LAUNCH_OK();
+    if (tr->nsplits) {
+      hipLaunchKernelGGL((kspread_reduce_kernel<2, S>), dim3(tr->nsplits), dim3(kGridThreads), 0, pl->stream,
+                         tr->splits, part, pl->C, grd, pl->dims, pl->ktile);
+      LAUNCH_OK();
+    }
+  }
+}
+
+#define STORAGE_DISPATCH(pl, fn, ...)                                  \
+  do {                                                                 \
+    switch ((pl)->storage) {                                           \
+      case kBF16: fn<kBF16>(__VA_ARGS__); break;                       \
+      case kFP16: fn<kFP16>(__VA_ARGS__); break;                       \
+      default: fn<kFP32>(__VA_ARGS__); break;                          \
+    }                                                                  \
+  } while (0)
+
+static void ensure_kspace(isg_plan* pl) {
+  if (pl->kgrid) return;
+  const size_t es = pl->storage == kFP32 ? 8 : 4;
+  const int64_t C = pl->C;
+  pl->kgrid = plan_alloc(pl, es * (size_t)pl->NG * C);
+  if (pl->ndim == 3) {
+    pl->k1buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->n[1] * pl->G[2] * C);
+    pl->k2buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->G[1] * pl->G[2] * C);
+  } else {
+    pl->k1buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->G[1] * C);
+  }
+  pl->wbuf = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->N * pl->P);
+}
+
+// ---------------------------------------------------------------------------
+// operator sequences
+// ---------------------------------------------------------------------------
+static void op_sense_forward(isg_plan* pl, int P, const float2* x, const isg_motion* const* d, const float2* S,
+                             const isg_traj* const* k, float2* y) {
+  ensure_kspace(pl);
+  upsample(pl, x, pl->ugrid);
+  int64_t off = 0;
+  for (int p = 0; p < P; ++p) {
+    warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
+    STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, pl->kgrid);
+    STORAGE_DISPATCH(pl, kgather_t, pl, pl->kgrid, k[p], y + off);
+    off += k[p]->M * pl->C;
+  }
+}
+
+static void op_sense_adjoint(isg_plan* pl, int P, const float2* y, const isg_motion* const* d, const float2* S,
+                             const isg_traj* const* k, float2* x) {
+  ensure_kspace(pl);
+  std::vector<const float2*> w(P);
+  int64_t off = 0;
+  for (int p = 0; p < P; ++p) {
+    STORAGE_DISPATCH(pl, kspread_t, pl, k[p], y + off, pl->kgrid);
+    STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, S, pl->wbuf + (int64_t)p * pl->N);
+    w[p] = pl->wbuf + (int64_t)p * pl->N;
+    off += k[p]->M * pl->C;
+  }
+  warp_spread(pl, P, d, w.data(), pl->ugrid);
+  upsample_adjoint(pl, pl->ugrid, x);
+}
+
+static void op_normal(isg_plan* pl, int P, const float2* x, double lam, const isg_motion* const* d, const float2* S,
+                      const isg_traj* const* k, float2* out) {
+  ensure_kspace(pl);
+  int64_t Mmax = 0;
+  for (int p = 0; p < P; ++p) Mmax = std::max(Mmax, k[p]->M);
+  grow(pl, pl->ybuf, sizeof(float2) * (size_t)Mmax * pl->C);
+  float2* y = (float2*)pl->ybuf.p;
+  upsample(pl, x, pl->ugrid);
+  std::vector<const float2*> w(P);
+  for (int p = 0; p < P; ++p) {
+    warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
+    STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, pl->kgrid);
+    STORAGE_DISPATCH(pl, kgather_t, pl, pl->kgrid, k[p], y);
+    STORAGE_DISPATCH(pl, kspread_t, pl, k[p], y, pl->kgrid);
+    STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, S, pl->wbuf + (int64_t)p * pl->N);
+    w[p] = pl->wbuf + (int64_t)p * pl->N;
+  }
+  warp_spread(pl, P, d, w.data(), pl->ugrid);
+  upsample_adjoint(pl, pl->ugrid, out);
+  if (lam != 0.0) {
+    hipLaunchKernelGGL(axpy_kernel, dim3(std::min<int64_t>(blocks_for(pl->N, kVecThreads), 4096)), dim3(kVecThreads),
+                       0, pl->stream, out, x, (float)lam, pl->N);
+    LAUNCH_OK();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plan-time preparation
+// ---------------------------------------------------------------------------
+static int iwrap(int64_t g, int G) {
+  int64_t r = g % G;
+  return (int)(r < 0 ? r + G : r);
+}
+
+// tiles (along one axis) touched by taps b..b+3 (mod G) with tile size TS
+static int axis_tiles(int b, int G, int TS, int out[2]) {
+  const int t0 = b / TS;
+  const int e = b + kWidth - 1;
+  const int t1 = (e >= G ? e - G : e) / TS;
+  out[0] = t0;
+  if (t1 != t0) {
+    out[1] = t1;
+    return 2;
+  }
+  return 1;
+}
+
+static isg_status prepare_motion(isg_plan* pl, const float* d_dev, isg_motion* mo) {
+  const int nd = pl->ndim;
+  const int64_t N = pl->N;
+  std::vector<float> d((size_t)nd * N);
+  HIP_OK(hipMemcpy(d.data(), d_dev, sizeof(float) * d.size(), hipMemcpyDeviceToHost));
+  for (float v : d) {
+    if (!std::isfinite(v)) return fail(ISG_ERR_NOT_FINITE, "displacement field holds NaN or Inf");
+    if (std::fabs(v) > 1.0e6f) return fail(ISG_ERR_INVALID_ARG, "displacement magnitude exceeds 1e6 voxels");
+  }
+  const int ntiles = warp_ntiles(pl);
+  std::vector<int> cnt(ntiles + 1, 0);
+  std::vector<int> tl[3];
+  for (int i = 0; i < 3; ++i) tl[i].resize(2);
+  auto visit = [&](int64_t r, auto&& fn) {
+    int ri[3] = {0, 0, 0};
+    int64_t t = r;
+    for (int i = nd - 1; i >= 0; --i) {
+      ri[i] = (int)(t % pl->n[i]);
+      t /= pl->n[i];
+    }
+    int ts[3][2], nts[3] = {1, 1, 1};
+    for (int i = 0; i < nd; ++i) {
+      const float y = 2.0f * d[(size_t)i * N + r];
+      const int b = iwrap(2 * (int64_t)ri[i] + (int64_t)std::floor(y) - 1, pl->G[i]);
+      nts[i] = axis_tiles(b, pl->G[i], pl->wtile.TS[i], ts[i]);
+    }
+    if (nd == 3) {
+      for (int a = 0; a < nts[0]; ++a)
+        for (int b = 0; b < nts[1]; ++b)
+          for (int c = 0; c < nts[2]; ++c)
+            fn((ts[0][a] * pl->wtile.nt[1] + ts[1][b]) * pl->wtile.nt[2] + ts[2][c]);
+    } else {
+      for (int a = 0; a < nts[0]; ++a)
+        for (int b = 0; b < nts[1]; ++b) fn(ts[0][a] * pl->wtile.nt[1] + ts[1][b]);
+    }
+  };
+  for (int64_t r = 0; r < N; ++r) visit(r, [&](int t) { cnt[t + 1]++; });
+  for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
+  std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+  std::vector<int> vox(cnt[ntiles]);
+  for (int64_t r = 0; r < N; ++r) visit(r, [&](int t) { vox[pos[t]++] = (int)r; });
+  mo->d = (float*)dmalloc(pl, sizeof(float) * d.size());
+  mo->tile_off = (int*)dmalloc(pl, sizeof(int) * cnt.size());
+  mo->vox = (int*)dmalloc(pl, sizeof(int) * std::max<size_t>(1, vox.size()));
+  mo->nentries = (int64_t)vox.size();
+  HIP_OK(hipMemcpy(mo->d, d.data(), sizeof(float) * d.size(), hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(mo->tile_off, cnt.data(), sizeof(int) * cnt.size(), hipMemcpyHostToDevice));
+  if (!vox.empty()) HIP_OK(hipMemcpy(mo->vox, vox.data(), sizeof(int) * vox.size(), hipMemcpyHostToDevice));
+  return ISG_OK;
+}
+
+static int kspread_chunk() {
+  const char* e = getenv("ISG_SPREAD_CHUNK");
+  const int v = e ? atoi(e) : 0;
+  return v > 0 ? v : 512;
+}
+
+static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_traj* tr) {
+  const int nd = pl->ndim;
+  std::vector<float> k((size_t)M * nd);
+  HIP_OK(hipMemcpy(k.data(), k_dev, sizeof(float) * k.size(), hipMemcpyDeviceToHost));
+  for (float v : k) {
+    if (!std::isfinite(v)) return fail(ISG_ERR_NOT_FINITE, "trajectory holds NaN or Inf");
+    if (std::fabs(v) > 1.0e6f) return fail(ISG_ERR_INVALID_ARG, "trajectory magnitude exceeds 1e6 cycles/voxel");
+  }
+  std::vector<KTap> taps(M);
+  for (int64_t j = 0; j < M; ++j) {
+    KTap t;
+    t.f[0] = t.f[1] = t.f[2] = 0.f;
+    uint32_t packed = 0;
+    for (int i = 0; i < nd; ++i) {
+      const double kap = (double)pl->G[i] * (double)k[(size_t)j * nd + i];  // exact in FP64
+      double fl = std::floor(kap);
+      float f = (float)(kap - fl);
+      if (f >= 1.0f) {  // fraction rounded up to 1 in FP32: move to the next cell
+        f = 0.0f;
+        fl += 1.0;
+      }
+      t.f[i] = f;
+      packed |= (uint32_t)iwrap((int64_t)fl - 1, pl->G[i]) << (10 * i);
+    }
+    t.base = packed;
+    taps[j] = t;
+  }
+  // bin samples by the spread tiles their taps touch
+  int ntiles = 1;
+  for (int i = 0; i < nd; ++i) ntiles *= pl->ktile.nt[i];
+  std::vector<int> cnt(ntiles + 1, 0);
+  auto visit = [&](int64_t j, auto&& fn) {
+    int ts[3][2], nts[3] = {1, 1, 1};
+    for (int i = 0; i < nd; ++i) {
+      const int b = (int)((taps[j].base >> (10 * i)) & 1023);
+      nts[i] = axis_tiles(b, pl->G[i], pl->ktile.TS[i], ts[i]);
+    }
+    if (nd == 3) {
+      for (int a = 0; a < nts[0]; ++a)
+        for (int b = 0; b < nts[1]; ++b)
+          for (int c = 0; c < nts[2]; ++c)
+            fn((ts[0][a] * pl->ktile.nt[1] + ts[1][b]) * pl->ktile.nt[2] + ts[2][c]);
+    } else {
+      for (int a = 0; a < nts[0]; ++a)
+        for (int b = 0; b < nts[1]; ++b) fn(ts[0][a] * pl->ktile.nt[1] + ts[1][b]);
+    }
+  };
+  for (int64_t j = 0; j < M; ++j) visit(j, [&](int t) { cnt[t + 1]++; });
+  for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
+  std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+  std::vector<int> order(std::max(1, cnt[ntiles]));
+  for (int64_t j = 0; j < M; ++j) visit(j, [&](int t) { order[pos[t]++] = (int)j; });
+  const int chunk = kspread_chunk();
+  std::vector<KUnit> units;
+  std::vector<KSplit> splits;
+  int slots = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    const int beg = cnt[t], c = cnt[t + 1] - cnt[t];
+    if (c <= chunk) {
+      units.push_back(KUnit{t, beg, c, -1});
+    } else {
+      const int nch = (c + chunk - 1) / chunk;
+      splits.push_back(KSplit{t, slots, nch});
+      for (int q = 0; q < nch; ++q) units.push_back(KUnit{t, beg + q * chunk, std::min(chunk, c - q * chunk), slots + q});
+      slots += nch;
+    }
+  }
+  // split units first: they are the longest
+  std::stable_sort(units.begin(), units.end(), [](const KUnit& a, const KUnit& b) { return a.count > b.count; });
+  tr->M = M;
+  tr->taps = (KTap*)dmalloc(pl, sizeof(KTap) * taps.size());
+  tr->order = (int*)dmalloc(pl, sizeof(int) * order.size());
+  tr->units = (KUnit*)dmalloc(pl, sizeof(KUnit) * units.size());
+  tr->nunits = (int)units.size();
+  tr->splits = (KSplit*)dmalloc(pl, sizeof(KSplit) * std::max<size_t>(1, splits.size()));
+  tr->nsplits = (int)splits.size();
+  tr->nslots = slots;
+  HIP_OK(hipMemcpy(tr->taps, taps.data(), sizeof(KTap) * taps.size(), hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(tr->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(tr->units, units.data(), sizeof(KUnit) * units.size(), hipMemcpyHostToDevice));
+  if (!splits.empty())
+    HIP_OK(hipMemcpy(tr->splits, splits.data(), sizeof(KSplit) * splits.size(), hipMemcpyHostToDevice));
+  return ISG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+static bool good_length(int64_t n) {
+  if (n < 8 || n > 512 || (n & 1)) return false;
+  std::vector<int> R;
+  return factor_235((int)n, R) && factor_235((int)(2 * n), R);
+}
+
+static isg_status check_plan(const isg_plan* pl) {
+  if (!pl) return fail(ISG_ERR_INVALID_ARG, "plan is NULL");
+  if (pl->failed) return fail(ISG_ERR_STATE, "plan hit a device error earlier; destroy it");
+  return ISG_OK;
+}
+
+static isg_status check_phases(const isg_plan* pl, int P, const isg_motion* const* d, const isg_traj* const* k) {
+  if (P < 1 || P > pl->P) return fail(ISG_ERR_INVALID_ARG, "nphases must be in 1..plan nphases");
+  if (!d || !k) return fail(ISG_ERR_INVALID_ARG, "motion / trajectory arrays must not be NULL");
+  for (int p = 0; p < P; ++p) {
+    if (!d[p] || !k[p]) return fail(ISG_ERR_INVALID_ARG, "NULL motion or trajectory handle");
+    if (d[p]->plan != pl || k[p]->plan != pl) return fail(ISG_ERR_INVALID_ARG, "handle belongs to another plan");
+  }
+  return ISG_OK;
+}
+
+static isg_status device_error(isg_plan* pl, const HipError& e) {
+  if (pl) pl->failed = true;
+  return fail(ISG_ERR_DEVICE, std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
+}
+
+template <class F>
+static isg_status guarded(isg_plan* pl, F&& f) {
+  try {
+    return f();
+  } catch (const HipError& e) {
+    return device_error(pl, e);
+  } catch (const std::bad_alloc&) {
+    return fail(ISG_ERR_OUT_OF_MEMORY, "device or host allocation failed");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* isg_version(void) { return "isg 0.1 gfx950"; }
+
+const char* isg_last_error(void) { return g_last_error.c_str(); }
+
+isg_status isg_device_count(int* count) {
+  if (!count) return fail(ISG_ERR_INVALID_ARG, "count is NULL");
+  int c = 0;
+  if (hipGetDeviceCount(&c) != hipSuccess) {
+    (void)hipGetLastError();
+    c = 0;
+  }
+  *count = c;
+  return ISG_OK;
+}
+
+isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
+  if (!desc || !out) return fail(ISG_ERR_INVALID_ARG, "desc and plan must not be NULL");
+  *out = nullptr;
+  if (desc->ndim != 2 && desc->ndim != 3) return fail(ISG_ERR_INVALID_ARG, "ndim must be 2 or 3");
+  if (desc->ncoils < 1 || desc->ncoils > 32) return fail(ISG_ERR_INVALID_ARG, "ncoils must be in 1..32");
+  if (desc->nphases < 1 || desc->nphases > 1024) return fail(ISG_ERR_INVALID_ARG, "nphases must be in 1..1024");
+  if (desc->storage < ISG_STORE_FP32 || desc->storage > ISG_STORE_FP16)
+    return fail(ISG_ERR_INVALID_ARG, "unknown storage type");
+  for (int i = 0; i < desc->ndim; ++i)
+    if (!good_length(desc->n[i]))
+      return fail(ISG_ERR_UNSUPPORTED_SHAPE,
+                  "each n_i must be even, in 8..512, with prime factors 2, 3, 5 only (got " +
+                      std::to_string((long long)desc->n[i]) + ")");
+  {  // the coil passes hold all C coils of a line: C * 2 n_last <= 8192
+    const int64_t Gl = 2 * desc->n[desc->ndim - 1];
+    if ((int64_t)desc->ncoils * Gl > kFftThreads * kMaxPerThread)
+      return fail(ISG_ERR_UNSUPPORTED_SHAPE, "ncoils * 2 * n_last must not exceed 8192");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(ISG_ERR_DEVICE, "no HIP device available");
+  }
+  isg_plan* pl = new (std::nothrow) isg_plan();
+  if (!pl) return fail(ISG_ERR_OUT_OF_MEMORY, "host allocation failed");
+  pl->ndim = desc->ndim;
+  pl->N = 1;
+  pl->NG = 1;
+  for (int i = 0; i < pl->ndim; ++i) {
+    pl->n[i] = (int)desc->n[i];
+    pl->G[i] = kAlpha * pl->n[i];
+    pl->N *= pl->n[i];
+    pl->NG *= pl->G[i];
+  }
+  pl->C = desc->ncoils;
+  pl->P = desc->nphases;
+  pl->storage = desc->storage;
+  pl->stream = (hipStream_t)desc->stream;
+  pl->beta = kb_beta();
+  pl->kb = make_kbpoly(pl->beta);
+  pl->dims.ndim = pl->ndim;
+  for (int i = 0; i < 3; ++i) {
+    pl->dims.n[i] = pl->n[i];
+    pl->dims.G[i] = pl->G[i];
+  }
+  pl->dims.N = pl->N;
+  // spread tiles
+  for (int i = 0; i < 3; ++i) {
+    pl->wtile.TS[i] = 1;
+    pl->wtile.nt[i] = 1;
+    pl->ktile.TS[i] = 1;
+    pl->ktile.nt[i] = 1;
+  }
+  const int wts = pl->ndim == 3 ? 16 : 64;
+  for (int i = 0; i < pl->ndim; ++i) {
+    pl->wtile.TS[i] = std::min(wts, pl->G[i]);
+    pl->wtile.nt[i] = (pl->G[i] + pl->wtile.TS[i] - 1) / pl->wtile.TS[i];
+  }
+  if (pl->ndim == 3) {
+    const int t0 = pl->C > 16 ? 4 : 8;
+    const int ts[3] = {t0, 8, 8};
+    for (int i = 0; i < 3; ++i) pl->ktile.TS[i] = std::min(ts[i], pl->G[i]);
+  } else {
+    for (int i = 0; i < 2; ++i) pl->ktile.TS[i] = std::min(16, pl->G[i]);
+  }
+  pl->ktile.vol = 1;
+  for (int i = 0; i < pl->ndim; ++i) {
+    pl->ktile.nt[i] = (pl->G[i] + pl->ktile.TS[i] - 1) / pl->ktile.TS[i];
+    pl->ktile.vol *= pl->ktile.TS[i];
+  }
+  isg_status st = guarded(pl, [&]() -> isg_status {
+    HIP_OK(hipGetDevice(&pl->device));
+    // deapodization tables
+    for (int i = 0; i < pl->ndim; ++i) {
+      const int n = pl->n[i], G = pl->G[i];
+      std::vector<float> k(n), x(n);
+      for (int j = 0; j < n; ++j) {
+        const int kk = j < n - n / 2 ? j : j - n;  // signed DFT bin
+        k[j] = (float)(1.0 / kb_transform((double)kk / G, pl->beta));
+        x[j] = (float)(1.0 / kb_transform((double)(j - n / 2) / G, pl->beta));
+      }
+      pl->dk[i] = (float*)plan_alloc(pl, sizeof(float) * n);
+      pl->dx[i] = (float*)plan_alloc(pl, sizeof(float) * n);
+      HIP_OK(hipMemcpy(pl->dk[i], k.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(pl->dx[i], x.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    }
+    for (int i = 0; i < pl->ndim; ++i) {
+      line_plan(pl, pl->n[i]);
+      line_plan(pl, pl->G[i]);
+    }
+    const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
+    pl->ugrid = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->NG);
+    pl->bufA = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->N);
+    pl->mbuf = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->N);
+    pl->bufB = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->G[0] * n1 * n2);
+    if (pl->ndim == 3) pl->bufC = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->G[0] * pl->G[1] * n2);
+    (void)n0;
+    return ISG_OK;
+  });
+  if (st != ISG_OK) {
+    isg_plan_destroy(pl);
+    return st;
+  }
+  *out = pl;
+  return ISG_OK;
+}
+
+isg_status isg_plan_destroy(isg_plan* pl) {
+  if (!pl) return ISG_OK;
+  if (pl->stream || true) (void)hipStreamSynchronize(pl->stream);
+  for (void* p : pl->owned) (void)hipFree(p);
+  if (pl->ybuf.p) (void)hipFree(pl->ybuf.p);
+  if (pl->partial.p) (void)hipFree(pl->partial.p);
+  if (pl->cg_hist.p) (void)hipFree(pl->cg_hist.p);
+  (void)hipGetLastError();
+  delete pl;
+  return ISG_OK;
+}
+
+isg_status isg_plan_set_stream(isg_plan* pl, void* stream) {
+  if (!pl) return fail(ISG_ERR_INVALID_ARG, "plan is NULL");
+  pl->stream = (hipStream_t)stream;
+  return ISG_OK;
+}
+
+isg_status isg_plan_device_bytes(const isg_plan* pl, int64_t* bytes) {
+  if (!pl || !bytes) return fail(ISG_ERR_INVALID_ARG, "plan and bytes must not be NULL");
+  *bytes = pl->bytes;
+  return ISG_OK;
+}
+
+isg_status isg_motion_create(isg_plan* pl, const float* d, isg_motion** out) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!d || !out) return fail(ISG_ERR_INVALID_ARG, "d and motion must not be NULL");
+  *out = nullptr;
+  isg_motion* mo = new (std::nothrow) isg_motion();
+  if (!mo) return fail(ISG_ERR_OUT_OF_MEMORY, "host allocation failed");
+  mo->plan = pl;
+  st = guarded(pl, [&]() { return prepare_motion(pl, d, mo); });
+  if (st != ISG_OK) {
+    isg_motion_destroy(mo);
+    return st;
+  }
+  *out = mo;
+  return ISG_OK;
+}
+
+isg_status isg_motion_destroy(isg_motion* mo) {
+  if (!mo) return ISG_OK;
+  if (mo->plan) (void)hipStreamSynchronize(mo->plan->stream);
+  for (void* p : {(void*)mo->d, (void*)mo->tile_off, (void*)mo->vox})
+    if (p) (void)hipFree(p);
+  delete mo;
+  return ISG_OK;
+}
+
+isg_status isg_traj_create(isg_plan* pl, const float* k, int64_t M, isg_traj** out) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!k || !out) return fail(ISG_ERR_INVALID_ARG, "k and traj must not be NULL");
+  if (M < 1 || M > (int64_t)1 << 30) return fail(ISG_ERR_INVALID_ARG, "M must be in 1..2^30");
+  *out = nullptr;
+  isg_traj* tr = new (std::nothrow) isg_traj();
+  if (!tr) return fail(ISG_ERR_OUT_OF_MEMORY, "host allocation failed");
+  tr->plan = pl;
+  st = guarded(pl, [&]() { return prepare_traj(pl, k, M, tr); });
+  if (st != ISG_OK) {
+    isg_traj_destroy(tr);
+    return st;
+  }
+  *out = tr;
+  return ISG_OK;
+}
+
+isg_status isg_traj_destroy(isg_traj* tr) {
+  if (!tr) return ISG_OK;
+  if (tr->plan) (void)hipStreamSynchronize(tr->plan->stream);
+  for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->units, (void*)tr->splits})
+    if (p) (void)hipFree(p);
+  delete tr;
+  return ISG_OK;
+}
+
+isg_status isg_traj_count(const isg_traj* tr, int64_t* M) {
+  if (!tr || !M) return fail(ISG_ERR_INVALID_ARG, "traj and M must not be NULL");
+  *M = tr->M;
+  return ISG_OK;
+}
+
+isg_status isg_warp(isg_plan* pl, const isg_motion* d, const void* x, void* y) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!d || !x || !y) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (d->plan != pl) return fail(ISG_ERR_INVALID_ARG, "motion belongs to another plan");
+  if (x == y) return fail(ISG_ERR_INVALID_ARG, "warp is out-of-place: x must differ from y");
+  return guarded(pl, [&]() {
+    upsample(pl, (const float2*)x, pl->ugrid);
+    warp_gather(pl, pl->ugrid, d, (float2*)y);
+    return ISG_OK;
+  });
+}
+
+isg_status isg_warp_adjoint(isg_plan* pl, const isg_motion* d, const void* y, void* x) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!d || !x || !y) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (d->plan != pl) return fail(ISG_ERR_INVALID_ARG, "motion belongs to another plan");
+  if (x == y) return fail(ISG_ERR_INVALID_ARG, "warp_adjoint is out-of-place: x must differ from y");
+  return guarded(pl, [&]() {
+    const float2* w = (const float2*)y;
+    warp_spread(pl, 1, &d, &w, pl->ugrid);
+    upsample_adjoint(pl, pl->ugrid, (float2*)x);
+    return ISG_OK;
+  });
+}
+
+isg_status isg_warp_grad_d(isg_plan* pl, const isg_motion* d, const void* x, const void* v, float* grad) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!d || !x || !v || !grad) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (d->plan != pl) return fail(ISG_ERR_INVALID_ARG, "motion belongs to another plan");
+  return guarded(pl, [&]() {
+    upsample(pl, (const float2*)x, pl->ugrid);
+    if (pl->ndim == 3)
+      hipLaunchKernelGGL(warp_grad_kernel<3>, dim3(blocks_for(pl->N, kGridThreads)), dim3(kGridThreads), 0,
+                         pl->stream, pl->ugrid, d->d, (const float2*)v, grad, pl->dims, pl->kb);
+    else
+      hipLaunchKernelGGL(warp_grad_kernel<2>, dim3(blocks_for(pl->N, kGridThreads)), dim3(kGridThreads), 0,
+                         pl->stream, pl->ugrid, d->d, (const float2*)v, grad, pl->dims, pl->kb);
+    LAUNCH_OK();
+    return ISG_OK;
+  });
+}
+
+isg_status isg_sense_forward(isg_plan* pl, int P, const void* x, const isg_motion* const* d, const void* S,
+                             const isg_traj* const* k, void* y) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!x || !S || !y) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  st = check_phases(pl, P, d, k);
+  if (st) return st;
+  return guarded(pl, [&]() {
+    op_sense_forward(pl, P, (const float2*)x, d, (const float2*)S, k, (float2*)y);
+    return ISG_OK;
+  });
+}
+
+isg_status isg_sense_adjoint(isg_plan* pl, int P, const void* y, const isg_motion* const* d, const void* S,
+                             const isg_traj* const* k, void* x) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!x || !S || !y) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  st = check_phases(pl, P, d, k);
+  if (st) return st;
+  return guarded(pl, [&]() {
+    op_sense_adjoint(pl, P, (const float2*)y, d, (const float2*)S, k, (float2*)x);
+    return ISG_OK;
+  });
+}
+
+isg_status isg_normal(isg_plan* pl, int P, const void* x, double lambda, const isg_motion* const* d, const void* S,
+                      const isg_traj* const* k, void* out) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!x || !S || !out) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (x == out) return fail(ISG_ERR_INVALID_ARG, "normal is out-of-place: x must differ from out");
+  if (!std::isfinite(lambda)) return fail(ISG_ERR_INVALID_ARG, "lambda must be finite");
+  st = check_phases(pl, P, d, k);
+  if (st) return st;
+  return guarded(pl, [&]() {
+    op_normal(pl, P, (const float2*)x, lambda, d, (const float2*)S, k, (float2*)out);
+    return ISG_OK;
+  });
+}
+
+isg_status isg_cg_solve(isg_plan* pl, int P, const void* y, const isg_motion* const* d, const void* S,
+                        const isg_traj* const* k, double lambda, int iters, void* x, double* resnorm) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!x || !S || !y) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (iters < 0 || iters > 100000) return fail(ISG_ERR_INVALID_ARG, "iters must be in 0..100000");
+  if (!std::isfinite(lambda)) return fail(ISG_ERR_INVALID_ARG, "lambda must be finite");
+  st = check_phases(pl, P, d, k);
+  if (st) return st;
+  return guarded(pl, [&]() -> isg_status {
+    const int64_t N = pl->N;
+    if (!pl->cg_r) {
+      pl->cg_r = (float2*)plan_alloc(pl, sizeof(float2) * N);
+      pl->cg_p = (float2*)plan_alloc(pl, sizeof(float2) * N);
+      pl->cg_q = (float2*)plan_alloc(pl, sizeof(float2) * N);
+      pl->cg_part = (double*)plan_alloc(pl, sizeof(double) * kDotBlocks);
+      pl->cg_sc = (CgScalars*)plan_alloc(pl, sizeof(CgScalars));
+    }
+    grow(pl, pl->cg_hist, sizeof(double) * (iters + 1));
+    double* hist = (double*)pl->cg_hist.p;
+    float2* xv = (float2*)x;
+    const unsigned vb = (unsigned)std::min<int64_t>(kDotBlocks, blocks_for(N, kVecThreads));
+    // r = b - N x0 with b = sum_p A_p^H y_p; p = r; rho = <r, r>
+    op_sense_adjoint(pl, P, (const float2*)y, d, (const float2*)S, k, pl->cg_p);
+    op_normal(pl, P, xv, lambda, d, (const float2*)S, k, pl->cg_q);
+    hipLaunchKernelGGL(sub_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_p, pl->cg_q, N);
+    hipLaunchKernelGGL(copy_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_r, N);
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_r, N,
+                       pl->cg_part);
+    hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb, pl->cg_sc,
+                       hist);
+    LAUNCH_OK();
+    auto iteration = [&]() {
+      op_normal(pl, P, pl->cg_p, lambda, d, (const float2*)S, k, pl->cg_q);
+      hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_q, N,
+                         pl->cg_part);
+      hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb,
+                         pl->cg_sc);
+      hipLaunchKernelGGL(cg_update_xr_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, xv, pl->cg_r, pl->cg_p,
+                         pl->cg_q, N, pl->cg_sc, pl->cg_part);
+      hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb, pl->cg_sc,
+                         hist);
+      hipLaunchKernelGGL(cg_update_p_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_r, N,
+                         pl->cg_sc);
+      LAUNCH_OK();
+    };
+    const char* ng = getenv("ISG_NO_GRAPH");
+    const bool use_graph = iters > 1 && pl->stream != nullptr && !(ng && atoi(ng));
+    if (use_graph) {
+      // make sure every lazily grown buffer exists before capture
+      iteration();
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      HIP_OK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
+      try {
+        iteration();
+      } catch (...) {
+        hipGraph_t g2 = nullptr;
+        (void)hipStreamEndCapture(pl->stream, &g2);
+        if (g2) (void)hipGraphDestroy(g2);
+        throw;
+      }
+      HIP_OK(hipStreamEndCapture(pl->stream, &graph));
+      HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      for (int it = 1; it < iters; ++it) HIP_OK(hipGraphLaunch(exec, pl->stream));
+      HIP_OK(hipStreamSynchronize(pl->stream));
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+    } else {
+      for (int it = 0; it < iters; ++it) iteration();
+    }
+    CgScalars sc;
+    HIP_OK(hipMemcpyAsync(&sc, pl->cg_sc, sizeof(sc), hipMemcpyDeviceToHost, pl->stream));
+    HIP_OK(hipStreamSynchronize(pl->stream));
+    if (resnorm) HIP_OK(hipMemcpy(resnorm, hist, sizeof(double) * (iters + 1), hipMemcpyDeviceToHost));
+    if (sc.breakdown) return fail(ISG_ERR_CG_BREAKDOWN, "CG breakdown: Re<p, N p> <= 0 or not finite");
+    return ISG_OK;
+  });
+}
+
+}  // extern "C"

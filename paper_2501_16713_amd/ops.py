@@ -1,0 +1,251 @@
+"""Python binding of the HIP library: plans, prepared motions and
+trajectories, and the operators.  Torch tensors supply device memory and
+the stream; every arithmetic step runs in libisg.so.
+
+Layouts follow include/isg.h: images complex64 [n0][n1](/[n2]); fields
+float32 [ndim][*shape]; coils complex64 [C][*shape]; trajectories float32
+[M][ndim]; data complex64 with the states packed one after another, state
+p holding [M_p][C].
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import check, isg_plan_desc
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+def _require(t: torch.Tensor, dtype, shape, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.contiguous()
+
+
+def device_count() -> int:
+    c = C.c_int(0)
+    check(_lib.load().isg_device_count(C.byref(c)))
+    return c.value
+
+
+def version() -> str:
+    return _lib.load().isg_version().decode()
+
+
+class Motion:
+    """A displacement field prepared for T_d / T_d^H (Eq. 5)."""
+
+    def __init__(self, plan: "Plan", d: torch.Tensor):
+        self.plan = plan
+        d = _require(d, torch.float32, (plan.ndim,) + plan.shape, "d")
+        h = C.c_void_p()
+        check(plan.lib.isg_motion_create(plan.handle, _ptr(d), C.byref(h)))
+        self.handle = h
+        self.d = d
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.plan.lib.isg_motion_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Traj:
+    """A trajectory prepared for the k-space pair (Eq. 1-3)."""
+
+    def __init__(self, plan: "Plan", k: torch.Tensor):
+        self.plan = plan
+        if k.dim() != 2 or k.shape[1] != plan.ndim:
+            raise ValueError(f"k must be [M][{plan.ndim}]")
+        k = _require(k, torch.float32, None, "k")
+        self.M = int(k.shape[0])
+        h = C.c_void_p()
+        check(plan.lib.isg_traj_create(plan.handle, _ptr(k), self.M, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.plan.lib.isg_traj_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Shape, tables and scratch for one image geometry.
+
+    shape: image shape (2D or 3D, even lengths 8..512 with factors 2, 3, 5);
+    ncoils / nphases: coil count and most states per call; storage: element
+    type of the coil-expanded k-space grids ("fp32", "bf16", "fp16").
+    """
+
+    def __init__(self, shape, ncoils: int = 1, nphases: int = 1, storage: str = "fp32",
+                 device=None):
+        self.lib = _lib.load()
+        self.shape = tuple(int(s) for s in shape)
+        self.ndim = len(self.shape)
+        self.ncoils = int(ncoils)
+        self.nphases = int(nphases)
+        self.storage = storage
+        self.device = torch.device("cuda" if device is None else device)
+        desc = isg_plan_desc()
+        desc.ndim = self.ndim
+        for i, s in enumerate(self.shape):
+            desc.n[i] = s
+        desc.ncoils = self.ncoils
+        desc.nphases = self.nphases
+        desc.storage = _lib.STORAGE[storage]
+        with torch.cuda.device(self.device):
+            desc.stream = torch.cuda.current_stream().cuda_stream
+            h = C.c_void_p()
+            check(self.lib.isg_plan_create(C.byref(desc), C.byref(h)))
+        self.handle = h
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.isg_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def device_bytes(self) -> int:
+        b = C.c_int64(0)
+        check(self.lib.isg_plan_device_bytes(self.handle, C.byref(b)))
+        return b.value
+
+    def _sync_stream(self):
+        check(self.lib.isg_plan_set_stream(self.handle, torch.cuda.current_stream(self.device).cuda_stream))
+
+    # -- prepared inputs ----------------------------------------------------
+    def motion(self, d: torch.Tensor) -> Motion:
+        self._sync_stream()
+        return Motion(self, d)
+
+    def traj(self, k: torch.Tensor) -> Traj:
+        self._sync_stream()
+        return Traj(self, k)
+
+    # -- helpers ------------------------------------------------------------
+    def _image(self, x, name="x"):
+        return _require(x, torch.complex64, self.shape, name)
+
+    def _empty_image(self):
+        return torch.empty(self.shape, dtype=torch.complex64, device=self.device)
+
+    def _handles(self, motions, trajs):
+        P = len(motions)
+        if P != len(trajs):
+            raise ValueError("one trajectory per motion")
+        for m in motions:
+            if m.plan is not self:
+                raise ValueError("motion belongs to another plan")
+        for t in trajs:
+            if t.plan is not self:
+                raise ValueError("trajectory belongs to another plan")
+        dm = (C.c_void_p * P)(*[m.handle for m in motions])
+        km = (C.c_void_p * P)(*[t.handle for t in trajs])
+        return P, dm, km
+
+    def data_rows(self, trajs) -> int:
+        return sum(t.M for t in trajs)
+
+    # -- operators ----------------------------------------------------------
+    def warp(self, x: torch.Tensor, motion: Motion, out: torch.Tensor | None = None) -> torch.Tensor:
+        """T_d x (Eq. 9)."""
+        x = self._image(x)
+        out = self._empty_image() if out is None else self._image(out, "out")
+        self._sync_stream()
+        check(self.lib.isg_warp(self.handle, motion.handle, _ptr(x), _ptr(out)))
+        return out
+
+    def warp_adjoint(self, y: torch.Tensor, motion: Motion, out: torch.Tensor | None = None) -> torch.Tensor:
+        """T_d^H y (Eq. 7-8)."""
+        y = self._image(y, "y")
+        out = self._empty_image() if out is None else self._image(out, "out")
+        self._sync_stream()
+        check(self.lib.isg_warp_adjoint(self.handle, motion.handle, _ptr(y), _ptr(out)))
+        return out
+
+    def warp_grad_d(self, x: torch.Tensor, v: torch.Tensor, motion: Motion,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+        """Re(conj(v) * d(T_d x)/dd), float32 [ndim][*shape]."""
+        x = self._image(x)
+        v = self._image(v, "v")
+        if out is None:
+            out = torch.empty((self.ndim,) + self.shape, dtype=torch.float32, device=self.device)
+        self._sync_stream()
+        check(self.lib.isg_warp_grad_d(self.handle, motion.handle, _ptr(x), _ptr(v), _ptr(out)))
+        return out
+
+    def sense_forward(self, x, motions, S, trajs, out=None) -> torch.Tensor:
+        """Stacked nonrigid SENSE model (Eq. 10); returns [sum_p M_p][C]."""
+        x = self._image(x)
+        S = _require(S, torch.complex64, (self.ncoils,) + self.shape, "S")
+        P, dm, km = self._handles(motions, trajs)
+        rows = self.data_rows(trajs)
+        if out is None:
+            out = torch.empty((rows, self.ncoils), dtype=torch.complex64, device=self.device)
+        else:
+            out = _require(out, torch.complex64, (rows, self.ncoils), "out")
+        self._sync_stream()
+        check(self.lib.isg_sense_forward(self.handle, P, _ptr(x), dm, _ptr(S), km, _ptr(out)))
+        return out
+
+    def sense_adjoint(self, y, motions, S, trajs, out=None) -> torch.Tensor:
+        """sum_p A_p^H y_p (Fig. 3b)."""
+        S = _require(S, torch.complex64, (self.ncoils,) + self.shape, "S")
+        P, dm, km = self._handles(motions, trajs)
+        y = _require(y, torch.complex64, (self.data_rows(trajs), self.ncoils), "y")
+        out = self._empty_image() if out is None else self._image(out, "out")
+        self._sync_stream()
+        check(self.lib.isg_sense_adjoint(self.handle, P, _ptr(y), dm, _ptr(S), km, _ptr(out)))
+        return out
+
+    def normal(self, x, lam, motions, S, trajs, out=None) -> torch.Tensor:
+        """sum_p A_p^H A_p x + lam x."""
+        x = self._image(x)
+        S = _require(S, torch.complex64, (self.ncoils,) + self.shape, "S")
+        P, dm, km = self._handles(motions, trajs)
+        out = self._empty_image() if out is None else self._image(out, "out")
+        self._sync_stream()
+        check(self.lib.isg_normal(self.handle, P, _ptr(x), float(lam), dm, _ptr(S), km, _ptr(out)))
+        return out
+
+    def cg_solve(self, y, motions, S, trajs, lam: float, iters: int, x0=None):
+        """CG on (sum_p A_p^H A_p + lam I) x = sum_p A_p^H y_p; returns
+        (x, residual norms [iters + 1])."""
+        S = _require(S, torch.complex64, (self.ncoils,) + self.shape, "S")
+        P, dm, km = self._handles(motions, trajs)
+        y = _require(y, torch.complex64, (self.data_rows(trajs), self.ncoils), "y")
+        x = torch.zeros(self.shape, dtype=torch.complex64, device=self.device) if x0 is None \
+            else self._image(x0, "x0").clone()
+        hist = (C.c_double * (iters + 1))()
+        self._sync_stream()
+        check(self.lib.isg_cg_solve(self.handle, P, _ptr(y), dm, _ptr(S), km, float(lam), int(iters),
+                                    _ptr(x), hist))
+        return x, list(hist)

@@ -1,0 +1,164 @@
+"""GPU parity of every operator against the FP64 oracle, through the C ABI,
+on seeded inputs at sizes the oracle finishes in seconds.  Shapes are chosen
+so that the spread tiles and FFT line tiles have ragged tails.
+
+Tolerance: 1e-5 relative L2 for FP32 operators against FP64."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import (bump_displacement, coil_maps, ellipsoid_phantom, make_inputs, radial_spokes_2d,
+                   radial_spokes_3d, rng, small_workload, WORKLOADS, uniform_samples)
+
+from gpu_util import pack, rel, say, to_dev, unpack
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def isg():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2501_16713_amd as isg
+    return isg
+
+
+def _rand_c(g, shape):
+    return (g.standard_normal(shape) + 1j * g.standard_normal(shape)).astype(np.complex64)
+
+
+# --------------------------------------------------------------------------
+# image-space gridding
+# --------------------------------------------------------------------------
+def test_warp_2d_workload(isg):
+    """the 2D warp workload: 64x64 ellipses, 4 bumps sigma 8, max |d| 3"""
+    w = WORKLOADS["warp2d_64"]
+    inp = make_inputs(w, with_traj=False)
+    x, d = inp["x"], inp["d"][0]
+    say("warp2d_64: forward + adjoint")
+    plan = isg.Plan(w.shape)
+    mo = plan.motion(to_dev(d))
+    got = plan.warp(to_dev(x), mo).cpu().numpy()
+    assert rel(got, oracle.warp.warp(x, d)) < TOL
+    v = _rand_c(np.random.default_rng(1), w.shape)
+    got_a = plan.warp_adjoint(to_dev(v), mo).cpu().numpy()
+    assert rel(got_a, oracle.warp.warp_adjoint(v, d)) < TOL
+
+
+@pytest.mark.parametrize("shape,dmax", [((24, 20, 36), 4.0), ((16, 16, 16), 0.0), ((40, 32, 24), 9.0)])
+def test_warp_3d(isg, shape, dmax):
+    say(f"warp3d {shape} dmax {dmax}")
+    g = rng(11, 1)
+    x = ellipsoid_phantom(shape, 10, rng(11, 0)).astype(np.complex64)
+    d = bump_displacement(shape, 4, shape[0] / 5, dmax, g) if dmax > 0 else \
+        np.zeros((3,) + shape, dtype=np.float32)
+    plan = isg.Plan(shape)
+    mo = plan.motion(to_dev(d))
+    assert rel(plan.warp(to_dev(x), mo).cpu().numpy(), oracle.warp.warp(x, d)) < TOL
+    v = _rand_c(g, shape)
+    assert rel(plan.warp_adjoint(to_dev(v), mo).cpu().numpy(), oracle.warp.warp_adjoint(v, d)) < TOL
+
+
+def test_warp_integer_shift_and_wrap(isg):
+    """integer d moves whole taps; large d wraps around the periodic grid"""
+    shape = (16, 24, 20)
+    g = np.random.default_rng(3)
+    x = _rand_c(g, shape)
+    d = np.stack([np.full(shape, s, np.float32) for s in (3.0, -17.0, 41.5)])
+    plan = isg.Plan(shape)
+    mo = plan.motion(to_dev(d))
+    assert rel(plan.warp(to_dev(x), mo).cpu().numpy(), oracle.warp.warp(x, d)) < TOL
+
+
+def test_warp_adjoint_identity(isg):
+    shape = (32, 24, 40)
+    g = np.random.default_rng(4)
+    d = bump_displacement(shape, 5, 6.0, 6.0, g)
+    x, y = _rand_c(g, shape), _rand_c(g, shape)
+    plan = isg.Plan(shape)
+    mo = plan.motion(to_dev(d))
+    Tx = plan.warp(to_dev(x), mo).cpu().numpy().astype(np.complex128)
+    THy = plan.warp_adjoint(to_dev(y), mo).cpu().numpy().astype(np.complex128)
+    lhs, rhs = np.vdot(y, Tx), np.vdot(THy, x)
+    assert abs(lhs - rhs) < 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("shape", [(40, 36), (16, 20, 24)])
+def test_warp_grad_d(isg, shape):
+    say(f"grad_d {shape}")
+    g = np.random.default_rng(5)
+    x = ellipsoid_phantom(shape, 10, rng(12, 0)).astype(np.complex64)
+    d = bump_displacement(shape, 3, shape[0] / 4, 3.0, g)
+    v = _rand_c(g, shape)
+    plan = isg.Plan(shape)
+    mo = plan.motion(to_dev(d))
+    got = plan.warp_grad_d(to_dev(x), to_dev(v), mo).cpu().numpy()
+    want = oracle.warp.warp_grad_d(x, d, v)
+    assert np.linalg.norm(got - want) < TOL * np.linalg.norm(want)
+
+
+# --------------------------------------------------------------------------
+# nonrigid SENSE
+# --------------------------------------------------------------------------
+def _small_sense(shape=(16, 20, 24), C=3, P=2):
+    ndim = len(shape)
+    w = small_workload(shape=shape, ncoils=C, nphases=P, spokes=(30, 45, 20)[:P], readout=max(shape))
+    if ndim == 3:
+        return w, make_inputs(w)
+    inp = make_inputs(w, with_traj=False)
+    inp["k"] = [radial_spokes_2d(0, 25, 48), uniform_samples(700, 2, np.random.default_rng(9))][:P]
+    return w, inp
+
+
+@pytest.mark.parametrize("shape,C,P", [((16, 20, 24), 3, 2), ((24, 18, 20), 5, 3), ((32, 40), 4, 2)])
+def test_sense_forward_adjoint(isg, shape, C, P):
+    say(f"sense {shape} C={C} P={P}")
+    w, inp = _small_sense(shape, C, P)
+    plan = isg.Plan(shape, ncoils=C, nphases=P)
+    S = to_dev(inp["S"])
+    mots = [plan.motion(to_dev(d)) for d in inp["d"]]
+    trs = [plan.traj(to_dev(k)) for k in inp["k"]]
+    y = plan.sense_forward(to_dev(inp["x"]), mots, S, trs).cpu().numpy()
+    want = oracle.sense.sense_forward(inp["x"], inp["d"], inp["S"], inp["k"])
+    assert rel(y, pack(want)) < TOL
+    g = np.random.default_rng(2)
+    yr = _rand_c(g, y.shape)
+    xa = plan.sense_adjoint(to_dev(yr), mots, S, trs).cpu().numpy()
+    want_a = oracle.sense.sense_adjoint(unpack(yr, inp["k"]), inp["d"], inp["S"], inp["k"], shape)
+    assert rel(xa, want_a) < TOL
+
+
+def test_normal_operator(isg):
+    shape, C, P = (16, 20, 24), 3, 2
+    say("normal small")
+    w, inp = _small_sense(shape, C, P)
+    plan = isg.Plan(shape, ncoils=C, nphases=P)
+    S = to_dev(inp["S"])
+    mots = [plan.motion(to_dev(d)) for d in inp["d"]]
+    trs = [plan.traj(to_dev(k)) for k in inp["k"]]
+    lam = 0.05
+    got = plan.normal(to_dev(inp["x"]), lam, mots, S, trs).cpu().numpy()
+    want = oracle.sense.normal(inp["x"], lam, inp["d"], inp["S"], inp["k"])
+    assert rel(got, want) < TOL
+
+
+def test_cg_solve(isg):
+    shape, C, P = (16, 16, 16), 3, 2
+    say("cg small")
+    w, inp = _small_sense(shape, C, P)
+    plan = isg.Plan(shape, ncoils=C, nphases=P)
+    S = to_dev(inp["S"])
+    mots = [plan.motion(to_dev(d)) for d in inp["d"]]
+    trs = [plan.traj(to_dev(k)) for k in inp["k"]]
+    ys = oracle.sense.sense_forward(inp["x"], inp["d"], inp["S"], inp["k"])
+    y = pack(ys).astype(np.complex64)
+    lam, iters = 1e-2, 8
+    x, hist = plan.cg_solve(to_dev(y), mots, S, trs, lam, iters)
+    yo = unpack(y.astype(np.complex128), inp["k"])
+    b = oracle.sense.sense_adjoint(yo, inp["d"], inp["S"], inp["k"], shape)
+    xo, ho = oracle.cg.cg(lambda v: oracle.sense.normal(v, lam, inp["d"], inp["S"], inp["k"]), b, iters)
+    # CG amplifies FP32 rounding; budget 1e-4 on the iterate
+    assert rel(x.cpu().numpy(), xo) < 1e-4
+    assert np.allclose(hist, ho, rtol=1e-3, atol=0)
