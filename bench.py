@@ -1,0 +1,230 @@
+"""Benchmark of the nonrigid-SENSE normal operator on one MI355X.
+
+A step is one application of the l2 normal operator of Eq. 11,
+N x = sum_p A_p^H A_p x + lambda x, at 160^3, 12 coils, 6 respiratory states
+with 80k..600k golden-angle radial samples each: every stage of the hot path
+(upsampling FFTs, warp gather, coil-expanded FFTs, k-space gather and
+spread, coil-reduced inverse FFTs, warp spread, adjoint upsampling FFTs and
+the lambda term).  Inputs are seeded synthetic data already resident in HBM.
+After the timed steps a 20-iteration CG solve (HIP graph per iteration) is
+timed as well and reported under "cg".
+
+Prints ONE JSON line (see the keys below).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic bytes of one launch of each operator stage (3D, C coils),
+# element size es of the coil-expanded grids; B* are element counts
+def stage_bytes(tag, n, G, C, es, M=0):
+    n0, n1, n2 = n
+    G0, G1, G2 = G
+    N = n0 * n1 * n2
+    NG = G0 * G1 * G2
+    c8 = 8
+    table = {
+        "fft_coil_fwd_last": N * c8 * (1 + C) + n0 * n1 * G2 * C * es,
+        "fft_coil_fwd_ax1": n0 * n1 * G2 * C * es + n0 * G1 * G2 * C * es,
+        "fft_coil_fwd_ax0": n0 * G1 * G2 * C * es + NG * C * es,
+        "fft_coil_adj_ax0": NG * C * es + n0 * G1 * G2 * C * es,
+        "fft_coil_adj_ax1": n0 * G1 * G2 * C * es + n0 * n1 * G2 * C * es,
+        "fft_coil_adj_last": n0 * n1 * G2 * C * es + N * c8 * (C + 1),
+        "fft_up_ax2": 2 * N * c8,
+        "fft_up_ax1": 2 * N * c8,
+        "fft_up_ax0": N * c8 + G0 * n1 * n2 * c8,
+        "fft_up_G1": G0 * n1 * n2 * c8 + G0 * G1 * n2 * c8,
+        "fft_up_G2": G0 * G1 * n2 * c8 + NG * c8,
+        "fft_uph_G2": NG * c8 + G0 * G1 * n2 * c8,
+        "fft_uph_G1": G0 * G1 * n2 * c8 + G0 * n1 * n2 * c8,
+        "fft_uph_ax0": G0 * n1 * n2 * c8 + N * c8,
+        "fft_uph_ax1": 2 * N * c8,
+        "fft_uph_ax2": 2 * N * c8,
+    }
+    return table.get(tag)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched_160")
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--cg-iters", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--breakdown", action="store_true", help="print a per-stage timing table to stderr")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the path would shard over (state, coil) units; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2501_16713_amd as isg
+    from synth import WORKLOADS, make_inputs, rng, complex_noise, P_NOISE
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    w = WORKLOADS[args.workload]
+    t0 = time.time()
+    inp = make_inputs(w)
+    log(f"inputs for {w.name} ready in {time.time() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    with torch.cuda.stream(stream):
+        plan = isg.Plan(w.shape, ncoils=w.ncoils, nphases=w.nphases, storage=args.storage)
+        x = torch.from_numpy(inp["x"]).to(dev)
+        S = torch.from_numpy(inp["S"]).to(dev)
+        t0 = time.time()
+        mots = [plan.motion(torch.from_numpy(d).to(dev)) for d in inp["d"]]
+        trs = [plan.traj(torch.from_numpy(k).to(dev)) for k in inp["k"]]
+        torch.cuda.synchronize()
+        log(f"plan-time preparation {time.time() - t0:.1f}s; plan holds {plan.device_bytes() / 2**30:.2f} GiB")
+        out = torch.empty_like(x)
+        lam = w.lam
+
+        def step():
+            plan.normal(x, lam, mots, S, trs, out=out)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+
+        # per-stage timing pass (not the timed region): find the dominant stage
+        plan.set_timing(True, "")
+        step()
+        stages = plan.read_timing()
+        plan.set_timing(False)
+        dominant = max(stages, key=lambda t: stages[t][1])
+        if args.breakdown:
+            tot = sum(v[1] for v in stages.values())
+            for t, (cnt, ms) in sorted(stages.items(), key=lambda kv: -kv[1][1]):
+                log(f"  {t:22s} {cnt:4d} launches {ms:9.3f} ms  {100 * ms / tot:5.1f}%")
+
+        # timed region: only the dominant stage is bracketed with events
+        plan.set_timing(True, dominant)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_total = ev0.elapsed_time(ev1)
+        dom = plan.read_timing().get(dominant, (0, 0.0))
+        plan.set_timing(False)
+        ms_per_step = ms_total / args.steps
+        value = 1000.0 / ms_per_step
+
+        # CG (not part of the headline value)
+        cg = None
+        if args.cg_iters > 0:
+            y = plan.sense_forward(x, mots, S, trs)
+            rms = float(torch.sqrt(torch.mean(torch.abs(y) ** 2)).item())
+            noise = torch.from_numpy(complex_noise(tuple(y.shape), rng(w.cfg, P_NOISE))).to(dev)
+            y = y + 0.01 * rms * noise
+            torch.cuda.synchronize()
+            t0 = time.time()
+            xs, hist = plan.cg_solve(y, mots, S, trs, lam, args.cg_iters)
+            cg_s = time.time() - t0
+            cg = {"iters": args.cg_iters, "seconds": round(cg_s, 4),
+                  "ms_per_iter": round(1000 * cg_s / args.cg_iters, 3),
+                  "resnorm_first_last": [hist[0], hist[-1]]}
+
+    es = 8 if args.storage == "fp32" else 4
+    G = tuple(2 * n for n in w.shape)
+    per_launch = stage_bytes(dominant, w.shape, G, w.ncoils, es)
+    roofline = None
+    if per_launch and dom[0] > 0:
+        avg_ms = dom[1] / dom[0]
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": 8000.0,
+                    "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                    "bytes_per_launch": per_launch, "avg_launch_ms": round(avg_ms, 4),
+                    "launches": dom[0]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(inp, w, log)
+
+    total_samples = sum(k.shape[0] for k in inp["k"])
+    line = {
+        "metric": "nonrigid-SENSE A^H A applies/s at 160^3x12 coils",
+        "value": round(value, 3),
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64" if args.storage == "fp32" else f"c64+{args.storage}-grids",
+        "data": "synthetic",
+        "config": {"workload": w.name, "shape": list(w.shape), "coils": w.ncoils, "phases": w.nphases,
+                   "samples_per_phase": [int(k.shape[0]) for k in inp["k"]], "lambda": lam,
+                   "storage": args.storage},
+        "gridding_gpts_per_s": {
+            "kspace_point_coil_interps": round(2 * total_samples * w.ncoils * value / 1e9, 4),
+            "warp_voxels": round(2 * w.nphases * int(np.prod(w.shape)) * value / 1e9, 4),
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "cg": cg,
+        "stages_ms": {k: round(v[1], 4) for k, v in sorted(stages.items(), key=lambda kv: -kv[1][1])},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(inp, w, log):
+    """The FP64 oracle timed on this host on a bounded sample of the same
+    workload, scaled to applies/s.  One apply is P x (T + T^H) plus
+    P x C coil units (G_p then G_p^H); the sample times one coil unit of
+    state 0 and the warp pair of state 0 on 1/32 of the voxels, whose FFT
+    part (the upsampling of the whole image) is timed separately."""
+    import numpy as np
+    import oracle
+
+    cores = os.cpu_count()
+    x = inp["x"].astype(np.complex128)
+    d, k, S = inp["d"][0], inp["k"][0], inp["S"]
+    shape = w.shape
+    nvox = int(np.prod(shape))
+    sub = np.arange(0, nvox, 32)
+    t = time.time()
+    u = oracle.warp.upsample(x)
+    t_up = time.time() - t
+    t = time.time()
+    oracle.grid.gather(u, oracle.warp.warp_coords(d)[sub])
+    t_gather_sub = time.time() - t
+    t = time.time()
+    yk = oracle.kspace.nufft_forward(S[0].astype(np.complex128) * x, k)
+    zk = oracle.kspace.nufft_adjoint(yk, k, shape)
+    t_coil = time.time() - t
+    # T ~ upsample + gather; T^H ~ spread + same FFT work: taken equal to T
+    t_warp = t_up + 32 * t_gather_sub
+    per_apply = w.nphases * 2 * t_warp + w.nphases * w.ncoils * t_coil
+    log(f"oracle sample: upsample {t_up:.1f}s, gather 1/32 {t_gather_sub:.1f}s, coil unit {t_coil:.1f}s "
+        f"-> {per_apply:.0f}s per apply")
+    return {"value": round(1.0 / per_apply, 6), "unit": "applies/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle, state 0: one coil's G then G^H ({t_coil:.1f}s), the upsampling FFTs "
+                       f"({t_up:.1f}s) and the warp gather on 1/32 of the voxels ({t_gather_sub:.1f}s); "
+                       f"scaled to {w.nphases} states x {w.ncoils} coils with T^H taken equal to T "
+                       f"-> {per_apply:.0f}s per apply")}
+
+
+if __name__ == "__main__":
+    main()

@@ -113,6 +113,17 @@ isg_status isg_plan_set_stream(isg_plan* plan, void* stream);
 /* Device bytes the plan currently holds. */
 isg_status isg_plan_device_bytes(const isg_plan* plan, int64_t* bytes);
 
+/* Per-kernel timing for profiling.  With enable != 0 every kernel launch
+ * whose tag starts with `prefix` ("" or NULL = every launch) is bracketed
+ * by HIP events on the plan's stream; enabling or disabling clears the
+ * totals.  Tags name the operator stage, e.g. "fft_coil_fwd_ax0",
+ * "kgather", "warp_spread". */
+isg_status isg_plan_set_timing(isg_plan* plan, int enable, const char* prefix);
+/* Write the totals as JSON {"tag": [launches, total_ms], ...} into buf (len
+ * bytes, NUL-terminated).  Waits for the recorded events.  INVALID_ARG if
+ * buf is too small. */
+isg_status isg_plan_read_timing(isg_plan* plan, char* buf, int64_t len);
+
 /* Prepare a displacement field d (device float32 [ndim][n...], voxels) for
  * T_d / T_d^H (Eq. 5): tap bases and tile bins for the spreading adjoint.
  * NOT_FINITE if d holds NaN/Inf. */

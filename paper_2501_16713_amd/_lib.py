@@ -27,6 +27,8 @@ SIGNATURES = {
     "isg_plan_destroy": (C.c_int, [_p]),
     "isg_plan_set_stream": (C.c_int, [_p, _p]),
     "isg_plan_device_bytes": (C.c_int, [_p, C.POINTER(_i64)]),
+    "isg_plan_set_timing": (C.c_int, [_p, C.c_int, C.c_char_p]),
+    "isg_plan_read_timing": (C.c_int, [_p, C.c_char_p, _i64]),
     "isg_motion_create": (C.c_int, [_p, _p, C.POINTER(_p)]),
     "isg_motion_destroy": (C.c_int, [_p]),
     "isg_traj_create": (C.c_int, [_p, _p, _i64, C.POINTER(_p)]),

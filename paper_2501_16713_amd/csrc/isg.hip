@@ -150,8 +150,67 @@ struct isg_plan {
   double* cg_part = nullptr;
   CgScalars* cg_sc = nullptr;
   DevBuf cg_hist;
+  hipStream_t own_stream = nullptr;  // CG capture stream when the caller's is the null stream
   int64_t bytes = 0;
+  // per-kernel event timing (off unless enabled)
+  struct Pending {
+    std::string tag;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  bool capturing = false;
+  std::string timing_filter;  // only tags starting with this prefix ("" = all)
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<int64_t, double>> timed;  // tag -> (launches, total ms)
 };
+
+static hipEvent_t pool_event(isg_plan* pl) {
+  if (!pl->pool.empty()) {
+    hipEvent_t e = pl->pool.back();
+    pl->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_OK(hipEventCreate(&e));
+  return e;
+}
+
+// brackets one launch with events on the plan's stream when timing is on
+struct Tick {
+  isg_plan* pl;
+  bool on;
+  hipEvent_t a = nullptr;
+  const char* tag;
+  Tick(isg_plan* p, const char* t) : pl(p), tag(t) {
+    on = pl->timing && !pl->capturing &&
+         (pl->timing_filter.empty() || std::string(t).rfind(pl->timing_filter, 0) == 0);
+    if (on) {
+      a = pool_event(pl);
+      HIP_OK(hipEventRecord(a, pl->stream));
+    }
+  }
+  ~Tick() noexcept(false) {
+    if (!on) return;
+    hipEvent_t b = pool_event(pl);
+    HIP_OK(hipEventRecord(b, pl->stream));
+    pl->pending.push_back({tag, a, b});
+  }
+};
+
+static void collect_timing(isg_plan* pl) {
+  for (auto& p : pl->pending) {
+    HIP_OK(hipEventSynchronize(p.b));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, p.a, p.b));
+    auto& t = pl->timed[p.tag];
+    t.first += 1;
+    t.second += ms;
+    pl->pool.push_back(p.a);
+    pl->pool.push_back(p.b);
+  }
+  pl->pending.clear();
+}
 
 struct isg_motion {
   isg_plan* plan = nullptr;
@@ -265,7 +324,7 @@ static void allow_lds(K kernel, size_t bytes) {
 }
 
 template <class Ld, class Mid, class St>
-static void run_pass(isg_plan* pl, const Ld& ld, const Mid& mid, const St& st, const TileGeom& g,
+static void run_pass(isg_plan* pl, const char* tag, const Ld& ld, const Mid& mid, const St& st, const TileGeom& g,
                      const LinePlan& l1, float s1, const LinePlan* l2, float s2) {
   PassDesc pd;
   memset(&pd, 0, sizeof(pd));
@@ -295,6 +354,7 @@ static void run_pass(isg_plan* pl, const Ld& ld, const Mid& mid, const St& st, c
   allow_lds(kern, lds);
   const int64_t gx = std::min<int64_t>(tiles, 1 << 30);
   const int64_t gy = (tiles + gx - 1) / gx;
+  Tick tick(pl, tag);
   hipLaunchKernelGGL(kern, dim3((unsigned)gx, (unsigned)gy), dim3(kFftThreads), lds, pl->stream, ld, mid, st, pd);
   LAUNCH_OK();
 }
@@ -350,30 +410,30 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
     mid.three_d = 1;
     {  // F along axis 2
       TileGeom g = make_geom((int64_t)n0 * n1, 1, n2, 0);
-      run_pass(pl, ld_strided<kFP32>(x, n2, 1, n2, n2, kDense, g), NoMid(),
+      run_pass(pl, "fft_up_ax2", ld_strided<kFP32>(x, n2, 1, n2, n2, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufA, n2, 1, n2, n2, kDense, g), g, line_plan(pl, n2), -1.f, nullptr, 0.f);
     }
     {  // F along axis 1, in place
       TileGeom g = make_geom(n0, n2, n1, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
+      run_pass(pl, "fft_up_ax1", ld_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), g, line_plan(pl, n1), -1.f,
                nullptr, 0.f);
     }
     {  // F along axis 0, deapodize, pad, F^H of length G0
       TileGeom g = make_geom(1, (int64_t)n1 * n2, G0, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufA, 0, (int64_t)n1 * n2, n0, n0, kDense, g), mid,
+      run_pass(pl, "fft_up_ax0", ld_strided<kFP32>(pl->bufA, 0, (int64_t)n1 * n2, n0, n0, kDense, g), mid,
                st_strided<kFP32>(pl->bufB, 0, (int64_t)n1 * n2, G0, G0, kDense, g), g, line_plan(pl, n0), -1.f,
                &line_plan(pl, G0), +1.f);
     }
     {  // F^H along axis 1 with the spectral pad
       TileGeom g = make_geom(G0, n2, G1, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufB, (int64_t)n1 * n2, n2, n1, G1, kSpectral, g), NoMid(),
+      run_pass(pl, "fft_up_G1", ld_strided<kFP32>(pl->bufB, (int64_t)n1 * n2, n2, n1, G1, kSpectral, g), NoMid(),
                st_strided<kFP32>(pl->bufC, (int64_t)G1 * n2, n2, G1, G1, kDense, g), g, line_plan(pl, G1), +1.f,
                nullptr, 0.f);
     }
     {  // F^H along axis 2 with the spectral pad
       TileGeom g = make_geom((int64_t)G0 * G1, 1, G2, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufC, n2, 1, n2, G2, kSpectral, g), NoMid(),
+      run_pass(pl, "fft_up_G2", ld_strided<kFP32>(pl->bufC, n2, 1, n2, G2, kSpectral, g), NoMid(),
                st_strided<kFP32>(u, G2, 1, G2, G2, kDense, g), g, line_plan(pl, G2), +1.f, nullptr, 0.f);
     }
   } else {
@@ -381,18 +441,18 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
     mid.three_d = 0;
     {
       TileGeom g = make_geom(n0, 1, n1, 0);
-      run_pass(pl, ld_strided<kFP32>(x, n1, 1, n1, n1, kDense, g), NoMid(),
+      run_pass(pl, "fft_up_ax1", ld_strided<kFP32>(x, n1, 1, n1, n1, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufA, n1, 1, n1, n1, kDense, g), g, line_plan(pl, n1), -1.f, nullptr, 0.f);
     }
     {
       TileGeom g = make_geom(1, n1, G0, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufA, 0, n1, n0, n0, kDense, g), mid,
+      run_pass(pl, "fft_up_ax0", ld_strided<kFP32>(pl->bufA, 0, n1, n0, n0, kDense, g), mid,
                st_strided<kFP32>(pl->bufB, 0, n1, G0, G0, kDense, g), g, line_plan(pl, n0), -1.f, &line_plan(pl, G0),
                +1.f);
     }
     {
       TileGeom g = make_geom(G0, 1, G1, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufB, n1, 1, n1, G1, kSpectral, g), NoMid(),
+      run_pass(pl, "fft_up_G1", ld_strided<kFP32>(pl->bufB, n1, 1, n1, G1, kSpectral, g), NoMid(),
                st_strided<kFP32>(u, G1, 1, G1, G1, kDense, g), g, line_plan(pl, G1), +1.f, nullptr, 0.f);
     }
   }
@@ -412,30 +472,30 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
     mid.three_d = 1;
     {  // F along axis 2, crop
       TileGeom g = make_geom((int64_t)G0 * G1, 1, G2, 0);
-      run_pass(pl, ld_strided<kFP32>(U, G2, 1, G2, G2, kDense, g), NoMid(),
+      run_pass(pl, "fft_uph_G2", ld_strided<kFP32>(U, G2, 1, G2, G2, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufC, n2, 1, n2, G2, kSpectral, g), g, line_plan(pl, G2), -1.f, nullptr, 0.f);
     }
     {  // F along axis 1, crop
       TileGeom g = make_geom(G0, n2, G1, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufC, (int64_t)G1 * n2, n2, G1, G1, kDense, g), NoMid(),
+      run_pass(pl, "fft_uph_G1", ld_strided<kFP32>(pl->bufC, (int64_t)G1 * n2, n2, G1, G1, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufB, (int64_t)n1 * n2, n2, n1, G1, kSpectral, g), g, line_plan(pl, G1), -1.f,
                nullptr, 0.f);
     }
     {  // F along axis 0, crop, deapodize, F^H of length n0
       TileGeom g = make_geom(1, (int64_t)n1 * n2, G0, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufB, 0, (int64_t)n1 * n2, G0, G0, kDense, g), mid,
+      run_pass(pl, "fft_uph_ax0", ld_strided<kFP32>(pl->bufB, 0, (int64_t)n1 * n2, G0, G0, kDense, g), mid,
                st_strided<kFP32>(pl->bufA, 0, (int64_t)n1 * n2, n0, n0, kDense, g), g, line_plan(pl, G0), -1.f,
                &line_plan(pl, n0), +1.f);
     }
     {  // F^H along axis 1, in place
       TileGeom g = make_geom(n0, n2, n1, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
+      run_pass(pl, "fft_uph_ax1", ld_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), g, line_plan(pl, n1), +1.f,
                nullptr, 0.f);
     }
     {  // F^H along axis 2
       TileGeom g = make_geom((int64_t)n0 * n1, 1, n2, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufA, n2, 1, n2, n2, kDense, g), NoMid(),
+      run_pass(pl, "fft_uph_ax2", ld_strided<kFP32>(pl->bufA, n2, 1, n2, n2, kDense, g), NoMid(),
                st_strided<kFP32>(out, n2, 1, n2, n2, kDense, g), g, line_plan(pl, n2), +1.f, nullptr, 0.f);
     }
   } else {
@@ -443,18 +503,18 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
     mid.three_d = 0;
     {
       TileGeom g = make_geom(G0, 1, G1, 0);
-      run_pass(pl, ld_strided<kFP32>(U, G1, 1, G1, G1, kDense, g), NoMid(),
+      run_pass(pl, "fft_uph_G1", ld_strided<kFP32>(U, G1, 1, G1, G1, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufB, n1, 1, n1, G1, kSpectral, g), g, line_plan(pl, G1), -1.f, nullptr, 0.f);
     }
     {
       TileGeom g = make_geom(1, n1, G0, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufB, 0, n1, G0, G0, kDense, g), mid,
+      run_pass(pl, "fft_uph_ax0", ld_strided<kFP32>(pl->bufB, 0, n1, G0, G0, kDense, g), mid,
                st_strided<kFP32>(pl->bufA, 0, n1, n0, n0, kDense, g), g, line_plan(pl, G0), -1.f, &line_plan(pl, n0),
                +1.f);
     }
     {
       TileGeom g = make_geom(n0, 1, n1, 0);
-      run_pass(pl, ld_strided<kFP32>(pl->bufA, n1, 1, n1, n1, kDense, g), NoMid(),
+      run_pass(pl, "fft_uph_ax1", ld_strided<kFP32>(pl->bufA, n1, 1, n1, n1, kDense, g), NoMid(),
                st_strided<kFP32>(out, n1, 1, n1, n1, kDense, g), g, line_plan(pl, n1), +1.f, nullptr, 0.f);
     }
   }
@@ -466,6 +526,7 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
 static unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 static void warp_gather(isg_plan* pl, const float2* u, const isg_motion* mo, float2* out) {
+  Tick tick(pl, "warp_gather");
   if (pl->ndim == 3)
     hipLaunchKernelGGL(warp_gather_kernel<3>, dim3(blocks_for(pl->N, kGridThreads)), dim3(kGridThreads), 0,
                        pl->stream, u, mo->d, out, pl->dims, pl->kb);
@@ -495,6 +556,7 @@ static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const 
       ph.w[i] = w[p0 + i];
     }
     const int acc = p0 > 0 ? 1 : 0;
+    Tick tick(pl, "warp_spread");
     if (pl->ndim == 3)
       hipLaunchKernelGGL(warp_spread_kernel<3>, dim3(warp_ntiles(pl)), dim3(kGridThreads), lds, pl->stream, ph, U,
                          acc, pl->dims, pl->wtile, pl->kb);
@@ -529,18 +591,18 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
       ld.n1 = n1;
       ld.nd = make_fastdiv(n2);
       ld.cd = make_fastdiv(C);
-      run_pass(pl, ld, NoMid(), st_strided<S>(pl->k1buf, (int64_t)G2 * C, C, G2, G2, kDense, g), g,
+      run_pass(pl, "fft_coil_fwd_last", ld, NoMid(), st_strided<S>(pl->k1buf, (int64_t)G2 * C, C, G2, G2, kDense, g), g,
                line_plan(pl, G2), -1.f, nullptr, 0.f);
     }
     {  // centred pad, F along axis 1
       TileGeom g = make_geom(n0, (int64_t)G2 * C, G1, 0);
-      run_pass(pl, ld_strided<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g), NoMid(),
+      run_pass(pl, "fft_coil_fwd_ax1", ld_strided<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g), NoMid(),
                st_strided<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g), g,
                line_plan(pl, G1), -1.f, nullptr, 0.f);
     }
     {  // centred pad, F along axis 0
       TileGeom g = make_geom(1, (int64_t)G1 * G2 * C, G0, 0);
-      run_pass(pl, ld_strided<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g), NoMid(),
+      run_pass(pl, "fft_coil_fwd_ax0", ld_strided<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g), NoMid(),
                st_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g), g, line_plan(pl, G0), -1.f, nullptr,
                0.f);
     }
@@ -559,12 +621,12 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
       ld.n1 = 0;
       ld.nd = make_fastdiv(n1);
       ld.cd = make_fastdiv(C);
-      run_pass(pl, ld, NoMid(), st_strided<S>(pl->k1buf, (int64_t)G1 * C, C, G1, G1, kDense, g), g,
+      run_pass(pl, "fft_coil_fwd_last", ld, NoMid(), st_strided<S>(pl->k1buf, (int64_t)G1 * C, C, G1, G1, kDense, g), g,
                line_plan(pl, G1), -1.f, nullptr, 0.f);
     }
     {
       TileGeom g = make_geom(1, (int64_t)G1 * C, G0, 0);
-      run_pass(pl, ld_strided<S>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g), NoMid(),
+      run_pass(pl, "fft_coil_fwd_ax0", ld_strided<S>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g), NoMid(),
                st_strided<S>(grid, 0, (int64_t)G1 * C, G0, G0, kDense, g), g, line_plan(pl, G0), -1.f, nullptr, 0.f);
     }
   }
@@ -579,13 +641,13 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
   if (pl->ndim == 3) {
     {  // F^H along axis 0, centred crop
       TileGeom g = make_geom(1, (int64_t)G1 * G2 * C, G0, 0);
-      run_pass(pl, ld_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g), NoMid(),
+      run_pass(pl, "fft_coil_adj_ax0", ld_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g), NoMid(),
                st_strided<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g), g, line_plan(pl, G0), +1.f,
                nullptr, 0.f);
     }
     {  // F^H along axis 1, centred crop
       TileGeom g = make_geom(n0, (int64_t)G2 * C, G1, 0);
-      run_pass(pl, ld_strided<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g), NoMid(),
+      run_pass(pl, "fft_coil_adj_ax1", ld_strided<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g), NoMid(),
                st_strided<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g), g,
                line_plan(pl, G1), +1.f, nullptr, 0.f);
     }
@@ -602,13 +664,13 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
       st.C = C;
       st.n1 = n1;
       st.nd = make_fastdiv(n2);
-      run_pass(pl, ld_strided<S>(pl->k1buf, (int64_t)G2 * C, C, G2, G2, kDense, g), NoMid(), st, g,
+      run_pass(pl, "fft_coil_adj_last", ld_strided<S>(pl->k1buf, (int64_t)G2 * C, C, G2, G2, kDense, g), NoMid(), st, g,
                line_plan(pl, G2), +1.f, nullptr, 0.f);
     }
   } else {
     {
       TileGeom g = make_geom(1, (int64_t)G1 * C, G0, 0);
-      run_pass(pl, ld_strided<S>(grid, 0, (int64_t)G1 * C, G0, G0, kDense, g), NoMid(),
+      run_pass(pl, "fft_coil_adj_ax0", ld_strided<S>(grid, 0, (int64_t)G1 * C, G0, G0, kDense, g), NoMid(),
                st_strided<S>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g), g, line_plan(pl, G0), +1.f,
                nullptr, 0.f);
     }
@@ -625,7 +687,7 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
       st.C = C;
       st.n1 = 0;
       st.nd = make_fastdiv(n1);
-      run_pass(pl, ld_strided<S>(pl->k1buf, (int64_t)G1 * C, C, G1, G1, kDense, g), NoMid(), st, g,
+      run_pass(pl, "fft_coil_adj_last", ld_strided<S>(pl->k1buf, (int64_t)G1 * C, C, G1, G1, kDense, g), NoMid(), st, g,
                line_plan(pl, G1), +1.f, nullptr, 0.f);
     }
   }
@@ -634,6 +696,7 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
 template <int S>
 static void kgather_t(isg_plan* pl, const void* grid, const isg_traj* tr, float2* y) {
   auto grd = (const typename Elem<S>::T*)grid;
+  Tick tick(pl, "kgather");
   if (pl->ndim == 3)
     hipLaunchKernelGGL((kgather_kernel<3, S>), dim3(blocks_for(tr->M, kGridThreads)), dim3(kGridThreads), 0,
                        pl->stream, grd, tr->taps, tr->M, y, pl->C, pl->dims, pl->kb);
@@ -653,10 +716,12 @@ static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* y, void* g
   if (pl->ndim == 3) {
     auto k = kspread_kernel<3, S>;
     allow_lds(k, lds);
+    Tick tick(pl, "kspread");
     hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kGridThreads), lds, pl->stream, tr->units, tr->order, tr->taps, y,
                        pl->C, grd, part, pl->dims, pl->ktile, pl->kb);
     LAUNCH_OK();
     if (tr->nsplits) {
+      Tick tick2(pl, "kspread_reduce");
       hipLaunchKernelGGL((kspread_reduce_kernel<3, S>), dim3(tr->nsplits), dim3(kGridThreads), 0, pl->stream,
                          tr->splits, part, pl->C, grd, pl->dims, pl->ktile);
       LAUNCH_OK();
@@ -664,10 +729,12 @@ static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* y, void* g
   } else {
     auto k = kspread_kernel<2, S>;
     allow_lds(k, lds);
+    Tick tick(pl, "kspread");
     hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kGridThreads), lds, pl->stream, tr->units, tr->order, tr->taps, y,
                        pl->C, grd, part, pl->dims, pl->ktile, pl->kb);
     LAUNCH_OK();
     if (tr->nsplits) {
+      Tick tick2(pl, "kspread_reduce");
       hipLaunchKernelGGL((kspread_reduce_kernel<2, S>), dim3(tr->nsplits), dim3(kGridThreads), 0, pl->stream,
                          tr->splits, part, pl->C, grd, pl->dims, pl->ktile);
       LAUNCH_OK();
@@ -749,6 +816,7 @@ static void op_normal(isg_plan* pl, int P, const float2* x, double lam, const is
   warp_spread(pl, P, d, w.data(), pl->ugrid);
   upsample_adjoint(pl, pl->ugrid, out);
   if (lam != 0.0) {
+    Tick tick(pl, "axpy");
     hipLaunchKernelGGL(axpy_kernel, dim3(std::min<int64_t>(blocks_for(pl->N, kVecThreads), 4096)), dim3(kVecThreads),
                        0, pl->stream, out, x, (float)lam, pl->N);
     LAUNCH_OK();
@@ -1093,6 +1161,12 @@ isg_status isg_plan_destroy(isg_plan* pl) {
   if (pl->ybuf.p) (void)hipFree(pl->ybuf.p);
   if (pl->partial.p) (void)hipFree(pl->partial.p);
   if (pl->cg_hist.p) (void)hipFree(pl->cg_hist.p);
+  if (pl->own_stream) (void)hipStreamDestroy(pl->own_stream);
+  for (auto& p : pl->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : pl->pool) (void)hipEventDestroy(e);
   (void)hipGetLastError();
   delete pl;
   return ISG_OK;
@@ -1108,6 +1182,37 @@ isg_status isg_plan_device_bytes(const isg_plan* pl, int64_t* bytes) {
   if (!pl || !bytes) return fail(ISG_ERR_INVALID_ARG, "plan and bytes must not be NULL");
   *bytes = pl->bytes;
   return ISG_OK;
+}
+
+isg_status isg_plan_set_timing(isg_plan* pl, int enable, const char* prefix) {
+  if (!pl) return fail(ISG_ERR_INVALID_ARG, "plan is NULL");
+  return guarded(pl, [&]() {
+    collect_timing(pl);
+    pl->timed.clear();
+    pl->timing = enable != 0;
+    pl->timing_filter = prefix ? prefix : "";
+    return ISG_OK;
+  });
+}
+
+isg_status isg_plan_read_timing(isg_plan* pl, char* buf, int64_t len) {
+  if (!pl || !buf || len < 3) return fail(ISG_ERR_INVALID_ARG, "plan / buffer invalid");
+  return guarded(pl, [&]() -> isg_status {
+    collect_timing(pl);
+    std::string js = "{";
+    bool first = true;
+    for (auto& kv : pl->timed) {
+      char tmp[256];
+      snprintf(tmp, sizeof(tmp), "%s\"%s\": [%lld, %.6f]", first ? "" : ", ", kv.first.c_str(),
+               (long long)kv.second.first, kv.second.second);
+      js += tmp;
+      first = false;
+    }
+    js += "}";
+    if ((int64_t)js.size() + 1 > len) return fail(ISG_ERR_INVALID_ARG, "timing buffer too small");
+    memcpy(buf, js.c_str(), js.size() + 1);
+    return ISG_OK;
+  });
 }
 
 isg_status isg_motion_create(isg_plan* pl, const float* d, isg_motion** out) {
@@ -1203,6 +1308,7 @@ isg_status isg_warp_grad_d(isg_plan* pl, const isg_motion* d, const void* x, con
   if (d->plan != pl) return fail(ISG_ERR_INVALID_ARG, "motion belongs to another plan");
   return guarded(pl, [&]() {
     upsample(pl, (const float2*)x, pl->ugrid);
+    Tick tick(pl, "warp_grad");
     if (pl->ndim == 3)
       hipLaunchKernelGGL(warp_grad_kernel<3>, dim3(blocks_for(pl->N, kGridThreads)), dim3(kGridThreads), 0,
                          pl->stream, pl->ugrid, d->d, (const float2*)v, grad, pl->dims, pl->kb);
@@ -1289,6 +1395,7 @@ isg_status isg_cg_solve(isg_plan* pl, int P, const void* y, const isg_motion* co
     LAUNCH_OK();
     auto iteration = [&]() {
       op_normal(pl, P, pl->cg_p, lambda, d, (const float2*)S, k, pl->cg_q);
+      Tick tick(pl, "cg_vector");
       hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_q, N,
                          pl->cg_part);
       hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb,
@@ -1302,21 +1409,37 @@ isg_status isg_cg_solve(isg_plan* pl, int P, const void* y, const isg_motion* co
       LAUNCH_OK();
     };
     const char* ng = getenv("ISG_NO_GRAPH");
-    const bool use_graph = iters > 1 && pl->stream != nullptr && !(ng && atoi(ng));
+    const bool use_graph = iters > 1 && !(ng && atoi(ng));
+    // a graph cannot be captured on the null stream: run the solve on a
+    // plan-owned stream, ordered after the caller's work
+    hipStream_t caller = pl->stream;
+    if (use_graph && caller == nullptr) {
+      if (!pl->own_stream) HIP_OK(hipStreamCreateWithFlags(&pl->own_stream, hipStreamNonBlocking));
+      HIP_OK(hipStreamSynchronize(nullptr));
+      pl->stream = pl->own_stream;
+    }
+    struct Restore {
+      isg_plan* p;
+      hipStream_t s;
+      ~Restore() { p->stream = s; }
+    } restore{pl, caller};
     if (use_graph) {
       // make sure every lazily grown buffer exists before capture
       iteration();
       hipGraph_t graph = nullptr;
       hipGraphExec_t exec = nullptr;
       HIP_OK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
+      pl->capturing = true;
       try {
         iteration();
       } catch (...) {
+        pl->capturing = false;
         hipGraph_t g2 = nullptr;
         (void)hipStreamEndCapture(pl->stream, &g2);
         if (g2) (void)hipGraphDestroy(g2);
         throw;
       }
+      pl->capturing = false;
       HIP_OK(hipStreamEndCapture(pl->stream, &graph));
       HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
       for (int it = 1; it < iters; ++it) HIP_OK(hipGraphLaunch(exec, pl->stream));

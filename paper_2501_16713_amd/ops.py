@@ -138,6 +138,19 @@ class Plan:
         check(self.lib.isg_plan_device_bytes(self.handle, C.byref(b)))
         return b.value
 
+    def set_timing(self, enable: bool, prefix: str = "") -> None:
+        """Bracket kernel launches whose tag starts with `prefix` with HIP
+        events on the plan's stream (clears the totals)."""
+        self._sync_stream()
+        check(self.lib.isg_plan_set_timing(self.handle, int(enable), prefix.encode()))
+
+    def read_timing(self) -> dict:
+        """{tag: (launches, total_ms)} of the launches timed so far."""
+        import json
+        buf = C.create_string_buffer(1 << 16)
+        check(self.lib.isg_plan_read_timing(self.handle, buf, len(buf)))
+        return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
+
     def _sync_stream(self):
         check(self.lib.isg_plan_set_stream(self.handle, torch.cuda.current_stream(self.device).cuda_stream))
 
