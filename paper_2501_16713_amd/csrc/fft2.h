@@ -1,0 +1,364 @@
+// Two-step register FFT for lines of compile-time length L = L1 * L2.
+//
+// With n = L2 n1 + n2 and k = k1 + L1 k2 (Cooley-Tukey, decimation in time):
+//   X[k1 + L1 k2] = sum_n2 w_L^(n2 k1) w_L2^(n2 k2) sum_n1 x[L2 n1 + n2] w_L1^(n1 k1),
+// w_M = exp(s 2 pi i / M).  Step 1: every thread owns one (line, n2), loads
+// its L1 inputs straight from global memory into registers, does the L1-point
+// DFT in registers and applies the twiddle w_L^(n2 k1).  The tile is exchanged
+// once through LDS.  Step 2: every thread owns one (line, k1), does the
+// L2-point DFT in registers and stores straight to global memory.  Each
+// element crosses LDS once (one write, one read) and the stage structure is
+// fully unrolled at compile time.
+//
+// The in-register DFTs are mixed-radix (4, 2, 5, 3) decimation-in-time
+// recursions whose twiddles are compile-time constants, computed below from
+// the Taylor series of sin and cos in double precision.
+#pragma once
+
+#include "passes.h"
+
+namespace isg {
+
+// ---------------------------------------------------------------------------
+// compile-time cos / sin of 2 pi j / M
+// ---------------------------------------------------------------------------
+constexpr double kCePi = 3.14159265358979323846264338327950288;
+
+constexpr double ce_sin_series(double x) {  // |x| <= pi/4
+  double term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+
+constexpr double ce_cos_series(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+
+// returns cos (which = 0) or sin (which = 1) of 2 pi j / M, reducing the
+// angle to [0, pi/4] with exact integer comparisons on j / M
+constexpr double ce_trig(long j, long M, int which) {
+  j %= M;
+  if (j < 0) j += M;
+  double sgn_s = 1.0, sgn_c = 1.0;
+  if (2 * j > M) {  // theta in (pi, 2 pi): use 2 pi - theta
+    j = M - j;
+    sgn_s = -1.0;
+  }
+  bool swap = false;
+  long num = j, den = M;  // theta = 2 pi num / den in [0, pi]
+  if (4 * num > den) {    // theta in (pi/2, pi]: use pi - theta
+    num = den - 2 * num;  // theta' = pi - theta = 2 pi (den/2 - num)/den = pi (den - 2 num)/den
+    den = 2 * den;        // keep theta' = 2 pi num / den
+    sgn_c = -1.0;
+  }
+  if (8 * num > den) {  // theta in (pi/4, pi/2]: use pi/2 - theta
+    num = den - 4 * num;
+    den = 4 * den;
+    swap = true;
+  }
+  const double x = 2.0 * kCePi * (double)num / (double)den;
+  double c = ce_cos_series(x), s = ce_sin_series(x);
+  if (swap) {
+    const double t = c;
+    c = s;
+    s = t;
+  }
+  return which == 0 ? sgn_c * c : sgn_s * s;
+}
+
+template <int M>
+struct TwTable {
+  float c[M];
+  float s[M];
+  constexpr TwTable() : c(), s() {
+    for (int j = 0; j < M; ++j) {
+      c[j] = (float)ce_trig(j, M, 0);
+      s[j] = (float)ce_trig(j, M, 1);
+    }
+  }
+};
+
+template <int M>
+__device__ __forceinline__ float2 twiddle_ce(int jk, float sgn) {
+  constexpr TwTable<M> t{};
+  const int j = jk % M;
+  return make_float2(t.c[j], sgn * t.s[j]);
+}
+
+constexpr int first_radix(int M) {
+  return M % 4 == 0 ? 4 : M % 2 == 0 ? 2 : M % 5 == 0 ? 5 : M % 3 == 0 ? 3 : M;
+}
+
+// in-register DFT of compile-time length M with exponent sign S (-1 / +1)
+template <int M, int S>
+__device__ __forceinline__ void reg_dft(float2* v) {
+  if constexpr (M == 1) {
+    return;
+  } else if constexpr (M == 2 || M == 3 || M == 4 || M == 5) {
+    dft<M>(v, (float)S);
+  } else {
+    constexpr int R = first_radix(M);
+    constexpr int Q = M / R;
+    float2 sub[R][Q];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) sub[r][q] = v[R * q + r];
+#pragma unroll
+    for (int r = 0; r < R; ++r) reg_dft<Q, S>(sub[r]);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      float2 t[R];
+      t[0] = sub[0][k];
+#pragma unroll
+      for (int r = 1; r < R; ++r) t[r] = cmul(sub[r][k], twiddle_ce<M>(r * k, (float)S));
+      dft<R>(t, (float)S);
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[k + Q * m] = t[m];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tile geometry and thread mappings
+// ---------------------------------------------------------------------------
+enum Map2 { kBFast = 0, kJFast = 1 };  // which index varies fastest across lanes
+
+struct Tile2 {
+  int64_t A, B;     // outer count, inner extent
+  int na, nb;       // lines per tile: na outer x nb inner
+  int64_t tiles_b;  // ceil(B / nb)
+  int LS;           // LDS line stride (float2)
+};
+
+template <int MAP>
+__device__ __forceinline__ void decode(int t, int nb, int span, int& bl, int& idx, int& al) {
+  // span = L2 (step 1) or L1 (step 2)
+  if (MAP == kBFast) {
+    bl = t % nb;
+    const int r = t / nb;
+    idx = r % span;
+    al = r / span;
+  } else {
+    idx = t % span;
+    const int r = t / span;
+    bl = r % nb;
+    al = r / nb;
+  }
+}
+
+// LDS slot of element (k1, n2) of a line: rows of L2 + 1 to spread banks
+template <int L1, int L2>
+__device__ __forceinline__ int slot(int k1, int n2) {
+  return k1 * (L2 + 1) + n2;
+}
+
+// The kernel.  Ld: per-thread line setup + element loads at positions of the
+// L-point line (zeros outside the stored range); St: per-thread line setup +
+// element stores (positions outside a crop are skipped).  St may also request
+// an LDS epilogue (coil reduction) through St::kEpilogue.
+template <int L1, int L2, int S, int MAP1, int MAP2, class Ld, class St>
+__global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
+  constexpr int L = L1 * L2;
+  extern __shared__ float2 smem[];
+  float2* tw = smem;           // exp(-2 pi i q / L)
+  float2* lines = smem + L;
+  const int tid = threadIdx.x;
+  const int nthreads = blockDim.x;
+  for (int i = tid; i < L; i += nthreads) tw[i] = ld.tw[i];
+
+  const int64_t tile = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+  const int64_t ta = tile / g.tiles_b;
+  const int64_t a0 = ta * g.na;
+  const int64_t b0 = (tile - ta * g.tiles_b) * g.nb;
+  if (a0 >= g.A) return;
+  const int nl = g.na * g.nb;
+  __syncthreads();
+
+  // ---- step 1 ----
+  if (tid < nl * L2) {
+    int bl, n2, al;
+    decode<MAP1>(tid, g.nb, L2, bl, n2, al);
+    const int64_t a = a0 + al, b = b0 + bl;
+    const bool valid = a < g.A && b < g.B;
+    float2 v[L1];
+    auto line = ld.setup(a, b, valid);
+#pragma unroll
+    for (int n1 = 0; n1 < L1; ++n1) v[n1] = ld.template get<L>(line, L2 * n1 + n2, valid);
+    reg_dft<L1, S>(v);
+    float2* dst = lines + (al * g.nb + bl) * g.LS;
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) {
+      float2 w = tw[(n2 * k1) % L];
+      w.y *= -(float)S;  // conjugate the table entry for the inverse sign
+      dst[slot<L1, L2>(k1, n2)] = k1 == 0 ? v[0] : cmul(v[k1], w);
+    }
+  }
+  __syncthreads();
+
+  // ---- step 2 ----
+  const bool act2 = tid < nl * L1;
+  int bl2 = 0, k1 = 0, al2 = 0;
+  float2 u[L2];
+  if (act2) {
+    decode<MAP2>(tid, g.nb, L1, bl2, k1, al2);
+    const float2* src = lines + (al2 * g.nb + bl2) * g.LS;
+#pragma unroll
+    for (int n2 = 0; n2 < L2; ++n2) u[n2] = src[slot<L1, L2>(k1, n2)];
+    reg_dft<L2, S>(u);
+  }
+  if constexpr (St::kEpilogue) {
+    // results go back to LDS in natural order for a cross-line epilogue
+    __syncthreads();
+    if (act2) {
+      float2* dstl = lines + (al2 * g.nb + bl2) * g.LS;
+#pragma unroll
+      for (int k2 = 0; k2 < L2; ++k2) dstl[k1 + L1 * k2] = u[k2];
+    }
+    __syncthreads();
+    st.epilogue(lines, g, a0, b0);
+  } else {
+    if (act2) {
+      const int64_t a = a0 + al2, b = b0 + bl2;
+      const bool valid = a < g.A && b < g.B;
+      auto line = st.setup(a, b, valid);
+#pragma unroll
+      for (int k2 = 0; k2 < L2; ++k2) st.template put<L>(line, k1 + L1 * k2, u[k2], valid);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// element maps of a line of length L holding n = L/2 stored values
+// ---------------------------------------------------------------------------
+// stored index of position p, or -1 in the zero gap
+template <int L>
+__device__ __forceinline__ int pad_src(int map, int p) {
+  constexpr int n = L / 2;
+  if (map == kCentred) return p < n / 2 ? p + n / 2 : (p >= L - n / 2 ? p - (L - n / 2) : -1);
+  if (map == kSpectral) return p < n / 2 ? p : (p >= L - n / 2 ? p - (L - n) : -1);
+  return p;
+}
+
+// strided load of element p of line (a, b): p[a*sa + j*sj + b]; map: dense,
+// or zero-pad of L/2 stored values (centred or spectral)
+template <int S>
+struct Ld2Strided {
+  const typename Elem<S>::T* p;
+  int64_t sa, sj;
+  int map;
+  const float2* tw;
+  struct Line {
+    const typename Elem<S>::T* base;
+  };
+  __device__ Line setup(int64_t a, int64_t b, bool) const { return Line{p + a * sa + b}; }
+  template <int L>
+  __device__ float2 get(const Line& ln, int pos, bool valid) const {
+    const int j = pad_src<L>(map, pos);
+    if (!valid || j < 0) return make_float2(0.f, 0.f);
+    return Elem<S>::load(ln.base + (int64_t)j * sj);
+  }
+};
+
+template <int S>
+struct St2Strided {
+  static constexpr bool kEpilogue = false;
+  typename Elem<S>::T* p;
+  int64_t sa, sj;
+  int map;  // dense, or crop to L/2 values (centred or spectral)
+  struct Line {
+    typename Elem<S>::T* base;
+  };
+  __device__ Line setup(int64_t a, int64_t b, bool) const { return Line{p + a * sa + b}; }
+  template <int L>
+  __device__ void put(const Line& ln, int pos, float2 v, bool valid) const {
+    const int j = pad_src<L>(map, pos);
+    if (valid && j >= 0) Elem<S>::store(ln.base + (int64_t)j * sj, v);
+  }
+};
+
+// first pass of inverse k-space gridding: S_c . m / c(x/G) |N|^{-1/2},
+// zero-padded (centred) along the last axis; lines are (a, c)
+struct Ld2CoilExpand {
+  const float2* m;
+  const float2* S;
+  AxisTabs dx;
+  float scale;
+  int64_t N;
+  int n;    // stored length (L/2)
+  int n1;   // axis-1 extent in 3D, 0 in 2D
+  const float2* tw;
+  struct Line {
+    const float2* mrow;
+    const float2* srow;
+    float f;
+  };
+  __device__ Line setup(int64_t a, int64_t c, bool valid) const {
+    Line ln{m, S, 0.f};
+    if (!valid) return ln;
+    float f = scale;
+    if (n1) {
+      const int i0 = (int)(a / n1), i1 = (int)(a - (int64_t)i0 * n1);
+      f *= dx.t[0][i0] * dx.t[1][i1];
+    } else {
+      f *= dx.t[0][a];
+    }
+    ln.mrow = m + a * n;
+    ln.srow = S + c * N + a * n;
+    ln.f = f;
+    return ln;
+  }
+  template <int L>
+  __device__ float2 get(const Line& ln, int pos, bool valid) const {
+    const int j = pad_src<L>(kCentred, pos);
+    if (!valid || j < 0) return make_float2(0.f, 0.f);
+    const float* dl = dx.t[n1 ? 2 : 1];
+    return cscale(cmul(ln.srow[j], ln.mrow[j]), ln.f * dl[j]);
+  }
+};
+
+// last pass of k-space gridding: crop (centred) along the last axis, times
+// 1/c(x/G) |N|^{-1/2}, times conj(S_c), summed over the coils of the tile
+struct St2CoilReduce {
+  static constexpr bool kEpilogue = true;
+  float2* out;
+  const float2* S;
+  AxisTabs dx;
+  float scale;
+  int64_t N;
+  int n, L, C;
+  int n1;
+  struct Line {};
+  __device__ void epilogue(const float2* lines, const Tile2& g, int64_t a0, int64_t) const {
+    const int total = g.na * n;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int al = e / n;
+      const int j = e - al * n;
+      const int64_t a = a0 + al;
+      if (a >= g.A) continue;
+      float f = scale * dx.t[n1 ? 2 : 1][j];
+      if (n1) {
+        const int i0 = (int)(a / n1), i1 = (int)(a - (int64_t)i0 * n1);
+        f *= dx.t[0][i0] * dx.t[1][i1];
+      } else {
+        f *= dx.t[0][a];
+      }
+      const int64_t off = a * n + j;
+      const int pos = j < n / 2 ? j + L - n / 2 : j - n / 2;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int c = 0; c < C; ++c)
+        acc = cadd(acc, cmulc(S[(int64_t)c * N + off], lines[(al * C + c) * g.LS + pos]));
+      out[off] = cscale(acc, f);
+    }
+  }
+};
+
+}  // namespace isg

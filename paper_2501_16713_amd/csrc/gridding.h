@@ -205,16 +205,33 @@ struct WarpSpreadPhases {
   const float2* w[kMaxPhasesPerLaunch];      // values to spread, [N]
 };
 
+// Image-space spread tile; LDS holds a re plane and an im plane of P floats,
+// point (l0, l1, l2) at l0 * S0 + l1 * S1 + l2 (padded strides spread banks).
 struct TileDims {
   int TS[3];      // tile extent per axis
   int nt[3];      // tiles per axis
+  int S0, S1;     // plane strides
+  int P;          // plane size (floats)
 };
+
+// Image-space spread of one tile, without atomics.  Entries (state, voxel)
+// of the tile, over all states, are cut into batches of 64; wave w takes
+// batches w, w + 4, ...: the 64 lanes stage one entry each (tap offsets
+// relative to the tile, weights, value) in the wave's LDS staging area, then
+// walk the staged entries with one lane per tap.  The 64 taps of an entry
+// are 64 distinct points and each wave accumulates into its own LDS copy of
+// the tile, so plain read-modify-write is race free; the copies are summed
+// at the end (fixed order: deterministic).
+constexpr int kWarpWaves = kGridThreads / 64;
 
 template <int NDIM>
 __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPhases ph, float2* __restrict__ U,
                                                                    int accumulate, Dims dm, TileDims td,
                                                                    KbPoly kb) {
-  extern __shared__ float2 acc[];
+  extern __shared__ float accw[];  // [kWarpWaves][2][P]
+  __shared__ int st_off[kWarpWaves][64][3];
+  __shared__ float st_w[kWarpWaves][64][3][4];
+  __shared__ float2 st_v[kWarpWaves][64];
   const int tile = blockIdx.x;
   int tc[3] = {0, 0, 0};
   {
@@ -224,7 +241,7 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
       t /= td.nt[i];
     }
   }
-  int lo[3], ext[3];
+  int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
   int vol = 1;
 #pragma unroll
   for (int i = 0; i < NDIM; ++i) {
@@ -232,15 +249,33 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
     ext[i] = min(td.TS[i], dm.G[i] - lo[i]);
     vol *= td.TS[i];
   }
-  for (int e = threadIdx.x; e < vol; e += kGridThreads) acc[e] = make_float2(0.f, 0.f);
-  __syncthreads();
-  for (int p = 0; p < ph.P; ++p) {
-    const int beg = ph.tile_off[p][tile], end = ph.tile_off[p][tile + 1];
-    const int* vox = ph.vox[p];
-    const float* d = ph.d[p];
-    const float2* w = ph.w[p];
-    for (int e = beg + threadIdx.x; e < end; e += kGridThreads) {
-      const int64_t r = vox[e];
+  for (int e = threadIdx.x; e < kWarpWaves * 2 * td.P; e += kGridThreads) accw[e] = 0.f;
+  // entries of this tile over all states, concatenated
+  int E = 0;
+  for (int p = 0; p < ph.P; ++p) E += ph.tile_off[p][tile + 1] - ph.tile_off[p][tile];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  float* are = accw + wave * 2 * td.P;
+  float* aim = are + td.P;
+  int tt[3];
+  tt[NDIM - 1] = lane & 3;
+  tt[NDIM - 2] = (lane >> 2) & 3;
+  if (NDIM == 3) tt[0] = lane >> 4;
+  const bool tap_lane = NDIM == 3 || lane < 16;
+  const int nbatch = (E + 63) / 64;
+  const int rounds = (nbatch + kWarpWaves - 1) / kWarpWaves;
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int b = rd * kWarpWaves + wave;
+    const int e0 = b * 64;
+    const int ne = max(0, min(64, E - e0));
+    __syncthreads();
+    if (lane < ne) {  // stage entry e0 + lane
+      int e = e0 + lane, p = 0;
+      while (e >= ph.tile_off[p][tile + 1] - ph.tile_off[p][tile]) {
+        e -= ph.tile_off[p][tile + 1] - ph.tile_off[p][tile];
+        ++p;
+      }
+      const int64_t r = ph.vox[p][ph.tile_off[p][tile] + e];
       int ri[3];
       {
         int64_t t = r;
@@ -249,61 +284,45 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
           t /= dm.n[i];
         }
       }
-      const float2 val = w[r];
-      int loc[NDIM][4];
-      float wt[NDIM][4];
 #pragma unroll
       for (int i = 0; i < NDIM; ++i) {
-        const float y = 2.0f * d[(int64_t)i * dm.N + r];
-        const float fl = floorf(y);
-        kb_weights(kb, y - fl, wt[i]);
-        const int b = wrap(2 * ri[i] + (int)fl - 1, dm.G[i]);
+        const float yv = 2.0f * ph.d[p][(int64_t)i * dm.N + r];
+        const float fl = floorf(yv);
+        float w[4];
+        kb_weights(kb, yv - fl, w);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          int g = b + t;
-          if (g >= dm.G[i]) g -= dm.G[i];
-          const int l = g - lo[i];
-          loc[i][t] = (l >= 0 && l < ext[i]) ? l : -1;
-        }
+        for (int t = 0; t < 4; ++t) st_w[wave][lane][i][t] = w[t];
+        int o = wrap(2 * ri[i] + (int)fl - 1, dm.G[i]) - lo[i];  // nearest periodic image
+        if (o > dm.G[i] / 2) o -= dm.G[i];
+        if (o < -dm.G[i] / 2) o += dm.G[i];
+        st_off[wave][lane][i] = o;
       }
-      if constexpr (NDIM == 3) {
+      st_v[wave][lane] = ph.w[p][r];
+    }
+    __syncthreads();
+    if (tap_lane) {
+      for (int s = 0; s < ne; ++s) {
+        bool ok = true;
+        float ww = 1.0f;
+        int idx = 0;
 #pragma unroll
-        for (int t0 = 0; t0 < 4; ++t0) {
-          if (loc[0][t0] < 0) continue;
-#pragma unroll
-          for (int t1 = 0; t1 < 4; ++t1) {
-            if (loc[1][t1] < 0) continue;
-            const float w01 = wt[0][t0] * wt[1][t1];
-            const int rowi = (loc[0][t0] * td.TS[1] + loc[1][t1]) * td.TS[2];
-#pragma unroll
-            for (int t2 = 0; t2 < 4; ++t2) {
-              if (loc[2][t2] < 0) continue;
-              const float ww = w01 * wt[2][t2];
-              float2* a = acc + rowi + loc[2][t2];
-              atomicAdd(&a->x, ww * val.x);
-              atomicAdd(&a->y, ww * val.y);
-            }
-          }
+        for (int i = 0; i < NDIM; ++i) {
+          const int l = st_off[wave][s][i] + tt[i];
+          ok = ok && l >= 0 && l < ext[i];
+          ww *= st_w[wave][s][i][tt[i]];
+          // 3D: l0 S0 + l1 S1 + l2; 2D: l0 S0 + l1
+          idx += l * (i == NDIM - 1 ? 1 : (i == 0 ? td.S0 : td.S1));
         }
-      } else {
-#pragma unroll
-        for (int t0 = 0; t0 < 4; ++t0) {
-          if (loc[0][t0] < 0) continue;
-#pragma unroll
-          for (int t1 = 0; t1 < 4; ++t1) {
-            if (loc[1][t1] < 0) continue;
-            const float ww = wt[0][t0] * wt[1][t1];
-            float2* a = acc + loc[0][t0] * td.TS[1] + loc[1][t1];
-            atomicAdd(&a->x, ww * val.x);
-            atomicAdd(&a->y, ww * val.y);
-          }
+        if (ok) {
+          const float2 v = st_v[wave][s];
+          are[idx] += ww * v.x;
+          aim[idx] += ww * v.y;
         }
       }
     }
   }
   __syncthreads();
-  // write the tile: rows along the last axis are contiguous in U
-  const int last = NDIM - 1;
+  // sum the per-wave copies and write the tile: rows along the last axis are contiguous in U
   for (int e = threadIdx.x; e < vol; e += kGridThreads) {
     int l[3] = {0, 0, 0};
     int t = e;
@@ -316,8 +335,13 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
     if (!ok) continue;
     int64_t gi = 0;
     for (int i = 0; i < NDIM; ++i) gi = gi * dm.G[i] + lo[i] + l[i];
-    (void)last;
-    float2 v = acc[e];
+    const int pi = NDIM == 3 ? l[0] * td.S0 + l[1] * td.S1 + l[2] : l[0] * td.S0 + l[1];
+    float2 v = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int w = 0; w < kWarpWaves; ++w) {
+      v.x += accw[w * 2 * td.P + pi];
+      v.y += accw[w * 2 * td.P + td.P + pi];
+    }
     if (accumulate) v = cadd(v, U[gi]);
     U[gi] = v;
   }
@@ -332,14 +356,22 @@ struct KTap {
   uint32_t base;  // b0 | b1 << 10 | b2 << 20
 };
 
-// y[j][c] = sum_taps prod_i c(kappa_ji - q_i) grid[q][c], grid [G...][C]
+// y[j][c] = sum_taps prod_i c(kappa_ji - q_i) grid[q][c], grid [G...][C].
+// Lane mapping: each wavefront holds spw = 64 / C samples and lane (s, c)
+// interpolates coil c of sample s, so the C coil values of every tap are one
+// contiguous run per sample and the output row y[j][*] is one coalesced store.
 template <int NDIM, int S>
 __global__ __launch_bounds__(kGridThreads) void kgather_kernel(const typename Elem<S>::T* __restrict__ grid,
                                                                const KTap* __restrict__ taps, int64_t M,
                                                                float2* __restrict__ y, int C, Dims dm,
                                                                KbPoly kb) {
-  const int64_t j = (int64_t)blockIdx.x * kGridThreads + threadIdx.x;
-  if (j >= M) return;
+  const int lane = threadIdx.x & 63;
+  const int spw = 64 / C;
+  const int sub = lane / C;
+  const int c = lane - sub * C;
+  const int64_t wave = (int64_t)blockIdx.x * (kGridThreads / 64) + (threadIdx.x >> 6);
+  const int64_t j = wave * spw + sub;
+  if (sub >= spw || j >= M) return;
   const KTap tp = taps[j];
   float w[NDIM][4];
   int g[NDIM][4];
@@ -350,55 +382,41 @@ __global__ __launch_bounds__(kGridThreads) void kgather_kernel(const typename El
 #pragma unroll
     for (int t = 0; t < 4; ++t) g[i][t] = b + t >= dm.G[i] ? b + t - dm.G[i] : b + t;
   }
-  constexpr int CC = 4;
-  for (int c0 = 0; c0 < C; c0 += CC) {
-    float2 acc[CC];
+  float2 acc = make_float2(0.f, 0.f);
+  if constexpr (NDIM == 3) {
 #pragma unroll
-    for (int c = 0; c < CC; ++c) acc[c] = make_float2(0.f, 0.f);
-    if constexpr (NDIM == 3) {
+    for (int t0 = 0; t0 < 4; ++t0) {
 #pragma unroll
-      for (int t0 = 0; t0 < 4; ++t0) {
+      for (int t1 = 0; t1 < 4; ++t1) {
+        const float w01 = w[0][t0] * w[1][t1];
+        const typename Elem<S>::T* row = grid + ((int64_t)g[0][t0] * dm.G[1] + g[1][t1]) * dm.G[2] * C + c;
+        float2 s = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int t1 = 0; t1 < 4; ++t1) {
-          const float w01 = w[0][t0] * w[1][t1];
-          const int64_t row = ((int64_t)g[0][t0] * dm.G[1] + g[1][t1]) * dm.G[2];
-#pragma unroll
-          for (int t2 = 0; t2 < 4; ++t2) {
-            const float ww = w01 * w[2][t2];
-            const typename Elem<S>::T* p = grid + (row + g[2][t2]) * C + c0;
-#pragma unroll
-            for (int c = 0; c < CC; ++c) {
-              if (c0 + c < C) {
-                const float2 v = Elem<S>::load(p + c);
-                acc[c].x = fmaf(ww, v.x, acc[c].x);
-                acc[c].y = fmaf(ww, v.y, acc[c].y);
-              }
-            }
-          }
+        for (int t2 = 0; t2 < 4; ++t2) {
+          const float2 v = Elem<S>::load(row + (int64_t)g[2][t2] * C);
+          s.x = fmaf(w[2][t2], v.x, s.x);
+          s.y = fmaf(w[2][t2], v.y, s.y);
         }
-      }
-    } else {
-#pragma unroll
-      for (int t0 = 0; t0 < 4; ++t0) {
-#pragma unroll
-        for (int t1 = 0; t1 < 4; ++t1) {
-          const float ww = w[0][t0] * w[1][t1];
-          const typename Elem<S>::T* p = grid + ((int64_t)g[0][t0] * dm.G[1] + g[1][t1]) * C + c0;
-#pragma unroll
-          for (int c = 0; c < CC; ++c) {
-            if (c0 + c < C) {
-              const float2 v = Elem<S>::load(p + c);
-              acc[c].x = fmaf(ww, v.x, acc[c].x);
-              acc[c].y = fmaf(ww, v.y, acc[c].y);
-            }
-          }
-        }
+        acc.x = fmaf(w01, s.x, acc.x);
+        acc.y = fmaf(w01, s.y, acc.y);
       }
     }
+  } else {
 #pragma unroll
-    for (int c = 0; c < CC; ++c)
-      if (c0 + c < C) y[j * C + c0 + c] = acc[c];
+    for (int t0 = 0; t0 < 4; ++t0) {
+      const typename Elem<S>::T* row = grid + (int64_t)g[0][t0] * dm.G[1] * C + c;
+      float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int t1 = 0; t1 < 4; ++t1) {
+        const float2 v = Elem<S>::load(row + (int64_t)g[1][t1] * C);
+        s.x = fmaf(w[1][t1], v.x, s.x);
+        s.y = fmaf(w[1][t1], v.y, s.y);
+      }
+      acc.x = fmaf(w[0][t0], s.x, acc.x);
+      acc.y = fmaf(w[0][t0], s.y, acc.y);
+    }
   }
+  y[j * C + c] = acc;
 }
 
 // k-space spread work unit: `count` samples of tile `tile` starting at
@@ -409,10 +427,16 @@ struct KUnit {
   int tile, start, count, slot;
 };
 
+// Tile of the k-space spread.  The LDS accumulator is planar, one plane of
+// P floats per (coil, re/im); inside a plane the point (l0, l1, l2) sits at
+// l0 * S0 + l1 * S1 + l2.  S1 = T2 and S0 = 4 (mod 32) spread the 64 taps of
+// a sample over distinct banks, and P = 1 (mod 16) staggers the coil planes.
 struct KTile {
   int TS[3];
   int nt[3];
   int vol;        // points per tile
+  int S0, S1;     // plane strides
+  int P;          // plane size (floats)
 };
 
 __device__ __forceinline__ void ktile_origin(int tile, const KTile& kt, int ndim, int lo[3]) {
@@ -423,7 +447,34 @@ __device__ __forceinline__ void ktile_origin(int tile, const KTile& kt, int ndim
   }
 }
 
-// one wavefront per sample and one lane per tap; C coil values per lane
+template <int NDIM>
+__device__ __forceinline__ int kplane_index(const KTile& kt, int pt) {
+  // point index (row-major over TS) -> planar index
+  if constexpr (NDIM == 3) {
+    const int l2 = pt % kt.TS[2];
+    const int r = pt / kt.TS[2];
+    const int l1 = r % kt.TS[1];
+    const int l0 = r / kt.TS[1];
+    return l0 * kt.S0 + l1 * kt.S1 + l2;
+  } else {
+    const int l1 = pt % kt.TS[1];
+    const int l0 = pt / kt.TS[1];
+    return l0 * kt.S0 + l1;
+  }
+}
+
+// Staged sample of a k-space spread batch: offsets of tap 0 relative to the
+// tile origin (tap t of axis i lands on tile row off[i] + t), and the tap
+// weights of every axis.
+constexpr int kSpreadBatch = 64;
+
+// k-space spread of one work unit, without atomics.  The unit's samples are
+// staged in LDS in batches of kSpreadBatch (tap offsets, weights, the C coil
+// values).  Wave w of the workgroup owns the tile planes
+// l0 in [w T0/4, (w+1) T0/4) and walks every staged sample, adding the taps
+// that land in its planes; within one (t0, t1) step its lanes cover distinct
+// (t1, t2, coil) points, so plain LDS read-modify-write is race free and the
+// summation order is fixed (the spread is deterministic).
 template <int NDIM, int S>
 __global__ __launch_bounds__(kGridThreads) void kspread_kernel(const KUnit* __restrict__ units,
                                                                const int* __restrict__ order,
@@ -432,60 +483,114 @@ __global__ __launch_bounds__(kGridThreads) void kspread_kernel(const KUnit* __re
                                                                typename Elem<S>::T* __restrict__ grid,
                                                                float2* __restrict__ partial, Dims dm,
                                                                KTile kt, KbPoly kb) {
-  extern __shared__ float2 acc[];  // [vol][C]
+  extern __shared__ float accf[];  // [C][2][P] accumulator, then the staging area
+  __shared__ int st_j[kSpreadBatch];
+  __shared__ int st_off[kSpreadBatch][3];
+  __shared__ float st_w[kSpreadBatch][3][4];
+  float2* st_y = (float2*)(accf + (size_t)C * 2 * kt.P);  // [kSpreadBatch][C]
   const KUnit un = units[blockIdx.x];
   int lo[3] = {0, 0, 0};
   ktile_origin(un.tile, kt, NDIM, lo);
-  const int volC = kt.vol * C;
-  for (int e = threadIdx.x; e < volC; e += kGridThreads) acc[e] = make_float2(0.f, 0.f);
-  __syncthreads();
-  constexpr int TAPS = NDIM == 3 ? 64 : 16;
-  constexpr int SPW = 64 / TAPS;  // samples per wavefront
+  const int nacc = C * 2 * kt.P;
+  for (int e = threadIdx.x; e < nacc; e += kGridThreads) accf[e] = 0.f;
+
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int sub = lane / TAPS;
-  const int tap = lane - sub * TAPS;
-  int tt[3];
-  tt[NDIM - 1] = tap & 3;
-  tt[NDIM >= 2 ? NDIM - 2 : 0] = (tap >> 2) & 3;
-  if constexpr (NDIM == 3) tt[0] = tap >> 4;
-  for (int s = wave * SPW + sub; s < un.count; s += (kGridThreads / 64) * SPW) {
-    const int j = order[un.start + s];
-    const KTap tp = taps[j];
-    bool inside = true;
-    float ww = 1.0f;
-    int li = 0;
+  constexpr int NW = kGridThreads / 64;
+  // plane slab of this wave
+  const int per = (kt.TS[0] + NW - 1) / NW;
+  const int slab_lo = wave * per, slab_hi = min(kt.TS[0], slab_lo + per);
+  // lane -> (t1 group member, t2, coil of a chunk of CC <= 16); coil fastest
+  const int CC = min(C, 16);
+  const int cl = lane % CC;
+  const int t2 = (lane / CC) & 3;
+  const int t1s = lane / (4 * CC);                    // which t1 of a round
+  const int t1n = min(4, 64 / (4 * CC));              // t1 values per round (1, 2 or 4)
+  const int t1r = (4 + t1n - 1) / t1n;                // rounds over t1
+  const bool lane_ok = lane < CC * 4 * t1n;
+
+  for (int b0 = 0; b0 < un.count; b0 += kSpreadBatch) {
+    const int nb = min(kSpreadBatch, un.count - b0);
+    __syncthreads();  // previous batch fully consumed (and accumulator zeroed)
+    if (threadIdx.x < nb) {
+      const int j = order[un.start + b0 + threadIdx.x];
+      const KTap tp = taps[j];
+      st_j[threadIdx.x] = j;
 #pragma unroll
-    for (int i = 0; i < NDIM; ++i) {
-      const float f = tp.f[i];
-      const int m = tt[i];
-      // t_m = ((1 + m) - f)((3 - m) + f)/4, the same float operations as
-      // kb_weights; the m = 3 tap is 0 when f == 0
-      const float t = ((float)(1 + m) - f) * ((float)(3 - m) + f) * 0.25f;
-      const float wi = (m == 3 && !(f > 0.0f)) ? 0.0f : kb_poly(kb, t);
-      ww *= wi;
-      int g = (int)((tp.base >> (10 * i)) & 1023) + m;
-      if (g >= dm.G[i]) g -= dm.G[i];
-      const int l = g - lo[i];
-      inside = inside && l >= 0 && l < kt.TS[i] && g < dm.G[i];
-      li = li * kt.TS[i] + l;
+      for (int i = 0; i < NDIM; ++i) {
+        float w[4];
+        kb_weights(kb, tp.f[i], w);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) st_w[threadIdx.x][i][t] = w[t];
+        int o = (int)((tp.base >> (10 * i)) & 1023) - lo[i];  // periodic: pick the image next to the tile
+        if (o > dm.G[i] / 2) o -= dm.G[i];
+        if (o < -dm.G[i] / 2) o += dm.G[i];
+        st_off[threadIdx.x][i] = o;
+      }
     }
-    if (!inside) continue;
-    const float2* yj = y + (int64_t)j * C;
-    float2* a = acc + (int64_t)li * C;
-    for (int c = 0; c < C; ++c) {
-      const float2 v = yj[c];
-      atomicAdd(&a[c].x, ww * v.x);
-      atomicAdd(&a[c].y, ww * v.y);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * C; e += kGridThreads) {
+      const int s = e / C;
+      st_y[e] = y[(int64_t)st_j[s] * C + (e - s * C)];
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < C; c0 += CC) {
+      const int c = c0 + cl;
+      if (!lane_ok || c >= C) continue;
+      float* pre = accf + (2 * c) * kt.P;
+      float* pim = pre + kt.P;
+      for (int s = 0; s < nb; ++s) {
+        const int o0 = st_off[s][0];
+        if (o0 + 3 < slab_lo || o0 >= slab_hi) continue;  // uniform across the wave
+        const float2 yv = st_y[s * C + c];
+        if constexpr (NDIM == 3) {
+          const int o1 = st_off[s][1], l2 = st_off[s][2] + t2;
+          const bool ok2 = l2 >= 0 && l2 < kt.TS[2];
+          const float w2 = st_w[s][2][t2];
+#pragma unroll
+          for (int t0 = 0; t0 < 4; ++t0) {
+            const int l0 = o0 + t0;
+            if (l0 < slab_lo || l0 >= slab_hi) continue;
+            const float w02 = st_w[s][0][t0] * w2;
+            for (int r = 0; r < t1r; ++r) {
+              const int t1 = r * t1n + t1s;
+              const int l1 = o1 + t1;
+              if (t1 < 4 && ok2 && l1 >= 0 && l1 < kt.TS[1]) {
+                const float ww = w02 * st_w[s][1][t1];
+                const int idx = l0 * kt.S0 + l1 * kt.S1 + l2;
+                pre[idx] += ww * yv.x;
+                pim[idx] += ww * yv.y;
+              }
+            }
+          }
+        } else {
+          // 2D: lanes cover (t1, coil); rows t0 within the slab
+          const int l1 = st_off[s][1] + t2;
+          const bool ok1 = l1 >= 0 && l1 < kt.TS[1];
+          const float w1 = st_w[s][1][t2];
+#pragma unroll
+          for (int t0 = 0; t0 < 4; ++t0) {
+            const int l0 = o0 + t0;
+            if (l0 < slab_lo || l0 >= slab_hi || t1s != 0 || !ok1) continue;
+            const float ww = st_w[s][0][t0] * w1;
+            const int idx = l0 * kt.S0 + l1;
+            pre[idx] += ww * yv.x;
+            pim[idx] += ww * yv.y;
+          }
+        }
+      }
     }
   }
   __syncthreads();
   // write out: rows along the last axis are TS*C contiguous values
+  const int volC = kt.vol * C;
   for (int e = threadIdx.x; e < volC; e += kGridThreads) {
     const int pt = e / C;
-    const int c = e - pt * C;
+    const int cc = e - pt * C;
+    const int pi = kplane_index<NDIM>(kt, pt);
+    const float2 v = make_float2(accf[(2 * cc) * kt.P + pi], accf[(2 * cc + 1) * kt.P + pi]);
     if (un.slot >= 0) {
-      partial[(int64_t)un.slot * volC + e] = acc[e];
+      partial[(int64_t)un.slot * volC + e] = v;
       continue;
     }
     int l[3] = {0, 0, 0};
@@ -501,7 +606,7 @@ __global__ __launch_bounds__(kGridThreads) void kspread_kernel(const KUnit* __re
       ok = ok && g < dm.G[i];
       gi = gi * dm.G[i] + g;
     }
-    if (ok) Elem<S>::store(grid + gi * C + c, acc[e]);
+    if (ok) Elem<S>::store(grid + gi * C + cc, v);
   }
 }
 

@@ -16,6 +16,7 @@
 #include "../../include/isg.h"
 #include "common.h"
 #include "fft.h"
+#include "fft2.h"
 #include "gridding.h"
 #include "passes.h"
 #include "solver.h"
@@ -359,6 +360,108 @@ static void run_pass(isg_plan* pl, const char* tag, const Ld& ld, const Mid& mid
   LAUNCH_OK();
 }
 
+// ---------------------------------------------------------------------------
+// two-step register FFT passes (compile-time lengths)
+// ---------------------------------------------------------------------------
+static bool fft2_supported(int L) {
+  switch (L) {
+    case 32: case 40: case 48: case 64: case 80: case 96: case 128:
+    case 160: case 192: case 256: case 320: case 512: return true;
+    default: return false;
+  }
+}
+
+static Tile2 make_tile2(int64_t A, int64_t B, int L, int nb_fixed) {
+  int L1 = 4, L2 = 8;
+  switch (L) {
+    case 32: L1 = 4; L2 = 8; break;
+    case 40: L1 = 5; L2 = 8; break;
+    case 48: L1 = 6; L2 = 8; break;
+    case 64: L1 = 8; L2 = 8; break;
+    case 80: L1 = 8; L2 = 10; break;
+    case 96: L1 = 8; L2 = 12; break;
+    case 128: L1 = 8; L2 = 16; break;
+    case 160: L1 = 10; L2 = 16; break;
+    case 192: L1 = 12; L2 = 16; break;
+    case 256: L1 = 16; L2 = 16; break;
+    case 320: L1 = 16; L2 = 20; break;
+    case 512: L1 = 16; L2 = 32; break;
+  }
+  Tile2 g;
+  g.A = A;
+  g.B = B;
+  if (nb_fixed > 0) {
+    g.nb = nb_fixed;
+    g.na = (int)std::max<int64_t>(1, std::min<int64_t>(A, 512 / (nb_fixed * L2)));
+  } else {
+    g.nb = (int)std::min<int64_t>(B, 16);
+    g.na = 1;
+  }
+  g.tiles_b = (B + g.nb - 1) / g.nb;
+  int LS = L1 * (L2 + 1);
+  if (!(LS & 1)) LS += 1;
+  g.LS = LS;
+  return g;
+}
+
+template <int L1, int L2, int SG, int M1, int M2, class Ld, class St>
+static void launch_fft2(isg_plan* pl, const char* tag, const Ld& ld, const St& st, const Tile2& g) {
+  constexpr int L = L1 * L2;
+  const int nl = g.na * g.nb;
+  const int threads = ((nl * L2 + 63) / 64) * 64;
+  if (threads > 512 || nl * L1 > threads)
+    throw HipError{hipErrorInvalidConfiguration, "fft2 tile does not fit one workgroup"};
+  const size_t lds = sizeof(float2) * ((size_t)L + (size_t)nl * g.LS);
+  auto kern = fft2_kernel<L1, L2, SG, M1, M2, Ld, St>;
+  allow_lds(kern, lds);
+  const int64_t tiles = ((g.A + g.na - 1) / g.na) * g.tiles_b;
+  const int64_t gx = std::min<int64_t>(tiles, 1 << 30);
+  const int64_t gy = (tiles + gx - 1) / gx;
+  Tick tick(pl, tag);
+  hipLaunchKernelGGL(kern, dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, pl->stream, ld, st, g);
+  LAUNCH_OK();
+}
+
+template <int SG, int M1, int M2, class Ld, class St>
+static void run_fft2(isg_plan* pl, const char* tag, int L, const Ld& ld, const St& st, const Tile2& g) {
+  switch (L) {
+    case 32: launch_fft2<4, 8, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 40: launch_fft2<5, 8, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 48: launch_fft2<6, 8, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 64: launch_fft2<8, 8, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 80: launch_fft2<8, 10, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 96: launch_fft2<8, 12, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 128: launch_fft2<8, 16, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 160: launch_fft2<10, 16, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 192: launch_fft2<12, 16, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 256: launch_fft2<16, 16, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 320: launch_fft2<16, 20, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 512: launch_fft2<16, 32, SG, M1, M2>(pl, tag, ld, st, g); break;
+    default: throw HipError{hipErrorInvalidValue, "fft2: unsupported length"};
+  }
+}
+
+template <int S>
+static Ld2Strided<S> ld2(const isg_plan* pl, const void* p, int64_t sa, int64_t sj, int map, int L) {
+  Ld2Strided<S> l;
+  l.p = (const typename Elem<S>::T*)p;
+  l.sa = sa;
+  l.sj = sj;
+  l.map = map;
+  l.tw = pl->lines.at(L).tw;
+  return l;
+}
+
+template <int S>
+static St2Strided<S> st2(void* p, int64_t sa, int64_t sj, int map) {
+  St2Strided<S> s;
+  s.p = (typename Elem<S>::T*)p;
+  s.sa = sa;
+  s.sj = sj;
+  s.map = map;
+  return s;
+}
+
 template <int S>
 static LdStrided<S> ld_strided(const void* p, int64_t sa, int64_t sj, int n, int L, int map, const TileGeom& g) {
   LdStrided<S> l;
@@ -544,7 +647,7 @@ static int warp_ntiles(const isg_plan* pl) {
 
 // U = sum_p P_{d_p} w_p over the given states
 static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const float2* const* w, float2* U) {
-  const size_t lds = sizeof(float2) * (size_t)pl->wtile.TS[0] * pl->wtile.TS[1] * pl->wtile.TS[2];
+  const size_t lds = sizeof(float) * 2 * (size_t)pl->wtile.P * kWarpWaves;
   for (int p0 = 0; p0 < P; p0 += kMaxPhasesPerLaunch) {
     WarpSpreadPhases ph;
     memset(&ph, 0, sizeof(ph));
@@ -570,13 +673,60 @@ static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const 
 // ---------------------------------------------------------------------------
 // coil-expanded k-space front end and back end
 // ---------------------------------------------------------------------------
+static Ld2CoilExpand ld2_expand(isg_plan* pl, const float2* m, const float2* Sm, int n, int n1, int L) {
+  Ld2CoilExpand ld;
+  ld.m = m;
+  ld.S = Sm;
+  ld.dx = tabs(pl->dx);
+  ld.scale = (float)(1.0 / std::sqrt((double)pl->N));
+  ld.N = pl->N;
+  ld.n = n;
+  ld.n1 = n1;
+  ld.tw = line_plan(pl, L).tw;
+  return ld;
+}
+
+static St2CoilReduce st2_reduce(isg_plan* pl, float2* w, const float2* Sm, int n, int n1, int L) {
+  St2CoilReduce st;
+  st.out = w;
+  st.S = Sm;
+  st.dx = tabs(pl->dx);
+  st.scale = (float)(1.0 / std::sqrt((double)pl->N));
+  st.N = pl->N;
+  st.n = n;
+  st.L = L;
+  st.C = pl->C;
+  st.n1 = n1;
+  return st;
+}
+
 template <int S>
 static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void* grid) {
   const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
   const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
   const int C = pl->C;
   const float scale = (float)(1.0 / std::sqrt((double)pl->N));
-  if (pl->ndim == 3) {
+  if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
+    // S_c m / c(x/G) |N|^{-1/2}, centred pad, F along axis 2
+    run_fft2<-1, kJFast, kBFast>(pl, "fft_coil_fwd_last", G2, ld2_expand(pl, m, Sm, n2, n1, G2),
+                                 st2<S>(pl->k1buf, (int64_t)G2 * C, C, kDense),
+                                 make_tile2((int64_t)n0 * n1, C, G2, C));
+    // centred pad, F along axis 1
+    run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax1", G1,
+                                 ld2<S>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
+                                 st2<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, kDense),
+                                 make_tile2(n0, (int64_t)G2 * C, G1, 0));
+    // centred pad, F along axis 0
+    run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0,
+                                 ld2<S>(pl, pl->k2buf, 0, (int64_t)G1 * G2 * C, kCentred, G0),
+                                 st2<S>(grid, 0, (int64_t)G1 * G2 * C, kDense),
+                                 make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
+  } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
+    run_fft2<-1, kJFast, kBFast>(pl, "fft_coil_fwd_last", G1, ld2_expand(pl, m, Sm, n1, 0, G1),
+                                 st2<S>(pl->k1buf, (int64_t)G1 * C, C, kDense), make_tile2(n0, C, G1, C));
+    run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0, ld2<S>(pl, pl->k1buf, 0, (int64_t)G1 * C, kCentred, G0),
+                                 st2<S>(grid, 0, (int64_t)G1 * C, kDense), make_tile2(1, (int64_t)G1 * C, G0, 0));
+  } else if (pl->ndim == 3) {
     {  // S_c m / c(x/G) |N|^{-1/2}, centred pad, F along axis 2
       TileGeom g = make_geom((int64_t)n0 * n1, C, G2, C);
       LdCoilExpand ld;
@@ -638,7 +788,22 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
   const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
   const int C = pl->C;
   const float scale = (float)(1.0 / std::sqrt((double)pl->N));
-  if (pl->ndim == 3) {
+  if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
+    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2<S>(pl, grid, 0, (int64_t)G1 * G2 * C, kDense, G0),
+                                 st2<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, kCentred),
+                                 make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
+    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax1", G1,
+                                 ld2<S>(pl, pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, kDense, G1),
+                                 st2<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred),
+                                 make_tile2(n0, (int64_t)G2 * C, G1, 0));
+    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G2, ld2<S>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
+                                 st2_reduce(pl, w, Sm, n2, n1, G2), make_tile2((int64_t)n0 * n1, C, G2, C));
+  } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
+    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2<S>(pl, grid, 0, (int64_t)G1 * C, kDense, G0),
+                                 st2<S>(pl->k1buf, 0, (int64_t)G1 * C, kCentred), make_tile2(1, (int64_t)G1 * C, G0, 0));
+    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G1, ld2<S>(pl, pl->k1buf, (int64_t)G1 * C, C, kDense, G1),
+                                 st2_reduce(pl, w, Sm, n1, 0, G1), make_tile2(n0, C, G1, C));
+  } else if (pl->ndim == 3) {
     {  // F^H along axis 0, centred crop
       TileGeom g = make_geom(1, (int64_t)G1 * G2 * C, G0, 0);
       run_pass(pl, "fft_coil_adj_ax0", ld_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g), NoMid(),
@@ -697,19 +862,22 @@ template <int S>
 static void kgather_t(isg_plan* pl, const void* grid, const isg_traj* tr, float2* y) {
   auto grd = (const typename Elem<S>::T*)grid;
   Tick tick(pl, "kgather");
+  const int spw = 64 / pl->C;  // samples per wavefront
+  const int64_t waves = (tr->M + spw - 1) / spw;
+  const unsigned nblk = (unsigned)((waves + kGridThreads / 64 - 1) / (kGridThreads / 64));
   if (pl->ndim == 3)
-    hipLaunchKernelGGL((kgather_kernel<3, S>), dim3(blocks_for(tr->M, kGridThreads)), dim3(kGridThreads), 0,
-                       pl->stream, grd, tr->taps, tr->M, y, pl->C, pl->dims, pl->kb);
+    hipLaunchKernelGGL((kgather_kernel<3, S>), dim3(nblk), dim3(kGridThreads), 0, pl->stream, grd, tr->taps, tr->M,
+                       y, pl->C, pl->dims, pl->kb);
   else
-    hipLaunchKernelGGL((kgather_kernel<2, S>), dim3(blocks_for(tr->M, kGridThreads)), dim3(kGridThreads), 0,
-                       pl->stream, grd, tr->taps, tr->M, y, pl->C, pl->dims, pl->kb);
+    hipLaunchKernelGGL((kgather_kernel<2, S>), dim3(nblk), dim3(kGridThreads), 0, pl->stream, grd, tr->taps, tr->M,
+                       y, pl->C, pl->dims, pl->kb);
   LAUNCH_OK();
 }
 
 template <int S>
 static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* y, void* grid) {
   auto grd = (typename Elem<S>::T*)grid;
-  const size_t lds = sizeof(float2) * (size_t)pl->ktile.vol * pl->C;
+  const size_t lds = sizeof(float) * 2 * (size_t)pl->ktile.P * pl->C + sizeof(float2) * kSpreadBatch * pl->C;
   const size_t volC = (size_t)pl->ktile.vol * pl->C;
   if (tr->nslots) grow(pl, pl->partial, sizeof(float2) * volC * tr->nslots);
   float2* part = (float2*)pl->partial.p;
@@ -1100,11 +1268,23 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
     pl->ktile.TS[i] = 1;
     pl->ktile.nt[i] = 1;
   }
-  const int wts = pl->ndim == 3 ? 16 : 64;
+  const int wts = pl->ndim == 3 ? 8 : 16;
   for (int i = 0; i < pl->ndim; ++i) {
     pl->wtile.TS[i] = std::min(wts, pl->G[i]);
     pl->wtile.nt[i] = (pl->G[i] + pl->wtile.TS[i] - 1) / pl->wtile.TS[i];
   }
+  if (pl->ndim == 3) {
+    // rows of TS2, planes at S0 = 4 (mod 32): the 64 taps of an entry hit
+    // distinct banks within each half-wavefront
+    pl->wtile.S1 = pl->wtile.TS[2];
+    int s0 = pl->wtile.TS[1] * pl->wtile.TS[2];
+    while (s0 % 32 != 4) ++s0;
+    pl->wtile.S0 = s0;
+  } else {
+    pl->wtile.S1 = 1;
+    pl->wtile.S0 = pl->wtile.TS[1] + 1;
+  }
+  pl->wtile.P = pl->wtile.TS[0] * pl->wtile.S0;
   if (pl->ndim == 3) {
     const int t0 = pl->C > 16 ? 4 : 8;
     const int ts[3] = {t0, 8, 8};
@@ -1116,6 +1296,21 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
   for (int i = 0; i < pl->ndim; ++i) {
     pl->ktile.nt[i] = (pl->G[i] + pl->ktile.TS[i] - 1) / pl->ktile.TS[i];
     pl->ktile.vol *= pl->ktile.TS[i];
+  }
+  if (pl->ndim == 3) {
+    pl->ktile.S1 = pl->ktile.TS[2];
+    // S0 = 4 (mod 32) and at least TS1 * TS2
+    int s0 = pl->ktile.TS[1] * pl->ktile.TS[2];
+    while (s0 % 32 != 4) ++s0;
+    pl->ktile.S0 = s0;
+  } else {
+    pl->ktile.S1 = 1;
+    pl->ktile.S0 = pl->ktile.TS[1] + 1;
+  }
+  {  // plane size = 1 (mod 16) staggers the coil planes across banks
+    int P = pl->ktile.TS[0] * pl->ktile.S0;
+    while (P % 16 != 1) ++P;
+    pl->ktile.P = P;
   }
   isg_status st = guarded(pl, [&]() -> isg_status {
     HIP_OK(hipGetDevice(&pl->device));
