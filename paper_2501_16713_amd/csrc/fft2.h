@@ -285,6 +285,67 @@ struct St2Strided {
   }
 };
 
+// Touched-tile masks of a trajectory.  The k-space grid [G0][...][C] is cut
+// into spread tiles; colmask[col] has bit t0 set when some sample's taps
+// touch tile (t0, col), col = (i1 / TS1) nt2 + i2 / TS2 (3D) or i1 / TS1 (2D).
+// Untouched tiles are never read by the gather and are zero after the
+// spread, so the axis-0 passes skip them.
+struct TileMask {
+  const uint64_t* colmask;  // null: every tile is touched
+  int C, G2, TS1, TS2, nt2, ts0_log2, three_d;
+  __device__ __forceinline__ uint64_t column(int64_t b) const {
+    if (!colmask) return ~0ull;
+    const uint32_t q = (uint32_t)b / (uint32_t)C;  // (i1, i2) flat, or i1 in 2D (< 2^31)
+    uint32_t col;
+    if (three_d) {
+      const uint32_t i1 = q / (uint32_t)G2, i2 = q - i1 * (uint32_t)G2;
+      col = (i1 / (uint32_t)TS1) * (uint32_t)nt2 + i2 / (uint32_t)TS2;
+    } else {
+      col = q / (uint32_t)TS1;
+    }
+    return colmask[col];
+  }
+};
+
+// axis-0 load that reads untouched tiles as zero (dense map)
+template <int S>
+struct Ld2Masked {
+  const typename Elem<S>::T* p;
+  int64_t sj;
+  TileMask tm;
+  const float2* tw;
+  struct Line {
+    const typename Elem<S>::T* base;
+    uint64_t mask;
+  };
+  __device__ Line setup(int64_t a, int64_t b, bool valid) const {
+    return Line{p + b, valid ? tm.column(b) : 0ull};
+  }
+  template <int L>
+  __device__ float2 get(const Line& ln, int pos, bool valid) const {
+    if (!valid || !((ln.mask >> (pos >> tm.ts0_log2)) & 1ull)) return make_float2(0.f, 0.f);
+    return Elem<S>::load(ln.base + (int64_t)pos * sj);
+  }
+};
+
+// axis-0 store that skips untouched tiles (dense map)
+template <int S>
+struct St2Masked {
+  static constexpr bool kEpilogue = false;
+  typename Elem<S>::T* p;
+  int64_t sj;
+  TileMask tm;
+  struct Line {
+    typename Elem<S>::T* base;
+    uint64_t mask;
+  };
+  __device__ Line setup(int64_t a, int64_t b, bool valid) const { return Line{p + b, valid ? tm.column(b) : 0ull}; }
+  template <int L>
+  __device__ void put(const Line& ln, int pos, float2 v, bool valid) const {
+    if (valid && ((ln.mask >> (pos >> tm.ts0_log2)) & 1ull)) Elem<S>::store(ln.base + (int64_t)pos * sj, v);
+  }
+};
+
 // first pass of inverse k-space gridding: S_c . m / c(x/G) |N|^{-1/2},
 // zero-padded (centred) along the last axis; lines are (a, c)
 struct Ld2CoilExpand {

@@ -226,13 +226,15 @@ constexpr int kWarpWaves = kGridThreads / 64;
 
 template <int NDIM>
 __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPhases ph, float2* __restrict__ U,
-                                                                   int accumulate, Dims dm, TileDims td,
-                                                                   KbPoly kb) {
-  extern __shared__ float accw[];  // [kWarpWaves][2][P]
+                                                                   int accumulate, int ntiles, Dims dm,
+                                                                   TileDims td, KbPoly kb) {
+  extern __shared__ float accw[];  // [kWarpWaves][2 copies][2][P]
   __shared__ int st_off[kWarpWaves][64][3];
   __shared__ float st_w[kWarpWaves][64][3][4];
   __shared__ float2 st_v[kWarpWaves][64];
-  const int tile = blockIdx.x;
+  // persistent: each workgroup walks tiles blockIdx.x, + gridDim.x, ...
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  __syncthreads();  // the previous tile's write-out has read the accumulators
   int tc[3] = {0, 0, 0};
   {
     int t = tile;
@@ -249,14 +251,18 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
     ext[i] = min(td.TS[i], dm.G[i] - lo[i]);
     vol *= td.TS[i];
   }
-  for (int e = threadIdx.x; e < kWarpWaves * 2 * td.P; e += kGridThreads) accw[e] = 0.f;
+  for (int e = threadIdx.x; e < kWarpWaves * 4 * td.P; e += kGridThreads) accw[e] = 0.f;
   // entries of this tile over all states, concatenated
   int E = 0;
   for (int p = 0; p < ph.P; ++p) E += ph.tile_off[p][tile + 1] - ph.tile_off[p][tile];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  float* are = accw + wave * 2 * td.P;
-  float* aim = are + td.P;
+  // two copies per wave: consecutive staged entries alternate between them,
+  // so the read-modify-writes of entries s and s+1 never alias
+  float* are0 = accw + wave * 4 * td.P;
+  float* aim0 = are0 + td.P;
+  float* are1 = aim0 + td.P;
+  float* aim1 = are1 + td.P;
   int tt[3];
   tt[NDIM - 1] = lane & 3;
   tt[NDIM - 2] = (lane >> 2) & 3;
@@ -301,22 +307,42 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
     }
     __syncthreads();
     if (tap_lane) {
-      for (int s = 0; s < ne; ++s) {
-        bool ok = true;
-        float ww = 1.0f;
-        int idx = 0;
+      for (int s = 0; s < ne; s += 2) {
+        bool ok[2];
+        float ww[2];
+        int idx[2];
 #pragma unroll
-        for (int i = 0; i < NDIM; ++i) {
-          const int l = st_off[wave][s][i] + tt[i];
-          ok = ok && l >= 0 && l < ext[i];
-          ww *= st_w[wave][s][i][tt[i]];
-          // 3D: l0 S0 + l1 S1 + l2; 2D: l0 S0 + l1
-          idx += l * (i == NDIM - 1 ? 1 : (i == 0 ? td.S0 : td.S1));
+        for (int q = 0; q < 2; ++q) {
+          const int sq = min(s + q, 63);
+          ok[q] = s + q < ne;
+          ww[q] = 1.0f;
+          idx[q] = 0;
+#pragma unroll
+          for (int i = 0; i < NDIM; ++i) {
+            const int l = st_off[wave][sq][i] + tt[i];
+            ok[q] = ok[q] && l >= 0 && l < ext[i];
+            ww[q] *= st_w[wave][sq][i][tt[i]];
+            // 3D: l0 S0 + l1 S1 + l2; 2D: l0 S0 + l1
+            idx[q] += l * (i == NDIM - 1 ? 1 : (i == 0 ? td.S0 : td.S1));
+          }
         }
-        if (ok) {
-          const float2 v = st_v[wave][s];
-          are[idx] += ww * v.x;
-          aim[idx] += ww * v.y;
+        const float2 v0 = st_v[wave][s], v1 = st_v[wave][min(s + 1, 63)];
+        float r0 = 0.f, i0 = 0.f, r1 = 0.f, i1 = 0.f;
+        if (ok[0]) {
+          r0 = are0[idx[0]];
+          i0 = aim0[idx[0]];
+        }
+        if (ok[1]) {
+          r1 = are1[idx[1]];
+          i1 = aim1[idx[1]];
+        }
+        if (ok[0]) {
+          are0[idx[0]] = fmaf(ww[0], v0.x, r0);
+          aim0[idx[0]] = fmaf(ww[0], v0.y, i0);
+        }
+        if (ok[1]) {
+          are1[idx[1]] = fmaf(ww[1], v1.x, r1);
+          aim1[idx[1]] = fmaf(ww[1], v1.y, i1);
         }
       }
     }
@@ -338,13 +364,14 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
     const int pi = NDIM == 3 ? l[0] * td.S0 + l[1] * td.S1 + l[2] : l[0] * td.S0 + l[1];
     float2 v = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int w = 0; w < kWarpWaves; ++w) {
+    for (int w = 0; w < 2 * kWarpWaves; ++w) {
       v.x += accw[w * 2 * td.P + pi];
       v.y += accw[w * 2 * td.P + td.P + pi];
     }
     if (accumulate) v = cadd(v, U[gi]);
     U[gi] = v;
   }
+  }  // tiles
 }
 
 // ---------------------------------------------------------------------------
@@ -469,49 +496,45 @@ __device__ __forceinline__ int kplane_index(const KTile& kt, int pt) {
 constexpr int kSpreadBatch = 64;
 
 // k-space spread of one work unit, without atomics.  The unit's samples are
-// staged in LDS in batches of kSpreadBatch (tap offsets, weights, the C coil
-// values).  Wave w of the workgroup owns the tile planes
-// l0 in [w T0/4, (w+1) T0/4) and walks every staged sample, adding the taps
-// that land in its planes; within one (t0, t1) step its lanes cover distinct
-// (t1, t2, coil) points, so plain LDS read-modify-write is race free and the
-// summation order is fixed (the spread is deterministic).
+// staged in LDS in batches of kSpreadBatch (tap offsets relative to the tile,
+// tap weights, the C coil values).  Wave w owns coils 4w .. 4w+3 (their LDS
+// planes are its alone); in 3D its 64 lanes are (coil, t1, t2) and each lane
+// applies the sample's four t0 taps, in 2D the lanes are (coil, t0, t1).
+// Within a wave every lane updates distinct points, so plain LDS
+// read-modify-write is race free, and the summation order is fixed (the
+// spread is deterministic).  The workgroup has ceil(C/4) waves.
 template <int NDIM, int S>
-__global__ __launch_bounds__(kGridThreads) void kspread_kernel(const KUnit* __restrict__ units,
-                                                               const int* __restrict__ order,
-                                                               const KTap* __restrict__ taps,
-                                                               const float2* __restrict__ y, int C,
-                                                               typename Elem<S>::T* __restrict__ grid,
-                                                               float2* __restrict__ partial, Dims dm,
-                                                               KTile kt, KbPoly kb) {
-  extern __shared__ float accf[];  // [C][2][P] accumulator, then the staging area
+__global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ units, int nunits,
+                                                      const int* __restrict__ order,
+                                                      const KTap* __restrict__ taps,
+                                                      const float2* __restrict__ y, int C,
+                                                      typename Elem<S>::T* __restrict__ grid,
+                                                      float2* __restrict__ partial, Dims dm, KTile kt,
+                                                      KbPoly kb, FastDiv cdiv) {
+  extern __shared__ float accf[];  // [C][2][P] accumulator, then the staged coil values
   __shared__ int st_j[kSpreadBatch];
   __shared__ int st_off[kSpreadBatch][3];
   __shared__ float st_w[kSpreadBatch][3][4];
   float2* st_y = (float2*)(accf + (size_t)C * 2 * kt.P);  // [kSpreadBatch][C]
+  const int nthr = blockDim.x;
   const KUnit un = units[blockIdx.x];
   int lo[3] = {0, 0, 0};
   ktile_origin(un.tile, kt, NDIM, lo);
   const int nacc = C * 2 * kt.P;
-  for (int e = threadIdx.x; e < nacc; e += kGridThreads) accf[e] = 0.f;
+  for (int e = threadIdx.x; e < nacc; e += nthr) accf[e] = 0.f;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  constexpr int NW = kGridThreads / 64;
-  // plane slab of this wave
-  const int per = (kt.TS[0] + NW - 1) / NW;
-  const int slab_lo = wave * per, slab_hi = min(kt.TS[0], slab_lo + per);
-  // lane -> (t1 group member, t2, coil of a chunk of CC <= 16); coil fastest
-  const int CC = min(C, 16);
-  const int cl = lane % CC;
-  const int t2 = (lane / CC) & 3;
-  const int t1s = lane / (4 * CC);                    // which t1 of a round
-  const int t1n = min(4, 64 / (4 * CC));              // t1 values per round (1, 2 or 4)
-  const int t1r = (4 + t1n - 1) / t1n;                // rounds over t1
-  const bool lane_ok = lane < CC * 4 * t1n;
+  const int c = 4 * wave + (lane & 3);
+  const int ta = (lane >> 2) & 3;  // 3D: t2; 2D: t1
+  const int tb = lane >> 4;        // 3D: t1; 2D: t0
+  const bool active = c < C;
+  float* pre = accf + (2 * (active ? c : 0)) * kt.P;
+  float* pim = pre + kt.P;
 
   for (int b0 = 0; b0 < un.count; b0 += kSpreadBatch) {
     const int nb = min(kSpreadBatch, un.count - b0);
-    __syncthreads();  // previous batch fully consumed (and accumulator zeroed)
+    __syncthreads();  // previous batch consumed (and the accumulator zeroed)
     if (threadIdx.x < nb) {
       const int j = order[un.start + b0 + threadIdx.x];
       const KTap tp = taps[j];
@@ -522,85 +545,79 @@ __global__ __launch_bounds__(kGridThreads) void kspread_kernel(const KUnit* __re
         kb_weights(kb, tp.f[i], w);
 #pragma unroll
         for (int t = 0; t < 4; ++t) st_w[threadIdx.x][i][t] = w[t];
-        int o = (int)((tp.base >> (10 * i)) & 1023) - lo[i];  // periodic: pick the image next to the tile
+        int o = (int)((tp.base >> (10 * i)) & 1023) - lo[i];  // periodic: the image next to the tile
         if (o > dm.G[i] / 2) o -= dm.G[i];
         if (o < -dm.G[i] / 2) o += dm.G[i];
         st_off[threadIdx.x][i] = o;
       }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nb * C; e += kGridThreads) {
-      const int s = e / C;
+    for (int e = threadIdx.x; e < nb * C; e += nthr) {
+      const int s = (int)cdiv.div((uint32_t)e);
       st_y[e] = y[(int64_t)st_j[s] * C + (e - s * C)];
     }
     __syncthreads();
-    for (int c0 = 0; c0 < C; c0 += CC) {
-      const int c = c0 + cl;
-      if (!lane_ok || c >= C) continue;
-      float* pre = accf + (2 * c) * kt.P;
-      float* pim = pre + kt.P;
-      for (int s = 0; s < nb; ++s) {
-        const int o0 = st_off[s][0];
-        if (o0 + 3 < slab_lo || o0 >= slab_hi) continue;  // uniform across the wave
-        const float2 yv = st_y[s * C + c];
-        if constexpr (NDIM == 3) {
-          const int o1 = st_off[s][1], l2 = st_off[s][2] + t2;
-          const bool ok2 = l2 >= 0 && l2 < kt.TS[2];
-          const float w2 = st_w[s][2][t2];
+    if (!active) continue;
+    for (int s = 0; s < nb; ++s) {
+      const float2 yv = st_y[s * C + c];
+      if constexpr (NDIM == 3) {
+        const int l2 = st_off[s][2] + ta, l1 = st_off[s][1] + tb, o0 = st_off[s][0];
+        if (l2 < 0 || l2 >= kt.TS[2] || l1 < 0 || l1 >= kt.TS[1]) continue;
+        const float w12 = st_w[s][1][tb] * st_w[s][2][ta];
+        const int base = l1 * kt.S1 + l2;
+        float vr[4], vi[4];
+        int idx[4];
 #pragma unroll
-          for (int t0 = 0; t0 < 4; ++t0) {
-            const int l0 = o0 + t0;
-            if (l0 < slab_lo || l0 >= slab_hi) continue;
-            const float w02 = st_w[s][0][t0] * w2;
-            for (int r = 0; r < t1r; ++r) {
-              const int t1 = r * t1n + t1s;
-              const int l1 = o1 + t1;
-              if (t1 < 4 && ok2 && l1 >= 0 && l1 < kt.TS[1]) {
-                const float ww = w02 * st_w[s][1][t1];
-                const int idx = l0 * kt.S0 + l1 * kt.S1 + l2;
-                pre[idx] += ww * yv.x;
-                pim[idx] += ww * yv.y;
-              }
-            }
-          }
-        } else {
-          // 2D: lanes cover (t1, coil); rows t0 within the slab
-          const int l1 = st_off[s][1] + t2;
-          const bool ok1 = l1 >= 0 && l1 < kt.TS[1];
-          const float w1 = st_w[s][1][t2];
-#pragma unroll
-          for (int t0 = 0; t0 < 4; ++t0) {
-            const int l0 = o0 + t0;
-            if (l0 < slab_lo || l0 >= slab_hi || t1s != 0 || !ok1) continue;
-            const float ww = st_w[s][0][t0] * w1;
-            const int idx = l0 * kt.S0 + l1;
-            pre[idx] += ww * yv.x;
-            pim[idx] += ww * yv.y;
+        for (int t0 = 0; t0 < 4; ++t0) {  // read all four, then write all four
+          const int l0 = o0 + t0;
+          idx[t0] = (l0 >= 0 && l0 < kt.TS[0]) ? l0 * kt.S0 + base : -1;
+          if (idx[t0] >= 0) {
+            vr[t0] = pre[idx[t0]];
+            vi[t0] = pim[idx[t0]];
           }
         }
+#pragma unroll
+        for (int t0 = 0; t0 < 4; ++t0) {
+          if (idx[t0] >= 0) {
+            const float ww = w12 * st_w[s][0][t0];
+            pre[idx[t0]] = fmaf(ww, yv.x, vr[t0]);
+            pim[idx[t0]] = fmaf(ww, yv.y, vi[t0]);
+          }
+        }
+      } else {
+        const int l1 = st_off[s][1] + ta, l0 = st_off[s][0] + tb;
+        if (l1 < 0 || l1 >= kt.TS[1] || l0 < 0 || l0 >= kt.TS[0]) continue;
+        const float ww = st_w[s][0][tb] * st_w[s][1][ta];
+        const int idx = l0 * kt.S0 + l1;
+        pre[idx] = fmaf(ww, yv.x, pre[idx]);
+        pim[idx] = fmaf(ww, yv.y, pim[idx]);
       }
     }
   }
   __syncthreads();
   // write out: rows along the last axis are TS*C contiguous values
   const int volC = kt.vol * C;
-  for (int e = threadIdx.x; e < volC; e += kGridThreads) {
-    const int pt = e / C;
+  for (int e = threadIdx.x; e < volC; e += nthr) {
+    const int pt = (int)cdiv.div((uint32_t)e);
     const int cc = e - pt * C;
-    const int pi = kplane_index<NDIM>(kt, pt);
+    int l[3] = {0, 0, 0};
+    if constexpr (NDIM == 3) {
+      l[2] = pt % kt.TS[2];
+      const int r = pt / kt.TS[2];
+      l[1] = r % kt.TS[1];
+      l[0] = r / kt.TS[1];
+    } else {
+      l[1] = pt % kt.TS[1];
+      l[0] = pt / kt.TS[1];
+    }
+    const int pi = NDIM == 3 ? l[0] * kt.S0 + l[1] * kt.S1 + l[2] : l[0] * kt.S0 + l[1];
     const float2 v = make_float2(accf[(2 * cc) * kt.P + pi], accf[(2 * cc + 1) * kt.P + pi]);
     if (un.slot >= 0) {
       partial[(int64_t)un.slot * volC + e] = v;
       continue;
     }
-    int l[3] = {0, 0, 0};
-    int t = pt;
     bool ok = true;
     int64_t gi = 0;
-    for (int i = NDIM - 1; i >= 0; --i) {
-      l[i] = t % kt.TS[i];
-      t /= kt.TS[i];
-    }
     for (int i = 0; i < NDIM; ++i) {
       const int g = lo[i] + l[i];
       ok = ok && g < dm.G[i];
@@ -625,8 +642,18 @@ __global__ __launch_bounds__(kGridThreads) void kspread_reduce_kernel(const KSpl
   ktile_origin(sp.tile, kt, NDIM, lo);
   const int volC = kt.vol * C;
   for (int e = threadIdx.x; e < volC; e += kGridThreads) {
-    float2 s = make_float2(0.f, 0.f);
-    for (int k = 0; k < sp.nslots; ++k) s = cadd(s, partial[(int64_t)(sp.first_slot + k) * volC + e]);
+    float2 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = make_float2(0.f, 0.f);
+    int k = 0;
+    for (; k + 8 <= sp.nslots; k += 8) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], partial[(int64_t)(sp.first_slot + k + q) * volC + e]);
+    }
+    for (; k < sp.nslots; ++k) acc[0] = cadd(acc[0], partial[(int64_t)(sp.first_slot + k) * volC + e]);
+    float2 s = acc[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) s = cadd(s, acc[q]);
     const int pt = e / C;
     const int c = e - pt * C;
     int l[3] = {0, 0, 0};

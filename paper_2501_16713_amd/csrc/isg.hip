@@ -123,6 +123,7 @@ struct isg_plan {
   int storage = 0;
   hipStream_t stream = nullptr;
   int device = 0;
+  int ncu = 256;  // compute units of the device
   bool failed = false;
   double beta = 0;
   KbPoly kb;
@@ -224,6 +225,7 @@ struct isg_motion {
 struct isg_traj {
   isg_plan* plan = nullptr;
   int64_t M = 0;
+  uint64_t* colmask = nullptr;  // touched-tile masks (null: all tiles written)
   KTap* taps = nullptr;
   int* order = nullptr;
   KUnit* units = nullptr;
@@ -647,7 +649,7 @@ static int warp_ntiles(const isg_plan* pl) {
 
 // U = sum_p P_{d_p} w_p over the given states
 static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const float2* const* w, float2* U) {
-  const size_t lds = sizeof(float) * 2 * (size_t)pl->wtile.P * kWarpWaves;
+  const size_t lds = sizeof(float) * 4 * (size_t)pl->wtile.P * kWarpWaves;
   for (int p0 = 0; p0 < P; p0 += kMaxPhasesPerLaunch) {
     WarpSpreadPhases ph;
     memset(&ph, 0, sizeof(ph));
@@ -659,13 +661,15 @@ static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const 
       ph.w[i] = w[p0 + i];
     }
     const int acc = p0 > 0 ? 1 : 0;
+    const int nt = warp_ntiles(pl);
+    const unsigned nblk = (unsigned)nt;  // one workgroup per tile
     Tick tick(pl, "warp_spread");
     if (pl->ndim == 3)
-      hipLaunchKernelGGL(warp_spread_kernel<3>, dim3(warp_ntiles(pl)), dim3(kGridThreads), lds, pl->stream, ph, U,
-                         acc, pl->dims, pl->wtile, pl->kb);
+      hipLaunchKernelGGL(warp_spread_kernel<3>, dim3(nblk), dim3(kGridThreads), lds, pl->stream, ph, U, acc, nt,
+                         pl->dims, pl->wtile, pl->kb);
     else
-      hipLaunchKernelGGL(warp_spread_kernel<2>, dim3(warp_ntiles(pl)), dim3(kGridThreads), lds, pl->stream, ph, U,
-                         acc, pl->dims, pl->wtile, pl->kb);
+      hipLaunchKernelGGL(warp_spread_kernel<2>, dim3(nblk), dim3(kGridThreads), lds, pl->stream, ph, U, acc, nt,
+                         pl->dims, pl->wtile, pl->kb);
     LAUNCH_OK();
   }
 }
@@ -700,8 +704,44 @@ static St2CoilReduce st2_reduce(isg_plan* pl, float2* w, const float2* Sm, int n
   return st;
 }
 
+static TileMask tile_mask(const isg_plan* pl, const isg_traj* tr) {
+  TileMask tm;
+  tm.colmask = tr ? tr->colmask : nullptr;
+  tm.C = pl->C;
+  tm.G2 = pl->G[2];
+  tm.TS1 = pl->ktile.TS[1];
+  tm.TS2 = pl->ktile.TS[2];
+  tm.nt2 = pl->ktile.nt[2];
+  int lg = 0;
+  while ((1 << lg) < pl->ktile.TS[0]) ++lg;
+  tm.ts0_log2 = lg;
+  tm.three_d = pl->ndim == 3;
+  return tm;
+}
+
 template <int S>
-static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void* grid) {
+static St2Masked<S> st2_masked(void* p, int64_t sj, const TileMask& tm) {
+  St2Masked<S> st;
+  st.p = (typename Elem<S>::T*)p;
+  st.sj = sj;
+  st.tm = tm;
+  return st;
+}
+
+template <int S>
+static Ld2Masked<S> ld2_masked(isg_plan* pl, const void* p, int64_t sj, const TileMask& tm, int L) {
+  Ld2Masked<S> ld;
+  ld.p = (const typename Elem<S>::T*)p;
+  ld.sj = sj;
+  ld.tm = tm;
+  ld.tw = line_plan(pl, L).tw;
+  return ld;
+}
+
+// grid = F_G Z (S_c m / c(x/G)) |N|^{-1/2} for every coil; tiles of `tr`
+// that no sample touches are not written (tr may be null)
+template <int S>
+static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void* grid, const isg_traj* tr) {
   const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
   const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
   const int C = pl->C;
@@ -719,13 +759,14 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
     // centred pad, F along axis 0
     run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0,
                                  ld2<S>(pl, pl->k2buf, 0, (int64_t)G1 * G2 * C, kCentred, G0),
-                                 st2<S>(grid, 0, (int64_t)G1 * G2 * C, kDense),
+                                 st2_masked<S>(grid, (int64_t)G1 * G2 * C, tile_mask(pl, tr)),
                                  make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
     run_fft2<-1, kJFast, kBFast>(pl, "fft_coil_fwd_last", G1, ld2_expand(pl, m, Sm, n1, 0, G1),
                                  st2<S>(pl->k1buf, (int64_t)G1 * C, C, kDense), make_tile2(n0, C, G1, C));
     run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0, ld2<S>(pl, pl->k1buf, 0, (int64_t)G1 * C, kCentred, G0),
-                                 st2<S>(grid, 0, (int64_t)G1 * C, kDense), make_tile2(1, (int64_t)G1 * C, G0, 0));
+                                 st2_masked<S>(grid, (int64_t)G1 * C, tile_mask(pl, tr)),
+                                 make_tile2(1, (int64_t)G1 * C, G0, 0));
   } else if (pl->ndim == 3) {
     {  // S_c m / c(x/G) |N|^{-1/2}, centred pad, F along axis 2
       TileGeom g = make_geom((int64_t)n0 * n1, C, G2, C);
@@ -782,14 +823,17 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
   }
 }
 
+// w = sum_c conj(S_c) crop(F_G^H grid) / c(x/G) |N|^{-1/2}; tiles of `tr`
+// that no sample touches are read as zero (tr may be null)
 template <int S>
-static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, float2* w) {
+static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, float2* w, const isg_traj* tr) {
   const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
   const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
   const int C = pl->C;
   const float scale = (float)(1.0 / std::sqrt((double)pl->N));
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
-    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2<S>(pl, grid, 0, (int64_t)G1 * G2 * C, kDense, G0),
+    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0,
+                                 ld2_masked<S>(pl, grid, (int64_t)G1 * G2 * C, tile_mask(pl, tr), G0),
                                  st2<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, kCentred),
                                  make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax1", G1,
@@ -799,7 +843,7 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G2, ld2<S>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
                                  st2_reduce(pl, w, Sm, n2, n1, G2), make_tile2((int64_t)n0 * n1, C, G2, C));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
-    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2<S>(pl, grid, 0, (int64_t)G1 * C, kDense, G0),
+    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2_masked<S>(pl, grid, (int64_t)G1 * C, tile_mask(pl, tr), G0),
                                  st2<S>(pl->k1buf, 0, (int64_t)G1 * C, kCentred), make_tile2(1, (int64_t)G1 * C, G0, 0));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G1, ld2<S>(pl, pl->k1buf, (int64_t)G1 * C, C, kDense, G1),
                                  st2_reduce(pl, w, Sm, n1, 0, G1), make_tile2(n0, C, G1, C));
@@ -881,12 +925,13 @@ static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* y, void* g
   const size_t volC = (size_t)pl->ktile.vol * pl->C;
   if (tr->nslots) grow(pl, pl->partial, sizeof(float2) * volC * tr->nslots);
   float2* part = (float2*)pl->partial.p;
+  const int kthreads = 64 * ((pl->C + 3) / 4);  // one wave per 4 coils
   if (pl->ndim == 3) {
     auto k = kspread_kernel<3, S>;
     allow_lds(k, lds);
     Tick tick(pl, "kspread");
-    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kGridThreads), lds, pl->stream, tr->units, tr->order, tr->taps, y,
-                       pl->C, grd, part, pl->dims, pl->ktile, pl->kb);
+    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kthreads), lds, pl->stream, tr->units, tr->nunits, tr->order,
+                       tr->taps, y, pl->C, grd, part, pl->dims, pl->ktile, pl->kb, make_fastdiv(pl->C));
     LAUNCH_OK();
     if (tr->nsplits) {
       Tick tick2(pl, "kspread_reduce");
@@ -898,8 +943,8 @@ static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* y, void* g
     auto k = kspread_kernel<2, S>;
     allow_lds(k, lds);
     Tick tick(pl, "kspread");
-    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kGridThreads), lds, pl->stream, tr->units, tr->order, tr->taps, y,
-                       pl->C, grd, part, pl->dims, pl->ktile, pl->kb);
+    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kthreads), lds, pl->stream, tr->units, tr->nunits, tr->order,
+                       tr->taps, y, pl->C, grd, part, pl->dims, pl->ktile, pl->kb, make_fastdiv(pl->C));
     LAUNCH_OK();
     if (tr->nsplits) {
       Tick tick2(pl, "kspread_reduce");
@@ -943,7 +988,7 @@ static void op_sense_forward(isg_plan* pl, int P, const float2* x, const isg_mot
   int64_t off = 0;
   for (int p = 0; p < P; ++p) {
     warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
-    STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, pl->kgrid);
+    STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, pl->kgrid, k[p]);
     STORAGE_DISPATCH(pl, kgather_t, pl, pl->kgrid, k[p], y + off);
     off += k[p]->M * pl->C;
   }
@@ -956,7 +1001,7 @@ static void op_sense_adjoint(isg_plan* pl, int P, const float2* y, const isg_mot
   int64_t off = 0;
   for (int p = 0; p < P; ++p) {
     STORAGE_DISPATCH(pl, kspread_t, pl, k[p], y + off, pl->kgrid);
-    STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, S, pl->wbuf + (int64_t)p * pl->N);
+    STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, S, pl->wbuf + (int64_t)p * pl->N, k[p]);
     w[p] = pl->wbuf + (int64_t)p * pl->N;
     off += k[p]->M * pl->C;
   }
@@ -975,10 +1020,10 @@ static void op_normal(isg_plan* pl, int P, const float2* x, double lam, const is
   std::vector<const float2*> w(P);
   for (int p = 0; p < P; ++p) {
     warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
-    STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, pl->kgrid);
+    STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, pl->kgrid, k[p]);
     STORAGE_DISPATCH(pl, kgather_t, pl, pl->kgrid, k[p], y);
     STORAGE_DISPATCH(pl, kspread_t, pl, k[p], y, pl->kgrid);
-    STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, S, pl->wbuf + (int64_t)p * pl->N);
+    STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, S, pl->wbuf + (int64_t)p * pl->N, k[p]);
     w[p] = pl->wbuf + (int64_t)p * pl->N;
   }
   warp_spread(pl, P, d, w.data(), pl->ugrid);
@@ -1063,6 +1108,19 @@ static isg_status prepare_motion(isg_plan* pl, const float* d_dev, isg_motion* m
   return ISG_OK;
 }
 
+static bool fft2_supported(int L);
+// untouched-tile skipping needs the two-step FFT on axis 0 and at most 64
+// tiles along it (one 64-bit mask per tile column)
+static bool traj_masked(const isg_plan* pl) {
+  const char* e = getenv("ISG_NO_TILE_MASK");
+  if (e && atoi(e)) return false;
+  int ts = pl->ktile.TS[0], lg = 0;
+  while ((1 << lg) < ts) ++lg;
+  return fft2_supported(pl->G[0]) && pl->ktile.nt[0] <= 64 && (1 << lg) == ts &&
+         (pl->ndim == 2 || (fft2_supported(pl->G[1]) && fft2_supported(pl->G[2]))) &&
+         (pl->ndim == 3 || fft2_supported(pl->G[1]));
+}
+
 static int kspread_chunk() {
   const char* e = getenv("ISG_SPREAD_CHUNK");
   const int v = e ? atoi(e) : 0;
@@ -1122,11 +1180,13 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
   std::vector<int> order(std::max(1, cnt[ntiles]));
   for (int64_t j = 0; j < M; ++j) visit(j, [&](int t) { order[pos[t]++] = (int)j; });
   const int chunk = kspread_chunk();
+  const bool masked = traj_masked(pl);
   std::vector<KUnit> units;
   std::vector<KSplit> splits;
   int slots = 0;
   for (int t = 0; t < ntiles; ++t) {
     const int beg = cnt[t], c = cnt[t + 1] - cnt[t];
+    if (c == 0 && masked) continue;  // untouched tile: the axis-0 passes skip it
     if (c <= chunk) {
       units.push_back(KUnit{t, beg, c, -1});
     } else {
@@ -1138,7 +1198,19 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
   }
   // split units first: they are the longest
   std::stable_sort(units.begin(), units.end(), [](const KUnit& a, const KUnit& b) { return a.count > b.count; });
+  if (units.empty()) units.push_back(KUnit{0, 0, 0, -1});  // keep the launch non-empty
   tr->M = M;
+  if (masked) {
+    const int ncols = nd == 3 ? pl->ktile.nt[1] * pl->ktile.nt[2] : pl->ktile.nt[1];
+    std::vector<uint64_t> cm(ncols, 0ull);
+    for (int t = 0; t < ntiles; ++t) {
+      if (cnt[t + 1] == cnt[t]) continue;
+      const int t0 = t / ncols, col = t - t0 * ncols;
+      cm[col] |= 1ull << t0;
+    }
+    tr->colmask = (uint64_t*)dmalloc(pl, sizeof(uint64_t) * ncols);
+    HIP_OK(hipMemcpy(tr->colmask, cm.data(), sizeof(uint64_t) * ncols, hipMemcpyHostToDevice));
+  }
   tr->taps = (KTap*)dmalloc(pl, sizeof(KTap) * taps.size());
   tr->order = (int*)dmalloc(pl, sizeof(int) * order.size());
   tr->units = (KUnit*)dmalloc(pl, sizeof(KUnit) * units.size());
@@ -1314,6 +1386,7 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
   }
   isg_status st = guarded(pl, [&]() -> isg_status {
     HIP_OK(hipGetDevice(&pl->device));
+    HIP_OK(hipDeviceGetAttribute(&pl->ncu, hipDeviceAttributeMultiprocessorCount, pl->device));
     // deapodization tables
     for (int i = 0; i < pl->ndim; ++i) {
       const int n = pl->n[i], G = pl->G[i];
@@ -1457,7 +1530,7 @@ isg_status isg_traj_create(isg_plan* pl, const float* k, int64_t M, isg_traj** o
 isg_status isg_traj_destroy(isg_traj* tr) {
   if (!tr) return ISG_OK;
   if (tr->plan) (void)hipStreamSynchronize(tr->plan->stream);
-  for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->units, (void*)tr->splits})
+  for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->units, (void*)tr->splits, (void*)tr->colmask})
     if (p) (void)hipFree(p);
   delete tr;
   return ISG_OK;
