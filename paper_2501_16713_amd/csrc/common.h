@@ -13,6 +13,13 @@ constexpr int kWidth = 4;   // kernel width in oversampled-grid cells
 constexpr int kAlpha = 2;   // oversampling factor
 constexpr int kPolyDeg = 17;
 
+// q = n / d for 0 <= n < 2^31 via a multiply-high (Granlund-Montgomery).
+struct FastDiv {
+  uint32_t d, m, s;
+  __device__ __forceinline__ uint32_t div(uint32_t n) const { return (__umulhi(n, m) + n) >> s; }
+  __device__ __forceinline__ uint32_t mod(uint32_t n) const { return n - div(n) * d; }
+};
+
 // ---------------------------------------------------------------------------
 // complex64 helpers
 // ---------------------------------------------------------------------------

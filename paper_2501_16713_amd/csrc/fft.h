@@ -28,12 +28,6 @@ constexpr int kFftThreads = 256;
 constexpr int kMaxPerThread = 32;   // L / threads-per-line must not exceed this
 constexpr int kMaxStages = 10;
 
-// q = n / d for 0 <= n < 2^31 via a multiply-high (Granlund-Montgomery).
-struct FastDiv {
-  uint32_t d, m, s;
-  __device__ __forceinline__ uint32_t div(uint32_t n) const { return (__umulhi(n, m) + n) >> s; }
-  __device__ __forceinline__ uint32_t mod(uint32_t n) const { return n - div(n) * d; }
-};
 
 struct LinePlan {
   int L;                    // transform length

@@ -197,7 +197,7 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
     float2* dst = lines + (al * g.nb + bl) * g.LS;
 #pragma unroll
     for (int k1 = 0; k1 < L1; ++k1) {
-      float2 w = tw[(n2 * k1) % L];
+      float2 w = tw[n2 * k1];  // n2 k1 <= (L2 - 1)(L1 - 1) < L
       w.y *= -(float)S;  // conjugate the table entry for the inverse sign
       dst[slot<L1, L2>(k1, n2)] = k1 == 0 ? v[0] : cmul(v[k1], w);
     }

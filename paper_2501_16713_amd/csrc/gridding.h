@@ -387,11 +387,15 @@ struct KTap {
 // Lane mapping: each wavefront holds spw = 64 / C samples and lane (s, c)
 // interpolates coil c of sample s, so the C coil values of every tap are one
 // contiguous run per sample and the output row y[j][*] is one coalesced store.
+// With vis_off != null the result of sample j is written to every spread
+// visit of the sample (y_visit[v][c] for v in vis[vis_off[j] .. vis_off[j+1]))
+// instead of y[j][c], which lets the spread read its inputs contiguously.
 template <int NDIM, int S>
 __global__ __launch_bounds__(kGridThreads) void kgather_kernel(const typename Elem<S>::T* __restrict__ grid,
                                                                const KTap* __restrict__ taps, int64_t M,
                                                                float2* __restrict__ y, int C, Dims dm,
-                                                               KbPoly kb) {
+                                                               KbPoly kb, const int* __restrict__ vis_off,
+                                                               const int* __restrict__ vis) {
   const int lane = threadIdx.x & 63;
   const int spw = 64 / C;
   const int sub = lane / C;
@@ -443,7 +447,22 @@ __global__ __launch_bounds__(kGridThreads) void kgather_kernel(const typename El
       acc.y = fmaf(w[0][t0], s.y, acc.y);
     }
   }
-  y[j * C + c] = acc;
+  if (vis_off) {
+    const int v1 = vis_off[j + 1];
+    for (int v = vis_off[j]; v < v1; ++v) y[(int64_t)vis[v] * C + c] = acc;
+  } else {
+    y[j * C + c] = acc;
+  }
+}
+
+// y_visit[v][c] = y[order[v]][c]: data in sample order to spread-visit order
+__global__ __launch_bounds__(kGridThreads) void visit_permute_kernel(const float2* __restrict__ y,
+                                                                     const int* __restrict__ order, int64_t nvis,
+                                                                     int C, float2* __restrict__ yv) {
+  const int64_t e = (int64_t)blockIdx.x * kGridThreads + threadIdx.x;
+  if (e >= nvis * C) return;
+  const int64_t v = e / C;
+  yv[e] = y[(int64_t)order[v] * C + (e - v * C)];
 }
 
 // k-space spread work unit: `count` samples of tile `tile` starting at
@@ -464,6 +483,7 @@ struct KTile {
   int vol;        // points per tile
   int S0, S1;     // plane strides
   int P;          // plane size (floats)
+  FastDiv rowdiv; // divides by TS_last * C (one tile row of the [G...][C] grid)
 };
 
 __device__ __forceinline__ void ktile_origin(int tile, const KTile& kt, int ndim, int lo[3]) {
@@ -503,16 +523,16 @@ constexpr int kSpreadBatch = 64;
 // Within a wave every lane updates distinct points, so plain LDS
 // read-modify-write is race free, and the summation order is fixed (the
 // spread is deterministic).  The workgroup has ceil(C/4) waves.
+// taps_v and yv are in visit order: the unit's samples are
+// taps_v[start .. start + count) and yv[(start ..)][C].
 template <int NDIM, int S>
 __global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ units, int nunits,
-                                                      const int* __restrict__ order,
-                                                      const KTap* __restrict__ taps,
-                                                      const float2* __restrict__ y, int C,
+                                                      const KTap* __restrict__ taps_v,
+                                                      const float2* __restrict__ yv, int C,
                                                       typename Elem<S>::T* __restrict__ grid,
                                                       float2* __restrict__ partial, Dims dm, KTile kt,
                                                       KbPoly kb, FastDiv cdiv) {
   extern __shared__ float accf[];  // [C][2][P] accumulator, then the staged coil values
-  __shared__ int st_j[kSpreadBatch];
   __shared__ int st_off[kSpreadBatch][3];
   __shared__ float st_w[kSpreadBatch][3][4];
   float2* st_y = (float2*)(accf + (size_t)C * 2 * kt.P);  // [kSpreadBatch][C]
@@ -535,10 +555,9 @@ __global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ 
   for (int b0 = 0; b0 < un.count; b0 += kSpreadBatch) {
     const int nb = min(kSpreadBatch, un.count - b0);
     __syncthreads();  // previous batch consumed (and the accumulator zeroed)
+    for (int e = threadIdx.x; e < nb * C; e += nthr) st_y[e] = yv[(int64_t)(un.start + b0) * C + e];
     if (threadIdx.x < nb) {
-      const int j = order[un.start + b0 + threadIdx.x];
-      const KTap tp = taps[j];
-      st_j[threadIdx.x] = j;
+      const KTap tp = taps_v[un.start + b0 + threadIdx.x];
 #pragma unroll
       for (int i = 0; i < NDIM; ++i) {
         float w[4];
@@ -550,11 +569,6 @@ __global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ 
         if (o < -dm.G[i] / 2) o += dm.G[i];
         st_off[threadIdx.x][i] = o;
       }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nb * C; e += nthr) {
-      const int s = (int)cdiv.div((uint32_t)e);
-      st_y[e] = y[(int64_t)st_j[s] * C + (e - s * C)];
     }
     __syncthreads();
     if (!active) continue;
@@ -595,36 +609,45 @@ __global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ 
     }
   }
   __syncthreads();
-  // write out: rows along the last axis are TS*C contiguous values
+  // write out, row by row: a tile row (fixed l0, l1) is TS_last * C
+  // contiguous values of the [G...][C] grid
   const int volC = kt.vol * C;
+  const int rowlen = kt.TS[NDIM - 1] * C;
+  const int nrows = kt.vol / kt.TS[NDIM - 1];
+  const FastDiv rdiv = kt.rowdiv;  // divides by rowlen
   for (int e = threadIdx.x; e < volC; e += nthr) {
-    const int pt = (int)cdiv.div((uint32_t)e);
-    const int cc = e - pt * C;
-    int l[3] = {0, 0, 0};
+    const int row = (int)rdiv.div((uint32_t)e);
+    const int within = e - row * rowlen;
+    const int l2 = (int)cdiv.div((uint32_t)within);  // point along the last axis
+    const int cc = within - l2 * C;
+    int pi, gl0, gl1 = 0;
     if constexpr (NDIM == 3) {
-      l[2] = pt % kt.TS[2];
-      const int r = pt / kt.TS[2];
-      l[1] = r % kt.TS[1];
-      l[0] = r / kt.TS[1];
+      const int l1 = row % kt.TS[1], l0 = row / kt.TS[1];
+      pi = l0 * kt.S0 + l1 * kt.S1 + l2;
+      gl0 = lo[0] + l0;
+      gl1 = lo[1] + l1;
     } else {
-      l[1] = pt % kt.TS[1];
-      l[0] = pt / kt.TS[1];
+      pi = row * kt.S0 + l2;
+      gl0 = lo[0] + row;
     }
-    const int pi = NDIM == 3 ? l[0] * kt.S0 + l[1] * kt.S1 + l[2] : l[0] * kt.S0 + l[1];
     const float2 v = make_float2(accf[(2 * cc) * kt.P + pi], accf[(2 * cc + 1) * kt.P + pi]);
     if (un.slot >= 0) {
+      // partial tiles keep the point-major layout e = point * C + coil
       partial[(int64_t)un.slot * volC + e] = v;
       continue;
     }
-    bool ok = true;
-    int64_t gi = 0;
-    for (int i = 0; i < NDIM; ++i) {
-      const int g = lo[i] + l[i];
-      ok = ok && g < dm.G[i];
-      gi = gi * dm.G[i] + g;
+    const int gl = lo[NDIM - 1] + l2;
+    bool ok = gl0 < dm.G[0] && gl < dm.G[NDIM - 1];
+    int64_t gi;
+    if constexpr (NDIM == 3) {
+      ok = ok && gl1 < dm.G[1];
+      gi = ((int64_t)gl0 * dm.G[1] + gl1) * dm.G[2] + gl;
+    } else {
+      gi = (int64_t)gl0 * dm.G[1] + gl;
     }
     if (ok) Elem<S>::store(grid + gi * C + cc, v);
   }
+  (void)nrows;
 }
 
 // sum the partial tiles of every split tile (fixed slot order) and write them

@@ -226,6 +226,10 @@ struct isg_traj {
   isg_plan* plan = nullptr;
   int64_t M = 0;
   uint64_t* colmask = nullptr;  // touched-tile masks (null: all tiles written)
+  int64_t nvis = 0;             // spread visits (sample, tile) in tile order
+  KTap* taps_v = nullptr;       // tap record of every visit
+  int* vis_off = nullptr;       // [M + 1]: visits of sample j ...
+  int* vis = nullptr;           // ... are vis[vis_off[j] .. vis_off[j + 1])
   KTap* taps = nullptr;
   int* order = nullptr;
   KUnit* units = nullptr;
@@ -902,8 +906,11 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
   }
 }
 
+// y[j][c] in sample order, or (to_visits) y[v][c] for every spread visit v
 template <int S>
-static void kgather_t(isg_plan* pl, const void* grid, const isg_traj* tr, float2* y) {
+static void kgather_t(isg_plan* pl, const void* grid, const isg_traj* tr, float2* y, bool to_visits) {
+  const int* voff = to_visits ? tr->vis_off : nullptr;
+  const int* vl = to_visits ? tr->vis : nullptr;
   auto grd = (const typename Elem<S>::T*)grid;
   Tick tick(pl, "kgather");
   const int spw = 64 / pl->C;  // samples per wavefront
@@ -911,15 +918,16 @@ static void kgather_t(isg_plan* pl, const void* grid, const isg_traj* tr, float2
   const unsigned nblk = (unsigned)((waves + kGridThreads / 64 - 1) / (kGridThreads / 64));
   if (pl->ndim == 3)
     hipLaunchKernelGGL((kgather_kernel<3, S>), dim3(nblk), dim3(kGridThreads), 0, pl->stream, grd, tr->taps, tr->M,
-                       y, pl->C, pl->dims, pl->kb);
+                       y, pl->C, pl->dims, pl->kb, voff, vl);
   else
     hipLaunchKernelGGL((kgather_kernel<2, S>), dim3(nblk), dim3(kGridThreads), 0, pl->stream, grd, tr->taps, tr->M,
-                       y, pl->C, pl->dims, pl->kb);
+                       y, pl->C, pl->dims, pl->kb, voff, vl);
   LAUNCH_OK();
 }
 
+// spread the visit-ordered data yv ([nvis][C]) of trajectory tr onto grid
 template <int S>
-static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* y, void* grid) {
+static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* yv, void* grid) {
   auto grd = (typename Elem<S>::T*)grid;
   const size_t lds = sizeof(float) * 2 * (size_t)pl->ktile.P * pl->C + sizeof(float2) * kSpreadBatch * pl->C;
   const size_t volC = (size_t)pl->ktile.vol * pl->C;
@@ -930,8 +938,8 @@ static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* y, void* g
     auto k = kspread_kernel<3, S>;
     allow_lds(k, lds);
     Tick tick(pl, "kspread");
-    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kthreads), lds, pl->stream, tr->units, tr->nunits, tr->order,
-                       tr->taps, y, pl->C, grd, part, pl->dims, pl->ktile, pl->kb, make_fastdiv(pl->C));
+    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kthreads), lds, pl->stream, tr->units, tr->nunits, tr->taps_v,
+                       yv, pl->C, grd, part, pl->dims, pl->ktile, pl->kb, make_fastdiv(pl->C));
     LAUNCH_OK();
     if (tr->nsplits) {
       Tick tick2(pl, "kspread_reduce");
@@ -943,8 +951,8 @@ static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* y, void* g
     auto k = kspread_kernel<2, S>;
     allow_lds(k, lds);
     Tick tick(pl, "kspread");
-    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kthreads), lds, pl->stream, tr->units, tr->nunits, tr->order,
-                       tr->taps, y, pl->C, grd, part, pl->dims, pl->ktile, pl->kb, make_fastdiv(pl->C));
+    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kthreads), lds, pl->stream, tr->units, tr->nunits, tr->taps_v,
+                       yv, pl->C, grd, part, pl->dims, pl->ktile, pl->kb, make_fastdiv(pl->C));
     LAUNCH_OK();
     if (tr->nsplits) {
       Tick tick2(pl, "kspread_reduce");
@@ -963,6 +971,20 @@ static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* y, void* g
       default: fn<kFP32>(__VA_ARGS__); break;                          \
     }                                                                  \
   } while (0)
+
+// data of one state in sample order -> spread-visit order (into ybuf)
+static float2* to_visit_order(isg_plan* pl, const isg_traj* tr, const float2* y) {
+  grow(pl, pl->ybuf, sizeof(float2) * (size_t)std::max<int64_t>(1, tr->nvis) * pl->C);
+  float2* yv = (float2*)pl->ybuf.p;
+  const int64_t n = tr->nvis * pl->C;
+  if (n > 0) {
+    Tick tick(pl, "visit_permute");
+    hipLaunchKernelGGL(visit_permute_kernel, dim3(blocks_for(n, kGridThreads)), dim3(kGridThreads), 0, pl->stream, y,
+                       tr->order, tr->nvis, pl->C, yv);
+    LAUNCH_OK();
+  }
+  return yv;
+}
 
 static void ensure_kspace(isg_plan* pl) {
   if (pl->kgrid) return;
@@ -989,7 +1011,7 @@ static void op_sense_forward(isg_plan* pl, int P, const float2* x, const isg_mot
   for (int p = 0; p < P; ++p) {
     warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
     STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, pl->kgrid, k[p]);
-    STORAGE_DISPATCH(pl, kgather_t, pl, pl->kgrid, k[p], y + off);
+    STORAGE_DISPATCH(pl, kgather_t, pl, pl->kgrid, k[p], y + off, false);
     off += k[p]->M * pl->C;
   }
 }
@@ -1000,7 +1022,8 @@ static void op_sense_adjoint(isg_plan* pl, int P, const float2* y, const isg_mot
   std::vector<const float2*> w(P);
   int64_t off = 0;
   for (int p = 0; p < P; ++p) {
-    STORAGE_DISPATCH(pl, kspread_t, pl, k[p], y + off, pl->kgrid);
+    const float2* yv = to_visit_order(pl, k[p], y + off);
+    STORAGE_DISPATCH(pl, kspread_t, pl, k[p], yv, pl->kgrid);
     STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, S, pl->wbuf + (int64_t)p * pl->N, k[p]);
     w[p] = pl->wbuf + (int64_t)p * pl->N;
     off += k[p]->M * pl->C;
@@ -1012,16 +1035,16 @@ static void op_sense_adjoint(isg_plan* pl, int P, const float2* y, const isg_mot
 static void op_normal(isg_plan* pl, int P, const float2* x, double lam, const isg_motion* const* d, const float2* S,
                       const isg_traj* const* k, float2* out) {
   ensure_kspace(pl);
-  int64_t Mmax = 0;
-  for (int p = 0; p < P; ++p) Mmax = std::max(Mmax, k[p]->M);
-  grow(pl, pl->ybuf, sizeof(float2) * (size_t)Mmax * pl->C);
+  int64_t Vmax = 1;
+  for (int p = 0; p < P; ++p) Vmax = std::max(Vmax, k[p]->nvis);
+  grow(pl, pl->ybuf, sizeof(float2) * (size_t)Vmax * pl->C);
   float2* y = (float2*)pl->ybuf.p;
   upsample(pl, x, pl->ugrid);
   std::vector<const float2*> w(P);
   for (int p = 0; p < P; ++p) {
     warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
     STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, pl->kgrid, k[p]);
-    STORAGE_DISPATCH(pl, kgather_t, pl, pl->kgrid, k[p], y);
+    STORAGE_DISPATCH(pl, kgather_t, pl, pl->kgrid, k[p], y, true);  // straight into visit order
     STORAGE_DISPATCH(pl, kspread_t, pl, k[p], y, pl->kgrid);
     STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, S, pl->wbuf + (int64_t)p * pl->N, k[p]);
     w[p] = pl->wbuf + (int64_t)p * pl->N;
@@ -1219,6 +1242,25 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
   tr->nsplits = (int)splits.size();
   tr->nslots = slots;
   HIP_OK(hipMemcpy(tr->taps, taps.data(), sizeof(KTap) * taps.size(), hipMemcpyHostToDevice));
+  {  // visit-ordered taps and, per sample, the list of its visits
+    const int64_t nvis = cnt[ntiles];
+    std::vector<KTap> tv(std::max<int64_t>(1, nvis));
+    std::vector<int> voff(M + 1, 0), vlist(std::max<int64_t>(1, nvis));
+    for (int64_t v = 0; v < nvis; ++v) {
+      tv[v] = taps[order[v]];
+      voff[order[v] + 1]++;
+    }
+    for (int64_t j = 0; j < M; ++j) voff[j + 1] += voff[j];
+    std::vector<int> vp(voff.begin(), voff.end() - 1);
+    for (int64_t v = 0; v < nvis; ++v) vlist[vp[order[v]]++] = (int)v;
+    tr->nvis = nvis;
+    tr->taps_v = (KTap*)dmalloc(pl, sizeof(KTap) * tv.size());
+    tr->vis_off = (int*)dmalloc(pl, sizeof(int) * voff.size());
+    tr->vis = (int*)dmalloc(pl, sizeof(int) * vlist.size());
+    HIP_OK(hipMemcpy(tr->taps_v, tv.data(), sizeof(KTap) * tv.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(tr->vis_off, voff.data(), sizeof(int) * voff.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(tr->vis, vlist.data(), sizeof(int) * vlist.size(), hipMemcpyHostToDevice));
+  }
   HIP_OK(hipMemcpy(tr->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
   HIP_OK(hipMemcpy(tr->units, units.data(), sizeof(KUnit) * units.size(), hipMemcpyHostToDevice));
   if (!splits.empty())
@@ -1384,6 +1426,7 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
     while (P % 16 != 1) ++P;
     pl->ktile.P = P;
   }
+  pl->ktile.rowdiv = make_fastdiv((uint32_t)(pl->ktile.TS[pl->ndim - 1] * pl->C));
   isg_status st = guarded(pl, [&]() -> isg_status {
     HIP_OK(hipGetDevice(&pl->device));
     HIP_OK(hipDeviceGetAttribute(&pl->ncu, hipDeviceAttributeMultiprocessorCount, pl->device));
@@ -1530,7 +1573,8 @@ isg_status isg_traj_create(isg_plan* pl, const float* k, int64_t M, isg_traj** o
 isg_status isg_traj_destroy(isg_traj* tr) {
   if (!tr) return ISG_OK;
   if (tr->plan) (void)hipStreamSynchronize(tr->plan->stream);
-  for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->units, (void*)tr->splits, (void*)tr->colmask})
+  for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->units, (void*)tr->splits, (void*)tr->colmask,
+                  (void*)tr->taps_v, (void*)tr->vis_off, (void*)tr->vis})
     if (p) (void)hipFree(p);
   delete tr;
   return ISG_OK;
