@@ -137,6 +137,10 @@ isg_status isg_motion_destroy(isg_motion* motion);
 isg_status isg_traj_create(isg_plan* plan, const float* k, int64_t M, isg_traj** traj);
 isg_status isg_traj_destroy(isg_traj* traj);
 isg_status isg_traj_count(const isg_traj* traj, int64_t* M);
+/* Spread bookkeeping of a prepared trajectory: the number of (sample, tile)
+ * visits, of k-space spread tiles any sample touches, and of grid points per
+ * tile (for traffic accounting). */
+isg_status isg_traj_info(const isg_traj* traj, int64_t* nvisits, int64_t* ntiles, int64_t* tile_points);
 
 /* y = T_d x, forward image-space gridding (Eq. 9).  x, y: device complex64
  * images; out-of-place (x != y). */
@@ -169,6 +173,17 @@ isg_status isg_sense_adjoint(isg_plan* plan, int nphases, const void* y,
 isg_status isg_normal(isg_plan* plan, int nphases, const void* x, double lambda,
                       const isg_motion* const* d, const void* S,
                       const isg_traj* const* k, void* out);
+
+/* Gradients of the data term L = sum_p 1/2 ||A_p x - y_p||^2 given the
+ * residual r = A x - y (device, packed like y):
+ *   grad_x = sum_p A_p^H r_p                                   (complex64 [n...])
+ *   grad_d[p][i][v] = Re(conj(v_p[v]) * d(T_{d_p} x)[v] / d d_{p,i}[v])
+ *       with v_p = sum_c conj(S_c) . G_p^H r_{p,c}             (float32 [P][ndim][n...])
+ * by the chain rule through the linear maps S and G_p.  Either output may
+ * be NULL (not computed), not both.  grad_x != x. */
+isg_status isg_sense_grad(isg_plan* plan, int nphases, const void* x, const isg_motion* const* d,
+                          const void* S, const isg_traj* const* k, const void* r, void* grad_x,
+                          float* grad_d);
 
 /* Conjugate gradients on (sum_p A_p^H A_p + lambda I) x = sum_p A_p^H y_p:
  * exactly `iters` Hestenes-Stiefel iterations from the x passed in (x is

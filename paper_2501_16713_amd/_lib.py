@@ -34,12 +34,14 @@ SIGNATURES = {
     "isg_traj_create": (C.c_int, [_p, _p, _i64, C.POINTER(_p)]),
     "isg_traj_destroy": (C.c_int, [_p]),
     "isg_traj_count": (C.c_int, [_p, C.POINTER(_i64)]),
+    "isg_traj_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)]),
     "isg_warp": (C.c_int, [_p, _p, _p, _p]),
     "isg_warp_adjoint": (C.c_int, [_p, _p, _p, _p]),
     "isg_warp_grad_d": (C.c_int, [_p, _p, _p, _p, _p]),
     "isg_sense_forward": (C.c_int, [_p, C.c_int, _p, _p, _p, _p, _p]),
     "isg_sense_adjoint": (C.c_int, [_p, C.c_int, _p, _p, _p, _p, _p]),
     "isg_normal": (C.c_int, [_p, C.c_int, _p, C.c_double, _p, _p, _p, _p]),
+    "isg_sense_grad": (C.c_int, [_p, C.c_int, _p, _p, _p, _p, _p, _p, _p]),
     "isg_cg_solve": (C.c_int, [_p, C.c_int, _p, _p, _p, _p, C.c_double, C.c_int, _p,
                                C.POINTER(C.c_double)]),
 }

@@ -227,6 +227,7 @@ struct isg_traj {
   int64_t M = 0;
   uint64_t* colmask = nullptr;  // touched-tile masks (null: all tiles written)
   int64_t nvis = 0;             // spread visits (sample, tile) in tile order
+  int64_t ntouched = 0;         // spread tiles any sample touches
   KTap* taps_v = nullptr;       // tap record of every visit
   int* vis_off = nullptr;       // [M + 1]: visits of sample j ...
   int* vis = nullptr;           // ... are vis[vis_off[j] .. vis_off[j + 1])
@@ -1207,8 +1208,10 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
   std::vector<KUnit> units;
   std::vector<KSplit> splits;
   int slots = 0;
+  tr->ntouched = 0;
   for (int t = 0; t < ntiles; ++t) {
     const int beg = cnt[t], c = cnt[t + 1] - cnt[t];
+    if (c > 0) tr->ntouched++;
     if (c == 0 && masked) continue;  // untouched tile: the axis-0 passes skip it
     if (c <= chunk) {
       units.push_back(KUnit{t, beg, c, -1});
@@ -1580,6 +1583,14 @@ isg_status isg_traj_destroy(isg_traj* tr) {
   return ISG_OK;
 }
 
+isg_status isg_traj_info(const isg_traj* tr, int64_t* nvisits, int64_t* ntiles, int64_t* tile_points) {
+  if (!tr || !nvisits || !ntiles || !tile_points) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  *nvisits = tr->nvis;
+  *ntiles = tr->ntouched;
+  *tile_points = tr->plan->ktile.vol;
+  return ISG_OK;
+}
+
 isg_status isg_traj_count(const isg_traj* tr, int64_t* M) {
   if (!tr || !M) return fail(ISG_ERR_INVALID_ARG, "traj and M must not be NULL");
   *M = tr->M;
@@ -1669,6 +1680,49 @@ isg_status isg_normal(isg_plan* pl, int P, const void* x, double lambda, const i
   if (st) return st;
   return guarded(pl, [&]() {
     op_normal(pl, P, (const float2*)x, lambda, d, (const float2*)S, k, (float2*)out);
+    return ISG_OK;
+  });
+}
+
+isg_status isg_sense_grad(isg_plan* pl, int P, const void* x, const isg_motion* const* d, const void* S,
+                          const isg_traj* const* k, const void* r, void* grad_x, float* grad_d) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!x || !S || !r || (!grad_x && !grad_d)) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (grad_x == x) return fail(ISG_ERR_INVALID_ARG, "grad_x must differ from x");
+  st = check_phases(pl, P, d, k);
+  if (st) return st;
+  return guarded(pl, [&]() {
+    ensure_kspace(pl);
+    const float2* Sm = (const float2*)S;
+    // u = the upsampled x, needed by every d-gradient (before the spread reuses ugrid)
+    if (grad_d) upsample(pl, (const float2*)x, pl->ugrid);
+    std::vector<const float2*> w(P);
+    int64_t off = 0;
+    for (int p = 0; p < P; ++p) {
+      // v_p = sum_c conj(S_c) G_p^H r_{p,c}
+      const float2* yv = to_visit_order(pl, k[p], (const float2*)r + off);
+      STORAGE_DISPATCH(pl, kspread_t, pl, k[p], yv, pl->kgrid);
+      float2* v = pl->wbuf + (int64_t)p * pl->N;
+      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, Sm, v, k[p]);
+      w[p] = v;
+      if (grad_d) {
+        Tick tick(pl, "warp_grad");
+        float* gd = grad_d + (int64_t)p * pl->ndim * pl->N;
+        if (pl->ndim == 3)
+          hipLaunchKernelGGL(warp_grad_kernel<3>, dim3(blocks_for(pl->N, kGridThreads)), dim3(kGridThreads), 0,
+                             pl->stream, pl->ugrid, d[p]->d, v, gd, pl->dims, pl->kb);
+        else
+          hipLaunchKernelGGL(warp_grad_kernel<2>, dim3(blocks_for(pl->N, kGridThreads)), dim3(kGridThreads), 0,
+                             pl->stream, pl->ugrid, d[p]->d, v, gd, pl->dims, pl->kb);
+        LAUNCH_OK();
+      }
+      off += k[p]->M * pl->C;
+    }
+    if (grad_x) {
+      warp_spread(pl, P, d, w.data(), pl->ugrid);
+      upsample_adjoint(pl, pl->ugrid, (float2*)grad_x);
+    }
     return ISG_OK;
   });
 }

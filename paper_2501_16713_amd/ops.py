@@ -79,6 +79,13 @@ class Traj:
         check(plan.lib.isg_traj_create(plan.handle, _ptr(k), self.M, C.byref(h)))
         self.handle = h
 
+    def info(self) -> dict:
+        """{"visits": (sample, tile) spread visits, "tiles": touched spread
+        tiles, "tile_points": grid points per tile}"""
+        a, b, c = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+        check(self.plan.lib.isg_traj_info(self.handle, C.byref(a), C.byref(b), C.byref(c)))
+        return {"visits": a.value, "tiles": b.value, "tile_points": c.value}
+
     def close(self):
         if getattr(self, "handle", None):
             self.plan.lib.isg_traj_destroy(self.handle)
@@ -248,6 +255,21 @@ class Plan:
         self._sync_stream()
         check(self.lib.isg_normal(self.handle, P, _ptr(x), float(lam), dm, _ptr(S), km, _ptr(out)))
         return out
+
+    def sense_grad(self, x, motions, S, trajs, r, want_x: bool = True, want_d: bool = True):
+        """Gradients of sum_p 1/2 ||A_p x - y_p||^2 from the residual r = A x - y:
+        (grad_x complex64 [*shape] or None, grad_d float32 [P][ndim][*shape] or None)."""
+        x = self._image(x)
+        S = _require(S, torch.complex64, (self.ncoils,) + self.shape, "S")
+        P, dm, km = self._handles(motions, trajs)
+        r = _require(r, torch.complex64, (self.data_rows(trajs), self.ncoils), "r")
+        gx = self._empty_image() if want_x else None
+        gd = torch.empty((P, self.ndim) + self.shape, dtype=torch.float32, device=self.device) if want_d else None
+        self._sync_stream()
+        check(self.lib.isg_sense_grad(self.handle, P, _ptr(x), dm, _ptr(S), km, _ptr(r),
+                                      _ptr(gx) if gx is not None else None,
+                                      _ptr(gd) if gd is not None else None))
+        return gx, gd
 
     def cg_solve(self, y, motions, S, trajs, lam: float, iters: int, x0=None):
         """CG on (sum_p A_p^H A_p + lam I) x = sum_p A_p^H y_p; returns
