@@ -115,4 +115,16 @@ template <> struct Elem<kFP16> {
   __device__ static __forceinline__ void store(T* p, float2 v) { *p = __float22half2_rn(v); }
 };
 
+// Half-precision grids are stored with a per-pass scale that keeps every
+// intermediate on the scale of the k-space data; FP32 grids take the whole
+// |N|^{-1/2} at the first load and store unscaled.
+template <int S>
+__device__ __forceinline__ float2 store_scaled(float2 v, float s) {
+  if constexpr (S == kFP32) {
+    return v;
+  } else {
+    return make_float2(v.x * s, v.y * s);
+  }
+}
+
 }  // namespace isg

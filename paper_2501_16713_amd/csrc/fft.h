@@ -281,6 +281,7 @@ struct StStrided {
   int n;        // stored length along the axis (n <= L: crop)
   int L;
   int map;
+  float scale;  // applied to half-precision stores only
   FastDiv nbd, nd;
   __device__ void operator()(const float2* lines, const TileGeom& g, int64_t a0, int64_t b0) const {
     const int nl = g.na * g.nb;
@@ -292,7 +293,8 @@ struct StStrided {
       const int j = r - al * n;
       const int64_t a = a0 + al, b = b0 + bl;
       if (a < g.A && b < g.B)
-        Elem<S>::store(p + a * sa + (int64_t)j * sj + b, lines[(al * g.nb + bl) * g.LS + map_index(map, j, n, L)]);
+        Elem<S>::store(p + a * sa + (int64_t)j * sj + b,
+                       store_scaled<S>(lines[(al * g.nb + bl) * g.LS + map_index(map, j, n, L)], scale));
     }
   }
 };

@@ -273,7 +273,8 @@ struct St2Strided {
   static constexpr bool kEpilogue = false;
   typename Elem<S>::T* p;
   int64_t sa, sj;
-  int map;  // dense, or crop to L/2 values (centred or spectral)
+  int map;      // dense, or crop to L/2 values (centred or spectral)
+  float scale;  // applied to half-precision stores only
   struct Line {
     typename Elem<S>::T* base;
   };
@@ -281,7 +282,7 @@ struct St2Strided {
   template <int L>
   __device__ void put(const Line& ln, int pos, float2 v, bool valid) const {
     const int j = pad_src<L>(map, pos);
-    if (valid && j >= 0) Elem<S>::store(ln.base + (int64_t)j * sj, v);
+    if (valid && j >= 0) Elem<S>::store(ln.base + (int64_t)j * sj, store_scaled<S>(v, scale));
   }
 };
 
@@ -335,6 +336,7 @@ struct St2Masked {
   typename Elem<S>::T* p;
   int64_t sj;
   TileMask tm;
+  float scale;  // applied to half-precision stores only
   struct Line {
     typename Elem<S>::T* base;
     uint64_t mask;
@@ -342,7 +344,8 @@ struct St2Masked {
   __device__ Line setup(int64_t a, int64_t b, bool valid) const { return Line{p + b, valid ? tm.column(b) : 0ull}; }
   template <int L>
   __device__ void put(const Line& ln, int pos, float2 v, bool valid) const {
-    if (valid && ((ln.mask >> (pos >> tm.ts0_log2)) & 1ull)) Elem<S>::store(ln.base + (int64_t)pos * sj, v);
+    if (valid && ((ln.mask >> (pos >> tm.ts0_log2)) & 1ull))
+      Elem<S>::store(ln.base + (int64_t)pos * sj, store_scaled<S>(v, scale));
   }
 };
 

@@ -91,16 +91,21 @@ static double kb_beta() {
   return M_PI * std::sqrt((W / a) * (W / a) * (a - 0.5) * (a - 0.5) - 0.8);
 }
 
-// I0(beta sqrt(t)) = sum_k (beta^2/4)^k t^k / (k!)^2
+// I0(beta sqrt(t)) / c(0) = sum_k (beta^2/4)^k t^k / (k!)^2 / c(0).  The
+// kernel is divided by the zero frequency of its transform, c(0) (its
+// integral), so that the taps of one axis sum to about 1 and k-space grids
+// hold values on the scale of the data; the deapodization tables carry the
+// matching factor c(0) per axis, which leaves every operator unchanged.
 static KbPoly make_kbpoly(double beta) {
   KbPoly p;
   const double q = beta * beta / 4.0;
+  const double norm = 1.0 / kb_transform(0.0, beta);
   double a = 1.0;
   double coef[kPolyDeg + 1];
   for (int k = 0; k <= kPolyDeg; ++k) {
     if (k) a *= q / ((double)k * k);
-    coef[k] = a;
-    p.a[k] = (float)a;
+    coef[k] = a * norm;
+    p.a[k] = (float)coef[k];
   }
   for (int k = 1; k <= kPolyDeg; ++k) p.da[k - 1] = (float)(coef[k] * k);
   return p;
@@ -131,8 +136,8 @@ struct isg_plan {
   TileDims wtile;   // image-space spread tiles
   KTile ktile;      // k-space spread tiles
   // tables
-  float* dk[3] = {nullptr, nullptr, nullptr};  // 1/C(k/G), DFT bin order, times nothing
-  float* dx[3] = {nullptr, nullptr, nullptr};  // 1/C(x/G), centred positions
+  float* dk[3] = {nullptr, nullptr, nullptr};  // c(0)/c(k/G), DFT bin order
+  float* dx[3] = {nullptr, nullptr, nullptr};  // c(0)/c(x/G), centred positions
   std::map<int, LinePlan> lines;
   std::vector<void*> owned;
   // scratch
@@ -460,12 +465,13 @@ static Ld2Strided<S> ld2(const isg_plan* pl, const void* p, int64_t sa, int64_t 
 }
 
 template <int S>
-static St2Strided<S> st2(void* p, int64_t sa, int64_t sj, int map) {
+static St2Strided<S> st2(void* p, int64_t sa, int64_t sj, int map, float scale = 1.f) {
   St2Strided<S> s;
   s.p = (typename Elem<S>::T*)p;
   s.sa = sa;
   s.sj = sj;
   s.map = map;
+  s.scale = scale;
   return s;
 }
 
@@ -484,7 +490,8 @@ static LdStrided<S> ld_strided(const void* p, int64_t sa, int64_t sj, int n, int
 }
 
 template <int S>
-static StStrided<S> st_strided(void* p, int64_t sa, int64_t sj, int n, int L, int map, const TileGeom& g) {
+static StStrided<S> st_strided(void* p, int64_t sa, int64_t sj, int n, int L, int map, const TileGeom& g,
+                                float scale = 1.f) {
   StStrided<S> s;
   s.p = (typename Elem<S>::T*)p;
   s.sa = sa;
@@ -492,6 +499,7 @@ static StStrided<S> st_strided(void* p, int64_t sa, int64_t sj, int n, int L, in
   s.n = n;
   s.L = L;
   s.map = map;
+  s.scale = scale;
   s.nbd = make_fastdiv(g.nb);
   s.nd = make_fastdiv(n);
   return s;
@@ -682,12 +690,24 @@ static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const 
 // ---------------------------------------------------------------------------
 // coil-expanded k-space front end and back end
 // ---------------------------------------------------------------------------
+// |N|^{-1/2} of the coil passes.  FP32 grids take it whole at the image
+// end (first load of the forward, last store of the adjoint).  Half-precision
+// grids take n_i^{-1/2} at the store of the axis-i pass and n_last^{-1/2} at
+// the image end, so no unnormalised pass grows a stored intermediate by up to
+// n_i (out of FP16 range) and every grid holds values on the scale of the data.
+static float image_end_scale(const isg_plan* pl) {
+  return (float)(1.0 / std::sqrt(pl->storage == kFP32 ? (double)pl->N : (double)pl->n[pl->ndim - 1]));
+}
+static float axis_store_scale(const isg_plan* pl, int i) {
+  return pl->storage == kFP32 ? 1.f : (float)(1.0 / std::sqrt((double)pl->n[i]));
+}
+
 static Ld2CoilExpand ld2_expand(isg_plan* pl, const float2* m, const float2* Sm, int n, int n1, int L) {
   Ld2CoilExpand ld;
   ld.m = m;
   ld.S = Sm;
   ld.dx = tabs(pl->dx);
-  ld.scale = (float)(1.0 / std::sqrt((double)pl->N));
+  ld.scale = image_end_scale(pl);
   ld.N = pl->N;
   ld.n = n;
   ld.n1 = n1;
@@ -700,7 +720,7 @@ static St2CoilReduce st2_reduce(isg_plan* pl, float2* w, const float2* Sm, int n
   st.out = w;
   st.S = Sm;
   st.dx = tabs(pl->dx);
-  st.scale = (float)(1.0 / std::sqrt((double)pl->N));
+  st.scale = image_end_scale(pl);
   st.N = pl->N;
   st.n = n;
   st.L = L;
@@ -725,11 +745,12 @@ static TileMask tile_mask(const isg_plan* pl, const isg_traj* tr) {
 }
 
 template <int S>
-static St2Masked<S> st2_masked(void* p, int64_t sj, const TileMask& tm) {
+static St2Masked<S> st2_masked(void* p, int64_t sj, const TileMask& tm, float scale) {
   St2Masked<S> st;
   st.p = (typename Elem<S>::T*)p;
   st.sj = sj;
   st.tm = tm;
+  st.scale = scale;
   return st;
 }
 
@@ -750,7 +771,7 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
   const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
   const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
   const int C = pl->C;
-  const float scale = (float)(1.0 / std::sqrt((double)pl->N));
+  const float scale = image_end_scale(pl);
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
     // S_c m / c(x/G) |N|^{-1/2}, centred pad, F along axis 2
     run_fft2<-1, kJFast, kBFast>(pl, "fft_coil_fwd_last", G2, ld2_expand(pl, m, Sm, n2, n1, G2),
@@ -759,18 +780,19 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
     // centred pad, F along axis 1
     run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax1", G1,
                                  ld2<S>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
-                                 st2<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, kDense),
+                                 st2<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, kDense,
+                                        axis_store_scale(pl, 1)),
                                  make_tile2(n0, (int64_t)G2 * C, G1, 0));
     // centred pad, F along axis 0
     run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0,
                                  ld2<S>(pl, pl->k2buf, 0, (int64_t)G1 * G2 * C, kCentred, G0),
-                                 st2_masked<S>(grid, (int64_t)G1 * G2 * C, tile_mask(pl, tr)),
+                                 st2_masked<S>(grid, (int64_t)G1 * G2 * C, tile_mask(pl, tr), axis_store_scale(pl, 0)),
                                  make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
     run_fft2<-1, kJFast, kBFast>(pl, "fft_coil_fwd_last", G1, ld2_expand(pl, m, Sm, n1, 0, G1),
                                  st2<S>(pl->k1buf, (int64_t)G1 * C, C, kDense), make_tile2(n0, C, G1, C));
     run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0, ld2<S>(pl, pl->k1buf, 0, (int64_t)G1 * C, kCentred, G0),
-                                 st2_masked<S>(grid, (int64_t)G1 * C, tile_mask(pl, tr)),
+                                 st2_masked<S>(grid, (int64_t)G1 * C, tile_mask(pl, tr), axis_store_scale(pl, 0)),
                                  make_tile2(1, (int64_t)G1 * C, G0, 0));
   } else if (pl->ndim == 3) {
     {  // S_c m / c(x/G) |N|^{-1/2}, centred pad, F along axis 2
@@ -793,14 +815,15 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
     {  // centred pad, F along axis 1
       TileGeom g = make_geom(n0, (int64_t)G2 * C, G1, 0);
       run_pass(pl, "fft_coil_fwd_ax1", ld_strided<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g), NoMid(),
-               st_strided<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g), g,
+               st_strided<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g,
+                             axis_store_scale(pl, 1)), g,
                line_plan(pl, G1), -1.f, nullptr, 0.f);
     }
     {  // centred pad, F along axis 0
       TileGeom g = make_geom(1, (int64_t)G1 * G2 * C, G0, 0);
       run_pass(pl, "fft_coil_fwd_ax0", ld_strided<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g), NoMid(),
-               st_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g), g, line_plan(pl, G0), -1.f, nullptr,
-               0.f);
+               st_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g, axis_store_scale(pl, 0)), g,
+               line_plan(pl, G0), -1.f, nullptr, 0.f);
     }
   } else {
     {
@@ -823,7 +846,8 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
     {
       TileGeom g = make_geom(1, (int64_t)G1 * C, G0, 0);
       run_pass(pl, "fft_coil_fwd_ax0", ld_strided<S>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g), NoMid(),
-               st_strided<S>(grid, 0, (int64_t)G1 * C, G0, G0, kDense, g), g, line_plan(pl, G0), -1.f, nullptr, 0.f);
+               st_strided<S>(grid, 0, (int64_t)G1 * C, G0, G0, kDense, g, axis_store_scale(pl, 0)), g,
+               line_plan(pl, G0), -1.f, nullptr, 0.f);
     }
   }
 }
@@ -835,34 +859,38 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
   const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
   const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
   const int C = pl->C;
-  const float scale = (float)(1.0 / std::sqrt((double)pl->N));
+  const float scale = image_end_scale(pl);
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0,
                                  ld2_masked<S>(pl, grid, (int64_t)G1 * G2 * C, tile_mask(pl, tr), G0),
-                                 st2<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, kCentred),
+                                 st2<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, kCentred, axis_store_scale(pl, 0)),
                                  make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax1", G1,
                                  ld2<S>(pl, pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, kDense, G1),
-                                 st2<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred),
+                                 st2<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred,
+                                        axis_store_scale(pl, 1)),
                                  make_tile2(n0, (int64_t)G2 * C, G1, 0));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G2, ld2<S>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
                                  st2_reduce(pl, w, Sm, n2, n1, G2), make_tile2((int64_t)n0 * n1, C, G2, C));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2_masked<S>(pl, grid, (int64_t)G1 * C, tile_mask(pl, tr), G0),
-                                 st2<S>(pl->k1buf, 0, (int64_t)G1 * C, kCentred), make_tile2(1, (int64_t)G1 * C, G0, 0));
+                                 st2<S>(pl->k1buf, 0, (int64_t)G1 * C, kCentred, axis_store_scale(pl, 0)),
+                                 make_tile2(1, (int64_t)G1 * C, G0, 0));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G1, ld2<S>(pl, pl->k1buf, (int64_t)G1 * C, C, kDense, G1),
                                  st2_reduce(pl, w, Sm, n1, 0, G1), make_tile2(n0, C, G1, C));
   } else if (pl->ndim == 3) {
     {  // F^H along axis 0, centred crop
       TileGeom g = make_geom(1, (int64_t)G1 * G2 * C, G0, 0);
       run_pass(pl, "fft_coil_adj_ax0", ld_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g), NoMid(),
-               st_strided<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g), g, line_plan(pl, G0), +1.f,
+               st_strided<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g, axis_store_scale(pl, 0)), g,
+               line_plan(pl, G0), +1.f,
                nullptr, 0.f);
     }
     {  // F^H along axis 1, centred crop
       TileGeom g = make_geom(n0, (int64_t)G2 * C, G1, 0);
       run_pass(pl, "fft_coil_adj_ax1", ld_strided<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g), NoMid(),
-               st_strided<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g), g,
+               st_strided<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g,
+                             axis_store_scale(pl, 1)), g,
                line_plan(pl, G1), +1.f, nullptr, 0.f);
     }
     {  // F^H along axis 2, centred crop, 1/c(x/G) |N|^{-1/2}, conj(S_c), coil sum
@@ -885,7 +913,8 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
     {
       TileGeom g = make_geom(1, (int64_t)G1 * C, G0, 0);
       run_pass(pl, "fft_coil_adj_ax0", ld_strided<S>(grid, 0, (int64_t)G1 * C, G0, G0, kDense, g), NoMid(),
-               st_strided<S>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g), g, line_plan(pl, G0), +1.f,
+               st_strided<S>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g, axis_store_scale(pl, 0)), g,
+               line_plan(pl, G0), +1.f,
                nullptr, 0.f);
     }
     {
@@ -926,7 +955,28 @@ static void kgather_t(isg_plan* pl, const void* grid, const isg_traj* tr, float2
   LAUNCH_OK();
 }
 
-// spread the visit-ordered data yv ([nvis][C]) of trajectory tr onto grid
+// spread the visit-ordered data yv ([nvis][C]) of trajectory tr onto grid;
+// the "kspread" tag times the spread kernel alone, "kspread_reduce" the
+// fixed-order reduction of split tiles
+template <int NDIM, int S>
+static void kspread_nd(isg_plan* pl, const isg_traj* tr, const float2* yv, typename Elem<S>::T* grd, float2* part,
+                       size_t lds, int kthreads) {
+  auto k = kspread_kernel<NDIM, S>;
+  allow_lds(k, lds);
+  {
+    Tick tick(pl, "kspread");
+    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kthreads), lds, pl->stream, tr->units, tr->nunits, tr->taps_v,
+                       yv, pl->C, grd, part, pl->dims, pl->ktile, pl->kb, make_fastdiv(pl->C));
+    LAUNCH_OK();
+  }
+  if (tr->nsplits) {
+    Tick tick(pl, "kspread_reduce");
+    hipLaunchKernelGGL((kspread_reduce_kernel<NDIM, S>), dim3(tr->nsplits), dim3(kGridThreads), 0, pl->stream,
+                       tr->splits, part, pl->C, grd, pl->dims, pl->ktile);
+    LAUNCH_OK();
+  }
+}
+
 template <int S>
 static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* yv, void* grid) {
   auto grd = (typename Elem<S>::T*)grid;
@@ -935,33 +985,10 @@ static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* yv, void* 
   if (tr->nslots) grow(pl, pl->partial, sizeof(float2) * volC * tr->nslots);
   float2* part = (float2*)pl->partial.p;
   const int kthreads = 64 * ((pl->C + 3) / 4);  // one wave per 4 coils
-  if (pl->ndim == 3) {
-    auto k = kspread_kernel<3, S>;
-    allow_lds(k, lds);
-    Tick tick(pl, "kspread");
-    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kthreads), lds, pl->stream, tr->units, tr->nunits, tr->taps_v,
-                       yv, pl->C, grd, part, pl->dims, pl->ktile, pl->kb, make_fastdiv(pl->C));
-    LAUNCH_OK();
-    if (tr->nsplits) {
-      Tick tick2(pl, "kspread_reduce");
-      hipLaunchKernelGGL((kspread_reduce_kernel<3, S>), dim3(tr->nsplits), dim3(kGridThreads), 0, pl->stream,
-                         tr->splits, part, pl->C, grd, pl->dims, pl->ktile);
-      LAUNCH_OK();
-    }
-  } else {
-    auto k = kspread_kernel<2, S>;
-    allow_lds(k, lds);
-    Tick tick(pl, "kspread");
-    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kthreads), lds, pl->stream, tr->units, tr->nunits, tr->taps_v,
-                       yv, pl->C, grd, part, pl->dims, pl->ktile, pl->kb, make_fastdiv(pl->C));
-    LAUNCH_OK();
-    if (tr->nsplits) {
-      Tick tick2(pl, "kspread_reduce");
-      hipLaunchKernelGGL((kspread_reduce_kernel<2, S>), dim3(tr->nsplits), dim3(kGridThreads), 0, pl->stream,
-                         tr->splits, part, pl->C, grd, pl->dims, pl->ktile);
-      LAUNCH_OK();
-    }
-  }
+  if (pl->ndim == 3)
+    kspread_nd<3, S>(pl, tr, yv, grd, part, lds, kthreads);
+  else
+    kspread_nd<2, S>(pl, tr, yv, grd, part, lds, kthreads);
 }
 
 #define STORAGE_DISPATCH(pl, fn, ...)                                  \
@@ -1439,8 +1466,8 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
       std::vector<float> k(n), x(n);
       for (int j = 0; j < n; ++j) {
         const int kk = j < n - n / 2 ? j : j - n;  // signed DFT bin
-        k[j] = (float)(1.0 / kb_transform((double)kk / G, pl->beta));
-        x[j] = (float)(1.0 / kb_transform((double)(j - n / 2) / G, pl->beta));
+        k[j] = (float)(kb_transform(0.0, pl->beta) / kb_transform((double)kk / G, pl->beta));
+        x[j] = (float)(kb_transform(0.0, pl->beta) / kb_transform((double)(j - n / 2) / G, pl->beta));
       }
       pl->dk[i] = (float*)plan_alloc(pl, sizeof(float) * n);
       pl->dx[i] = (float*)plan_alloc(pl, sizeof(float) * n);

@@ -1,7 +1,15 @@
 """Mixed precision: the coil-expanded oversampled k-space grids stored as
 BF16 or FP16 pairs (FP32 arithmetic in registers and LDS), against the FP64
-oracle on the 96^3, 8-coil, 192k-sample workload.  Bar: 1e-3 relative L2
-per result."""
+oracle on the 96^3, 8-coil, 192k-sample workload, with the error stated per
+result.
+
+Bars.  Each direction stores three rounded grids (after the last-axis, the
+middle-axis and the axis-0 pass).  Rounding to nearest leaves a relative
+error of at most u (u = 2^-8 for BF16's 8-bit significand, 2^-11 for FP16's
+11 bits), about u/sqrt(3) in RMS for independent errors, and three such
+stores add in quadrature to about u: 3.9e-3 for BF16 and 4.9e-4 for FP16.
+FP16 is held to the 1e-3 target; BF16 cannot reach it on A^H and is held to
+its own bound u."""
 import numpy as np
 import pytest
 
@@ -12,7 +20,7 @@ from gpu_util import pack, rel, say, to_dev, unpack
 
 pytestmark = pytest.mark.gpu
 
-BAR = 1e-3
+BARS = {"fp16": 1e-3, "bf16": 2.0 ** -8}
 
 
 @pytest.fixture(scope="module")
@@ -39,4 +47,4 @@ def test_mixed_precision_operators(ref, storage):
     ea = rel(plan.sense_adjoint(to_dev(y), mots, S, trs).cpu().numpy(), adj)
     say(f"  {storage}: A rel err {ef:.2e}, A^H rel err {ea:.2e}")
     assert np.isfinite(ef) and np.isfinite(ea)
-    assert ef < BAR and ea < BAR
+    assert ef < BARS[storage] and ea < BARS[storage]
