@@ -158,6 +158,13 @@ def main():
     es = 8 if args.storage == "fp32" else 4
     G = tuple(2 * n for n in w.shape)
     per_launch = stage_bytes(dominant, w.shape, G, w.ncoils, es)
+    if dominant in ("fft_coil_fwd_ax0", "fft_coil_adj_ax0"):
+        # these passes touch only the spread tiles some sample reaches
+        tot = 0
+        for t in trs:
+            info = t.info()
+            tot += info["tiles"] * info["tile_points"] * w.ncoils * es
+        per_launch = tot // len(trs) + w.shape[0] * G[1] * G[2] * w.ncoils * es
     if per_launch is None and dominant in ("kspread", "kgather"):
         # one launch per state: average over the states
         tot = 0

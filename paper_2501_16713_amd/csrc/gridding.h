@@ -473,16 +473,18 @@ struct KUnit {
   int tile, start, count, slot;
 };
 
-// Tile of the k-space spread.  The LDS accumulator is planar, one plane of
-// P floats per (coil, re/im); inside a plane the point (l0, l1, l2) sits at
-// l0 * S0 + l1 * S1 + l2.  S1 = T2 and S0 = 4 (mod 32) spread the 64 taps of
-// a sample over distinct banks, and P = 1 (mod 16) staggers the coil planes.
+// Tile of the k-space spread.  The LDS accumulator holds one plane of P
+// complex values per coil; inside a plane the point (l0, l1, l2) sits at
+// l0 * S0 + l1 * S1 + l2.  P = 4 (mod 16) puts the four coils of a wave on
+// distinct banks (2P = 8 mod 32 banks of 4 bytes), and within a coil the
+// lanes of one row step along l2, so a 16-lane group touches 32 distinct
+// banks.
 struct KTile {
   int TS[3];
   int nt[3];
   int vol;        // points per tile
-  int S0, S1;     // plane strides
-  int P;          // plane size (floats)
+  int S0, S1;     // plane strides (complex values)
+  int P;          // plane size (complex values)
   FastDiv rowdiv; // divides by TS_last * C (one tile row of the [G...][C] grid)
 };
 
@@ -494,37 +496,30 @@ __device__ __forceinline__ void ktile_origin(int tile, const KTile& kt, int ndim
   }
 }
 
-template <int NDIM>
-__device__ __forceinline__ int kplane_index(const KTile& kt, int pt) {
-  // point index (row-major over TS) -> planar index
-  if constexpr (NDIM == 3) {
-    const int l2 = pt % kt.TS[2];
-    const int r = pt / kt.TS[2];
-    const int l1 = r % kt.TS[1];
-    const int l0 = r / kt.TS[1];
-    return l0 * kt.S0 + l1 * kt.S1 + l2;
-  } else {
-    const int l1 = pt % kt.TS[1];
-    const int l0 = pt / kt.TS[1];
-    return l0 * kt.S0 + l1;
-  }
-}
-
 // Staged sample of a k-space spread batch: offsets of tap 0 relative to the
 // tile origin (tap t of axis i lands on tile row off[i] + t), and the tap
 // weights of every axis.
 constexpr int kSpreadBatch = 64;
+// garbage slots that out-of-tile taps update instead of branching: 4 per lane
+constexpr int kSpreadDump = 4 * 64;
+
+// LDS bytes of one k-space spread workgroup for C coils (dynamic part)
+__host__ __device__ inline size_t kspread_lds_bytes(const KTile& kt, int C) {
+  return sizeof(float2) * ((size_t)C * kt.P + kSpreadDump + (size_t)kSpreadBatch * C);
+}
 
 // k-space spread of one work unit, without atomics.  The unit's samples are
 // staged in LDS in batches of kSpreadBatch (tap offsets relative to the tile,
-// tap weights, the C coil values).  Wave w owns coils 4w .. 4w+3 (their LDS
-// planes are its alone); in 3D its 64 lanes are (coil, t1, t2) and each lane
-// applies the sample's four t0 taps, in 2D the lanes are (coil, t0, t1).
+// tap weights, the C coil values); staging work is spread over every thread,
+// one (sample, axis) pair each.  Wave w owns coils 4w .. 4w+3 (their planes
+// are its alone); in 3D its 64 lanes are (coil, t2, t1) and each lane
+// applies the sample's four t0 taps, in 2D the lanes are (coil, t1, t0).
 // Within a wave every lane updates distinct points, so plain LDS
 // read-modify-write is race free, and the summation order is fixed (the
-// spread is deterministic).  The workgroup has ceil(C/4) waves.
-// taps_v and yv are in visit order: the unit's samples are
-// taps_v[start .. start + count) and yv[(start ..)][C].
+// spread is deterministic).  Taps outside the tile, and lanes without a
+// coil, update a private garbage slot instead of branching.  The workgroup
+// has ceil(C/4) waves.  taps_v and yv are in visit order: the unit's
+// samples are taps_v[start .. start + count) and yv[(start ..)][C].
 template <int NDIM, int S>
 __global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ units, int nunits,
                                                       const KTap* __restrict__ taps_v,
@@ -532,16 +527,20 @@ __global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ 
                                                       typename Elem<S>::T* __restrict__ grid,
                                                       float2* __restrict__ partial, Dims dm, KTile kt,
                                                       KbPoly kb, FastDiv cdiv) {
-  extern __shared__ float accf[];  // [C][2][P] accumulator, then the staged coil values
-  __shared__ int st_off[kSpreadBatch][3];
-  __shared__ float st_w[kSpreadBatch][3][4];
-  float2* st_y = (float2*)(accf + (size_t)C * 2 * kt.P);  // [kSpreadBatch][C]
+  extern __shared__ float2 acc[];  // [C][P] accumulator, [4][64] garbage, [kSpreadBatch][C] coil values
+  __shared__ int4 st_off[kSpreadBatch];
+  __shared__ float4 st_w[kSpreadBatch][3];
+  float2* dump = acc + (size_t)C * kt.P;
+  float2* st_y = dump + kSpreadDump;
   const int nthr = blockDim.x;
   const KUnit un = units[blockIdx.x];
   int lo[3] = {0, 0, 0};
   ktile_origin(un.tile, kt, NDIM, lo);
-  const int nacc = C * 2 * kt.P;
-  for (int e = threadIdx.x; e < nacc; e += nthr) accf[e] = 0.f;
+  {
+    float4* a4 = (float4*)acc;
+    const int n4 = (C * kt.P) >> 1;  // P is even
+    for (int e = threadIdx.x; e < n4; e += nthr) a4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -549,62 +548,73 @@ __global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ 
   const int ta = (lane >> 2) & 3;  // 3D: t2; 2D: t1
   const int tb = lane >> 4;        // 3D: t1; 2D: t0
   const bool active = c < C;
-  float* pre = accf + (2 * (active ? c : 0)) * kt.P;
-  float* pim = pre + kt.P;
+  const int cr = active ? c : 0;
+  float2* plane = acc + (size_t)cr * kt.P;
+  float2* mydump = dump + lane;  // slot t at mydump[64 t]
 
   for (int b0 = 0; b0 < un.count; b0 += kSpreadBatch) {
     const int nb = min(kSpreadBatch, un.count - b0);
     __syncthreads();  // previous batch consumed (and the accumulator zeroed)
-    for (int e = threadIdx.x; e < nb * C; e += nthr) st_y[e] = yv[(int64_t)(un.start + b0) * C + e];
-    if (threadIdx.x < nb) {
-      const KTap tp = taps_v[un.start + b0 + threadIdx.x];
-#pragma unroll
-      for (int i = 0; i < NDIM; ++i) {
-        float w[4];
-        kb_weights(kb, tp.f[i], w);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) st_w[threadIdx.x][i][t] = w[t];
-        int o = (int)((tp.base >> (10 * i)) & 1023) - lo[i];  // periodic: the image next to the tile
-        if (o > dm.G[i] / 2) o -= dm.G[i];
-        if (o < -dm.G[i] / 2) o += dm.G[i];
-        st_off[threadIdx.x][i] = o;
-      }
+    {
+      const float2* src = yv + (int64_t)(un.start + b0) * C;
+      for (int e = threadIdx.x; e < nb * C; e += nthr) st_y[e] = src[e];
+    }
+    for (int e = threadIdx.x; e < nb * NDIM; e += nthr) {
+      const int sidx = e / NDIM, i = e - sidx * NDIM;
+      const KTap tp = taps_v[un.start + b0 + sidx];
+      float w[4];
+      kb_weights(kb, tp.f[i], w);
+      st_w[sidx][i] = make_float4(w[0], w[1], w[2], w[3]);
+      int o = (int)((tp.base >> (10 * i)) & 1023) - lo[i];  // periodic: the image next to the tile
+      if (o > dm.G[i] / 2) o -= dm.G[i];
+      if (o < -dm.G[i] / 2) o += dm.G[i];
+      ((int*)&st_off[sidx])[i] = o;
     }
     __syncthreads();
-    if (!active) continue;
+    // the parameters of sample s + 1 are read before the accumulator update
+    // of sample s, so each sample costs one LDS round trip
+    int4 of = st_off[0];
+    float2 y = st_y[cr];
+    float wa = ((const float*)&st_w[0][NDIM - 2])[tb];
+    float wb = ((const float*)&st_w[0][NDIM - 1])[ta];
+    float4 w0 = st_w[0][0];
     for (int s = 0; s < nb; ++s) {
-      const float2 yv = st_y[s * C + c];
+      const int4 cof = of;
+      const float2 cy = y;
+      const float cwa = wa, cwb = wb;
+      const float4 cw0 = w0;
+      {
+        const int sn = min(s + 1, nb - 1);  // the last sample re-reads itself
+        of = st_off[sn];
+        y = st_y[sn * C + cr];
+        wa = ((const float*)&st_w[sn][NDIM - 2])[tb];
+        wb = ((const float*)&st_w[sn][NDIM - 1])[ta];
+        if constexpr (NDIM == 3) w0 = st_w[sn][0];
+      }
       if constexpr (NDIM == 3) {
-        const int l2 = st_off[s][2] + ta, l1 = st_off[s][1] + tb, o0 = st_off[s][0];
-        if (l2 < 0 || l2 >= kt.TS[2] || l1 < 0 || l1 >= kt.TS[1]) continue;
-        const float w12 = st_w[s][1][tb] * st_w[s][2][ta];
-        const int base = l1 * kt.S1 + l2;
-        float vr[4], vi[4];
-        int idx[4];
+        const int l1 = cof.y + tb, l2 = cof.z + ta;
+        const bool lane_ok = active && (unsigned)l1 < (unsigned)kt.TS[1] && (unsigned)l2 < (unsigned)kt.TS[2];
+        const float w12 = cwa * cwb;
+        const float wt[4] = {cw0.x * w12, cw0.y * w12, cw0.z * w12, cw0.w * w12};
+        const int base = cof.x * kt.S0 + l1 * kt.S1 + l2;
+        float2* ptr[4];
+        float2 v[4];
 #pragma unroll
         for (int t0 = 0; t0 < 4; ++t0) {  // read all four, then write all four
-          const int l0 = o0 + t0;
-          idx[t0] = (l0 >= 0 && l0 < kt.TS[0]) ? l0 * kt.S0 + base : -1;
-          if (idx[t0] >= 0) {
-            vr[t0] = pre[idx[t0]];
-            vi[t0] = pim[idx[t0]];
-          }
+          const bool ok = lane_ok && (unsigned)(cof.x + t0) < (unsigned)kt.TS[0];
+          ptr[t0] = ok ? plane + (base + t0 * kt.S0) : mydump + 64 * t0;
+          v[t0] = *ptr[t0];
         }
 #pragma unroll
-        for (int t0 = 0; t0 < 4; ++t0) {
-          if (idx[t0] >= 0) {
-            const float ww = w12 * st_w[s][0][t0];
-            pre[idx[t0]] = fmaf(ww, yv.x, vr[t0]);
-            pim[idx[t0]] = fmaf(ww, yv.y, vi[t0]);
-          }
-        }
+        for (int t0 = 0; t0 < 4; ++t0)
+          *ptr[t0] = make_float2(fmaf(wt[t0], cy.x, v[t0].x), fmaf(wt[t0], cy.y, v[t0].y));
       } else {
-        const int l1 = st_off[s][1] + ta, l0 = st_off[s][0] + tb;
-        if (l1 < 0 || l1 >= kt.TS[1] || l0 < 0 || l0 >= kt.TS[0]) continue;
-        const float ww = st_w[s][0][tb] * st_w[s][1][ta];
-        const int idx = l0 * kt.S0 + l1;
-        pre[idx] = fmaf(ww, yv.x, pre[idx]);
-        pim[idx] = fmaf(ww, yv.y, pim[idx]);
+        const int l1 = cof.y + ta, l0 = cof.x + tb;
+        const bool ok = active && (unsigned)l1 < (unsigned)kt.TS[1] && (unsigned)l0 < (unsigned)kt.TS[0];
+        const float ww = cwa * cwb;
+        float2* pt = ok ? plane + (l0 * kt.S0 + l1) : mydump;
+        const float2 v = *pt;
+        *pt = make_float2(fmaf(ww, cy.x, v.x), fmaf(ww, cy.y, v.y));
       }
     }
   }
@@ -613,7 +623,6 @@ __global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ 
   // contiguous values of the [G...][C] grid
   const int volC = kt.vol * C;
   const int rowlen = kt.TS[NDIM - 1] * C;
-  const int nrows = kt.vol / kt.TS[NDIM - 1];
   const FastDiv rdiv = kt.rowdiv;  // divides by rowlen
   for (int e = threadIdx.x; e < volC; e += nthr) {
     const int row = (int)rdiv.div((uint32_t)e);
@@ -630,7 +639,7 @@ __global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ 
       pi = row * kt.S0 + l2;
       gl0 = lo[0] + row;
     }
-    const float2 v = make_float2(accf[(2 * cc) * kt.P + pi], accf[(2 * cc + 1) * kt.P + pi]);
+    const float2 v = acc[(size_t)cc * kt.P + pi];
     if (un.slot >= 0) {
       // partial tiles keep the point-major layout e = point * C + coil
       partial[(int64_t)un.slot * volC + e] = v;
@@ -647,7 +656,6 @@ __global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ 
     }
     if (ok) Elem<S>::store(grid + gi * C + cc, v);
   }
-  (void)nrows;
 }
 
 // sum the partial tiles of every split tile (fixed slot order) and write them

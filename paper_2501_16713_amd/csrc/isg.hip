@@ -980,7 +980,7 @@ static void kspread_nd(isg_plan* pl, const isg_traj* tr, const float2* yv, typen
 template <int S>
 static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* yv, void* grid) {
   auto grd = (typename Elem<S>::T*)grid;
-  const size_t lds = sizeof(float) * 2 * (size_t)pl->ktile.P * pl->C + sizeof(float2) * kSpreadBatch * pl->C;
+  const size_t lds = kspread_lds_bytes(pl->ktile, pl->C);
   const size_t volC = (size_t)pl->ktile.vol * pl->C;
   if (tr->nslots) grow(pl, pl->partial, sizeof(float2) * volC * tr->nslots);
   float2* part = (float2*)pl->partial.p;
@@ -1441,19 +1441,18 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
     pl->ktile.nt[i] = (pl->G[i] + pl->ktile.TS[i] - 1) / pl->ktile.TS[i];
     pl->ktile.vol *= pl->ktile.TS[i];
   }
+  // dense planes of complex values; plane size = 4 (mod 16) puts the four
+  // coils of a spread wave on distinct banks
   if (pl->ndim == 3) {
     pl->ktile.S1 = pl->ktile.TS[2];
-    // S0 = 4 (mod 32) and at least TS1 * TS2
-    int s0 = pl->ktile.TS[1] * pl->ktile.TS[2];
-    while (s0 % 32 != 4) ++s0;
-    pl->ktile.S0 = s0;
+    pl->ktile.S0 = pl->ktile.TS[1] * pl->ktile.TS[2];
   } else {
     pl->ktile.S1 = 1;
-    pl->ktile.S0 = pl->ktile.TS[1] + 1;
+    pl->ktile.S0 = pl->ktile.TS[1];
   }
-  {  // plane size = 1 (mod 16) staggers the coil planes across banks
+  {
     int P = pl->ktile.TS[0] * pl->ktile.S0;
-    while (P % 16 != 1) ++P;
+    while (P % 16 != 4) ++P;
     pl->ktile.P = P;
   }
   pl->ktile.rowdiv = make_fastdiv((uint32_t)(pl->ktile.TS[pl->ndim - 1] * pl->C));
