@@ -57,7 +57,15 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched_160")
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16", "fp16"],
+                    help="grid storage of the headline form")
+    ap.add_argument("--forms", default="plain,tuned,bf16,fp16",
+                    help="forms to time besides the headline: plain (one state per k-space launch, no graph), "
+                         "tuned (autotuned batching / graph), bf16, fp16 (tuned, half-precision grids)")
+    ap.add_argument("--no-tune", action="store_true", help="headline form without autotuning (options below)")
+    ap.add_argument("--chunk", type=int, default=512, help="spread chunk with --no-tune")
+    ap.add_argument("--batch", type=int, default=1, help="phase batch with --no-tune")
+    ap.add_argument("--graph", type=int, default=0, help="graph replay (0/1) with --no-tune")
     ap.add_argument("--cg-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="print a per-stage timing table to stderr")
@@ -86,24 +94,60 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(dev)
+    lam = w.lam
     with torch.cuda.stream(stream):
-        plan = isg.Plan(w.shape, ncoils=w.ncoils, nphases=w.nphases, storage=args.storage)
         x = torch.from_numpy(inp["x"]).to(dev)
         S = torch.from_numpy(inp["S"]).to(dev)
-        t0 = time.time()
-        mots = [plan.motion(torch.from_numpy(d).to(dev)) for d in inp["d"]]
-        trs = [plan.traj(torch.from_numpy(k).to(dev)) for k in inp["k"]]
-        torch.cuda.synchronize()
-        log(f"plan-time preparation {time.time() - t0:.1f}s; plan holds {plan.device_bytes() / 2**30:.2f} GiB")
-        out = torch.empty_like(x)
-        lam = w.lam
+        d_dev = [torch.from_numpy(d).to(dev) for d in inp["d"]]
+        k_dev = [torch.from_numpy(k).to(dev) for k in inp["k"]]
+    torch.cuda.synchronize()
 
-        def step():
-            plan.normal(x, lam, mots, S, trs, out=out)
+    def make_plan(storage, options=None):
+        with torch.cuda.stream(stream):
+            t = time.time()
+            plan = isg.Plan(w.shape, ncoils=w.ncoils, nphases=w.nphases, storage=storage)
+            for name, v in (options or {}).items():
+                plan.set_option(name, v)
+            mots = [plan.motion(d) for d in d_dev]
+            trs = [plan.traj(k) for k in k_dev]
+            torch.cuda.synchronize()
+        log(f"{storage} plan: preparation {time.time() - t:.1f}s")
+        return plan, mots, trs
 
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
+    def time_steps(plan, mots, trs, out, steps):
+        """ms per normal-operator application over `steps` back-to-back calls"""
+        with torch.cuda.stream(stream):
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            for _ in range(steps):
+                plan.normal(x, lam, mots, S, trs, out=out)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps
+
+    def run_form(storage, tune, options=None):
+        plan, mots, trs = make_plan(storage, options)
+        report = None
+        with torch.cuda.stream(stream):
+            out = torch.empty_like(x)
+            if tune:
+                t = time.time()
+                report = plan.tune(x, lam, mots, S, trs, reps=3)
+                log(f"{storage} tuned in {time.time() - t:.1f}s: {report['chosen']}")
+            for _ in range(args.warmup):
+                plan.normal(x, lam, mots, S, trs, out=out)
+        ms = time_steps(plan, mots, trs, out, args.steps)
+        opts = {k: plan.get_option(k) for k in ("spread_chunk", "phase_batch", "graph")}
+        log(f"{storage} {'tuned' if tune else 'plain'}: {ms:.3f} ms/apply, options {opts}")
+        return plan, mots, trs, out, ms, opts, report
+
+    # ---- headline form ------------------------------------------------------
+    fixed = None if not args.no_tune else {"spread_chunk": args.chunk, "phase_batch": args.batch,
+                                           "graph": args.graph}
+    plan, mots, trs, out, ms_per_step, opts, tune_report = run_form(args.storage, not args.no_tune, fixed)
+    value = 1000.0 / ms_per_step
+    with torch.cuda.stream(stream):
         if args.calib_copy_mb > 0:
             # one plain streaming kernel of known size (reads and writes
             # calib_copy_mb MiB each) against which HBM counters are scaled
@@ -113,10 +157,9 @@ def main():
             torch.neg(src, out=dst)
             torch.cuda.synchronize()
             del src, dst
-
-        # per-stage timing pass (not the timed region): find the dominant stage
+        # per-stage pass (eager, every launch bracketed by events): the dominant stage
         plan.set_timing(True, "")
-        step()
+        plan.normal(x, lam, mots, S, trs, out=out)
         stages = plan.read_timing()
         plan.set_timing(False)
         dominant = max(stages, key=lambda t: stages[t][1])
@@ -124,21 +167,14 @@ def main():
             tot = sum(v[1] for v in stages.values())
             for t, (cnt, ms) in sorted(stages.items(), key=lambda kv: -kv[1][1]):
                 log(f"  {t:22s} {cnt:4d} launches {ms:9.3f} ms  {100 * ms / tot:5.1f}%")
-
-        # timed region: only the dominant stage is bracketed with events
+        # the dominant stage's launches over `steps` applications, bracketed
+        # by events on the plan's stream (eager: a graph replay hides launches)
         plan.set_timing(True, dominant)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
         for _ in range(args.steps):
-            step()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms_total = ev0.elapsed_time(ev1)
+            plan.normal(x, lam, mots, S, trs, out=out)
         dom = plan.read_timing().get(dominant, (0, 0.0))
         plan.set_timing(False)
-        ms_per_step = ms_total / args.steps
-        value = 1000.0 / ms_per_step
+        torch.cuda.synchronize()
 
         # CG (not part of the headline value)
         cg = None
@@ -154,28 +190,27 @@ def main():
             cg = {"iters": args.cg_iters, "seconds": round(cg_s, 4),
                   "ms_per_iter": round(1000 * cg_s / args.cg_iters, 3),
                   "resnorm_first_last": [hist[0], hist[-1]]}
+        ref_out = out.clone()
+    torch.cuda.synchronize()
 
     es = 8 if args.storage == "fp32" else 4
     G = tuple(2 * n for n in w.shape)
     per_launch = stage_bytes(dominant, w.shape, G, w.ncoils, es)
+    infos = [t.info() for t in trs]
     if dominant in ("fft_coil_fwd_ax0", "fft_coil_adj_ax0"):
         # these passes touch only the spread tiles some sample reaches
-        tot = 0
-        for t in trs:
-            info = t.info()
-            tot += info["tiles"] * info["tile_points"] * w.ncoils * es
+        tot = sum(i["tiles"] * i["tile_points"] * w.ncoils * es for i in infos)
         per_launch = tot // len(trs) + w.shape[0] * G[1] * G[2] * w.ncoils * es
     if per_launch is None and dominant in ("kspread", "kgather"):
-        # one launch per state: average over the states
+        # one state per launch unless batched: bytes of all states / launches
         tot = 0
-        for t, k in zip(trs, inp["k"]):
-            info = t.info()
-            tile_bytes = info["tiles"] * info["tile_points"] * w.ncoils * es
+        for i, k in zip(infos, inp["k"]):
+            tile_bytes = i["tiles"] * i["tile_points"] * w.ncoils * es
             if dominant == "kspread":  # touched tiles written; tap records and visit data read
-                tot += tile_bytes + info["visits"] * (16 + 8 * w.ncoils)
+                tot += tile_bytes + i["visits"] * (16 + 8 * w.ncoils)
             else:  # tap records, touched-tile footprint read; visit-ordered values written
-                tot += k.shape[0] * 16 + tile_bytes + info["visits"] * 8 * w.ncoils
-        per_launch = tot // len(trs)
+                tot += k.shape[0] * 16 + tile_bytes + i["visits"] * 8 * w.ncoils
+        per_launch = tot * args.steps // max(1, dom[0])
     roofline = None
     if per_launch and dom[0] > 0:
         avg_ms = dom[1] / dom[0]
@@ -185,6 +220,32 @@ def main():
                     "traffic": measured_traffic(dominant, w.name, args.storage),
                     "bytes_per_launch": per_launch, "avg_launch_ms": round(avg_ms, 4),
                     "launches": dom[0]}
+
+    # ---- other forms, for the batched / mixed-precision speedups -------------
+    if not args.no_tune:
+        head = "tuned"
+    else:
+        head = "plain" if (args.chunk, args.batch, args.graph) == (512, 1, 0) else "fixed"
+    forms = {f"{head}_{args.storage}": {"ms": round(ms_per_step, 4), "options": opts}}
+    del plan, mots, trs
+    for f in [f.strip() for f in args.forms.split(",") if f.strip()]:
+        storage = f if f in ("bf16", "fp16") else "fp32"
+        tune = f != "plain"
+        name = f"{'tuned' if tune else 'plain'}_{storage}"
+        if name in forms:
+            continue
+        p2, m2, t2, o2, ms2, opts2, _ = run_form(storage, tune)
+        entry = {"ms": round(ms2, 4), "options": opts2}
+        if storage != args.storage:  # relative difference from the headline form's output
+            diff = torch.linalg.vector_norm(o2 - ref_out) / torch.linalg.vector_norm(ref_out)
+            entry["rel_diff_vs_" + args.storage] = float(diff.item())
+        forms[name] = entry
+        del p2, m2, t2, o2
+        torch.cuda.synchronize()
+    base = forms.get("plain_fp32", {}).get("ms")
+    if base:
+        for v in forms.values():
+            v["speedup_vs_plain_fp32"] = round(base / v["ms"], 3)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -206,13 +267,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "shape": list(w.shape), "coils": w.ncoils, "phases": w.nphases,
                    "samples_per_phase": [int(k.shape[0]) for k in inp["k"]], "lambda": lam,
-                   "storage": args.storage},
+                   "storage": args.storage, "options": opts},
         "gridding_gpts_per_s": {
             "kspace_point_coil_interps": round(2 * total_samples * w.ncoils * value / 1e9, 4),
             "warp_voxels": round(2 * w.nphases * int(np.prod(w.shape)) * value / 1e9, 4),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": forms,
+        "tune": tune_report,
         "cg": cg,
         "stages_ms": {k: round(v[1], 4) for k, v in sorted(stages.items(), key=lambda kv: -kv[1][1])},
     }

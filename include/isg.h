@@ -124,6 +124,44 @@ isg_status isg_plan_set_timing(isg_plan* plan, int enable, const char* prefix);
  * buf is too small. */
 isg_status isg_plan_read_timing(isg_plan* plan, char* buf, int64_t len);
 
+/* Tunable execution options of a plan.  None of them changes the result
+ * beyond floating-point summation order.
+ *   ISG_OPT_SPREAD_CHUNK  samples per k-space spread work unit (tiles with
+ *                         more samples are split and their partial tiles
+ *                         summed in a fixed order); 32..65536, default 512;
+ *                         applies to trajectories prepared (or re-tuned) later
+ *   ISG_OPT_PHASE_BATCH   states whose k-space gather and spread run as one
+ *                         launch (each state keeps its own grid, so device
+ *                         memory grows by one coil-expanded grid per state);
+ *                         1..16, default 1
+ *   ISG_OPT_GRAPH         1: isg_normal captures its kernel sequence in a HIP
+ *                         graph and replays it while its arguments stay the
+ *                         same (not on the null stream, not while timing);
+ *                         default 0 */
+typedef enum {
+  ISG_OPT_SPREAD_CHUNK = 1,
+  ISG_OPT_PHASE_BATCH = 2,
+  ISG_OPT_GRAPH = 3
+} isg_option;
+
+/* Set / read an option.  INVALID_ARG for an unknown option or a value out of
+ * range. */
+isg_status isg_plan_set_option(isg_plan* plan, isg_option option, int64_t value);
+isg_status isg_plan_get_option(const isg_plan* plan, isg_option option, int64_t* value);
+
+/* Autotuner: times the normal operator sum_p A_p^H A_p x + lambda x on the
+ * given inputs for candidate spread chunk sizes, phase batch sizes and graph
+ * replay (a coordinate search, each candidate the best of `reps` timed
+ * applications after one warm-up), keeps the fastest setting in the plan and
+ * re-prepares the trajectories for its chunk size.  Candidates that do not
+ * fit in device memory are skipped.  report (host, may be NULL) receives a
+ * JSON object {"candidates": [{"chunk", "batch", "graph", "ms"}...],
+ * "chosen": {...}} (NUL-terminated, truncated to len bytes).  Synchronizes
+ * the stream. */
+isg_status isg_plan_tune(isg_plan* plan, int nphases, const void* x, const isg_motion* const* d,
+                         const void* S, isg_traj* const* k, double lambda, int reps, char* report,
+                         int64_t len);
+
 /* Prepare a displacement field d (device float32 [ndim][n...], voxels) for
  * T_d / T_d^H (Eq. 5): tap bases and tile bins for the spreading adjoint.
  * NOT_FINITE if d holds NaN/Inf. */

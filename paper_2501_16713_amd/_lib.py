@@ -15,6 +15,7 @@ STATUS_NAMES = {
     6: "ISG_ERR_CG_BREAKDOWN", 7: "ISG_ERR_STATE",
 }
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
+OPTIONS = {"spread_chunk": 1, "phase_batch": 2, "graph": 3}
 
 # every symbol the header declares, with (restype, argtypes)
 _p = C.c_void_p
@@ -29,6 +30,9 @@ SIGNATURES = {
     "isg_plan_device_bytes": (C.c_int, [_p, C.POINTER(_i64)]),
     "isg_plan_set_timing": (C.c_int, [_p, C.c_int, C.c_char_p]),
     "isg_plan_read_timing": (C.c_int, [_p, C.c_char_p, _i64]),
+    "isg_plan_set_option": (C.c_int, [_p, C.c_int, _i64]),
+    "isg_plan_get_option": (C.c_int, [_p, C.c_int, C.POINTER(_i64)]),
+    "isg_plan_tune": (C.c_int, [_p, C.c_int, _p, _p, _p, _p, C.c_double, C.c_int, C.c_char_p, _i64]),
     "isg_motion_create": (C.c_int, [_p, _p, C.POINTER(_p)]),
     "isg_motion_destroy": (C.c_int, [_p]),
     "isg_traj_create": (C.c_int, [_p, _p, _i64, C.POINTER(_p)]),

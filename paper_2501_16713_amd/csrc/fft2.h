@@ -137,6 +137,8 @@ struct Tile2 {
   int na, nb;       // lines per tile: na outer x nb inner
   int64_t tiles_b;  // ceil(B / nb)
   int LS;           // LDS line stride (float2)
+  int64_t tiles;    // > 0: total tiles, launched as 8 ceil(tiles / 8) workgroups in XCD-contiguous
+                    // order; 0: plain order (host: < 0 requests XCD order)
 };
 
 template <int MAP>
@@ -175,7 +177,15 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
   const int nthreads = blockDim.x;
   for (int i = tid; i < L; i += nthreads) tw[i] = ld.tw[i];
 
-  const int64_t tile = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+  int64_t tile = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+  if (g.tiles > 0) {
+    // consecutive workgroup indices go to the 8 XCDs in turn; give each XCD
+    // one contiguous range of tiles so that its L2 and translation caches
+    // see neighbouring columns of the same rows
+    const int64_t per = (g.tiles + 7) >> 3;
+    tile = (tile & 7) * per + (tile >> 3);
+    if (tile >= g.tiles) return;
+  }
   const int64_t ta = tile / g.tiles_b;
   const int64_t a0 = ta * g.na;
   const int64_t b0 = (tile - ta * g.tiles_b) * g.nb;

@@ -26,11 +26,33 @@ struct Dims {
   int n[3];       // image shape (n[2] = 1 in 2D)
   int G[3];       // oversampled shape (G[2] = 1 in 2D)
   int64_t N;      // voxels
+  FastDiv nfd[3]; // division by n[i]
+  float invG[3];  // 1 / G[i]
 };
 
-__device__ __forceinline__ int wrap(int g, int G) {
-  g %= G;
-  return g < 0 ? g + G : g;
+// g mod G in [0, G) for |g| < 2^24: a float quotient, then one correction
+// either way
+__device__ __forceinline__ int wrap(int g, int G, float invG) {
+  g -= G * (int)floorf((float)g * invG);
+  if (g >= G) g -= G;
+  if (g < 0) g += G;
+  return g;
+}
+
+// integer coordinates of voxel r (r < 2^31) of the image [n0][n1](/[n2])
+template <int NDIM>
+__device__ __forceinline__ void voxel_coords(int64_t r, const Dims& dm, int ri[3]) {
+  const uint32_t rr = (uint32_t)r;
+  if constexpr (NDIM == 3) {
+    const uint32_t q = dm.nfd[2].div(rr);
+    ri[2] = (int)(rr - q * (uint32_t)dm.n[2]);
+    ri[0] = (int)dm.nfd[1].div(q);
+    ri[1] = (int)(q - (uint32_t)ri[0] * (uint32_t)dm.n[1]);
+  } else {
+    ri[0] = (int)dm.nfd[1].div(rr);
+    ri[1] = (int)(rr - (uint32_t)ri[0] * (uint32_t)dm.n[1]);
+    ri[2] = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -44,13 +66,7 @@ __global__ __launch_bounds__(kGridThreads) void warp_gather_kernel(const float2*
   const int64_t r = (int64_t)blockIdx.x * kGridThreads + threadIdx.x;
   if (r >= dm.N) return;
   int ri[3];
-  {
-    int64_t t = r;
-    for (int i = NDIM - 1; i >= 0; --i) {
-      ri[i] = (int)(t % dm.n[i]);
-      t /= dm.n[i];
-    }
-  }
+  voxel_coords<NDIM>(r, dm, ri);
   int base[NDIM];
   float w[NDIM][4];
 #pragma unroll
@@ -58,7 +74,7 @@ __global__ __launch_bounds__(kGridThreads) void warp_gather_kernel(const float2*
     const float y = 2.0f * d[(int64_t)i * dm.N + r];
     const float fl = floorf(y);
     kb_weights(kb, y - fl, w[i]);
-    base[i] = wrap(2 * ri[i] + (int)fl - 1, dm.G[i]);
+    base[i] = wrap(2 * ri[i] + (int)fl - 1, dm.G[i], dm.invG[i]);
   }
   float2 acc = make_float2(0.f, 0.f);
   if constexpr (NDIM == 3) {
@@ -121,13 +137,7 @@ __global__ __launch_bounds__(kGridThreads) void warp_grad_kernel(const float2* _
   const int64_t r = (int64_t)blockIdx.x * kGridThreads + threadIdx.x;
   if (r >= dm.N) return;
   int ri[3];
-  {
-    int64_t t = r;
-    for (int i = NDIM - 1; i >= 0; --i) {
-      ri[i] = (int)(t % dm.n[i]);
-      t /= dm.n[i];
-    }
-  }
+  voxel_coords<NDIM>(r, dm, ri);
   int base[NDIM];
   float w[NDIM][4], dw[NDIM][4];
 #pragma unroll
@@ -135,7 +145,7 @@ __global__ __launch_bounds__(kGridThreads) void warp_grad_kernel(const float2* _
     const float y = 2.0f * d[(int64_t)i * dm.N + r];
     const float fl = floorf(y);
     kb_weights_deriv(kb, y - fl, w[i], dw[i]);
-    base[i] = wrap(2 * ri[i] + (int)fl - 1, dm.G[i]);
+    base[i] = wrap(2 * ri[i] + (int)fl - 1, dm.G[i], dm.invG[i]);
   }
   float2 J[NDIM];
 #pragma unroll
@@ -205,76 +215,106 @@ struct WarpSpreadPhases {
   const float2* w[kMaxPhasesPerLaunch];      // values to spread, [N]
 };
 
-// Image-space spread tile; LDS holds a re plane and an im plane of P floats,
-// point (l0, l1, l2) at l0 * S0 + l1 * S1 + l2 (padded strides spread banks).
+// Image-space spread tile; LDS holds planes of P complex values, point
+// (l0, l1, l2) at l0 * S0 + l1 * S1 + l2.
 struct TileDims {
   int TS[3];      // tile extent per axis
   int nt[3];      // tiles per axis
-  int S0, S1;     // plane strides
-  int P;          // plane size (floats)
+  int S0, S1;     // plane strides (complex values)
+  int P;          // plane size (complex values), = 4 (mod 16)
 };
+
+// Workgroup index -> tile such that the workgroups of one XCD (consecutive
+// indices go to the 8 XCDs in turn) take one contiguous range of tiles, whose
+// neighbouring tiles share source voxels in that XCD's L2.  Launch
+// 8 * ceil(n / 8) workgroups; indices past the last tile return n or more.
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+  const int per = (n + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+constexpr int kWarpWaves = kGridThreads / 64;
+// entries a wave applies per step: 3D lanes (entry, t0 half, t1, t2) apply
+// two taps each; 2D lanes (entry, t0, t1) one
+template <int NDIM> struct WarpLanes {
+  static constexpr int kCopies = NDIM == 3 ? 2 : 4;
+  static constexpr int kTapsPerLane = NDIM == 3 ? 2 : 1;
+};
+constexpr int kWarpDump = 2 * 64;  // garbage slots for out-of-tile taps
+
+__host__ __device__ inline size_t warp_spread_lds_bytes(const TileDims& td, int ndim) {
+  const int copies = ndim == 3 ? WarpLanes<3>::kCopies : WarpLanes<2>::kCopies;
+  return sizeof(float2) * ((size_t)kWarpWaves * copies * td.P + kWarpDump);
+}
 
 // Image-space spread of one tile, without atomics.  Entries (state, voxel)
 // of the tile, over all states, are cut into batches of 64; wave w takes
 // batches w, w + 4, ...: the 64 lanes stage one entry each (tap offsets
 // relative to the tile, weights, value) in the wave's LDS staging area, then
-// walk the staged entries with one lane per tap.  The 64 taps of an entry
-// are 64 distinct points and each wave accumulates into its own LDS copy of
-// the tile, so plain read-modify-write is race free; the copies are summed
-// at the end (fixed order: deterministic).
-constexpr int kWarpWaves = kGridThreads / 64;
-
+// walk the staged entries several at a time, each entry in an LDS copy of
+// the tile of its own.  The lanes of one entry cover its 64 taps (distinct
+// points), so plain read-modify-write is race free; out-of-tile taps update
+// garbage slots instead of branching.  The copies are summed at the end in a
+// fixed order (deterministic).
 template <int NDIM>
 __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPhases ph, float2* __restrict__ U,
                                                                    int accumulate, int ntiles, Dims dm,
                                                                    TileDims td, KbPoly kb) {
-  extern __shared__ float accw[];  // [kWarpWaves][2 copies][2][P]
-  __shared__ int st_off[kWarpWaves][64][3];
-  __shared__ float st_w[kWarpWaves][64][3][4];
+  using WL = WarpLanes<NDIM>;
+  constexpr int Q = WL::kCopies;
+  extern __shared__ float2 accw[];  // [kWarpWaves][Q][P], then [kWarpDump] garbage
+  __shared__ int4 st_off[kWarpWaves][64];
+  __shared__ float4 st_w[kWarpWaves][64][3];
   __shared__ float2 st_v[kWarpWaves][64];
-  // persistent: each workgroup walks tiles blockIdx.x, + gridDim.x, ...
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-  __syncthreads();  // the previous tile's write-out has read the accumulators
-  int tc[3] = {0, 0, 0};
+  const int tile = xcd_contiguous(blockIdx.x, ntiles);
+  if (tile >= ntiles) return;
+  float2* dump = accw + (size_t)kWarpWaves * Q * td.P;
+  int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+  int vol = 1;
   {
     int t = tile;
     for (int i = NDIM - 1; i >= 0; --i) {
-      tc[i] = t % td.nt[i];
+      lo[i] = (t % td.nt[i]) * td.TS[i];
       t /= td.nt[i];
     }
-  }
-  int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
-  int vol = 1;
 #pragma unroll
-  for (int i = 0; i < NDIM; ++i) {
-    lo[i] = tc[i] * td.TS[i];
-    ext[i] = min(td.TS[i], dm.G[i] - lo[i]);
-    vol *= td.TS[i];
+    for (int i = 0; i < NDIM; ++i) {
+      ext[i] = min(td.TS[i], dm.G[i] - lo[i]);
+      vol *= td.TS[i];
+    }
   }
-  for (int e = threadIdx.x; e < kWarpWaves * 4 * td.P; e += kGridThreads) accw[e] = 0.f;
+  {
+    float4* a4 = (float4*)accw;
+    const int n4 = (kWarpWaves * Q * td.P) >> 1;  // P is even
+    for (int e = threadIdx.x; e < n4; e += kGridThreads) a4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   // entries of this tile over all states, concatenated
   int E = 0;
   for (int p = 0; p < ph.P; ++p) E += ph.tile_off[p][tile + 1] - ph.tile_off[p][tile];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  // two copies per wave: consecutive staged entries alternate between them,
-  // so the read-modify-writes of entries s and s+1 never alias
-  float* are0 = accw + wave * 4 * td.P;
-  float* aim0 = are0 + td.P;
-  float* are1 = aim0 + td.P;
-  float* aim1 = are1 + td.P;
-  int tt[3];
-  tt[NDIM - 1] = lane & 3;
-  tt[NDIM - 2] = (lane >> 2) & 3;
-  if (NDIM == 3) tt[0] = lane >> 4;
-  const bool tap_lane = NDIM == 3 || lane < 16;
+  // lane roles
+  int q, t0a, ta, tb;  // entry slot, first t0, and the taps of the two faster axes
+  if constexpr (NDIM == 3) {
+    q = lane >> 5;
+    t0a = 2 * ((lane >> 4) & 1);
+    tb = (lane >> 2) & 3;  // t1
+    ta = lane & 3;         // t2
+  } else {
+    q = lane >> 4;
+    t0a = (lane >> 2) & 3;  // t0
+    tb = 0;
+    ta = lane & 3;  // t1
+  }
+  float2* copy = accw + (size_t)(wave * Q + q) * td.P;
+  float2* mydump = dump + lane;  // slot j at mydump[64 j]
   const int nbatch = (E + 63) / 64;
   const int rounds = (nbatch + kWarpWaves - 1) / kWarpWaves;
   for (int rd = 0; rd < rounds; ++rd) {
     const int b = rd * kWarpWaves + wave;
     const int e0 = b * 64;
     const int ne = max(0, min(64, E - e0));
-    __syncthreads();
+    __syncthreads();  // accumulators zeroed / this wave's previous batch consumed
     if (lane < ne) {  // stage entry e0 + lane
       int e = e0 + lane, p = 0;
       while (e >= ph.tile_off[p][tile + 1] - ph.tile_off[p][tile]) {
@@ -283,72 +323,61 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
       }
       const int64_t r = ph.vox[p][ph.tile_off[p][tile] + e];
       int ri[3];
-      {
-        int64_t t = r;
-        for (int i = NDIM - 1; i >= 0; --i) {
-          ri[i] = (int)(t % dm.n[i]);
-          t /= dm.n[i];
-        }
-      }
+      voxel_coords<NDIM>(r, dm, ri);
+      int off[3] = {0, 0, 0};
 #pragma unroll
       for (int i = 0; i < NDIM; ++i) {
         const float yv = 2.0f * ph.d[p][(int64_t)i * dm.N + r];
         const float fl = floorf(yv);
         float w[4];
         kb_weights(kb, yv - fl, w);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) st_w[wave][lane][i][t] = w[t];
-        int o = wrap(2 * ri[i] + (int)fl - 1, dm.G[i]) - lo[i];  // nearest periodic image
+        st_w[wave][lane][i] = make_float4(w[0], w[1], w[2], w[3]);
+        int o = wrap(2 * ri[i] + (int)fl - 1, dm.G[i], dm.invG[i]) - lo[i];  // nearest periodic image
         if (o > dm.G[i] / 2) o -= dm.G[i];
         if (o < -dm.G[i] / 2) o += dm.G[i];
-        st_off[wave][lane][i] = o;
+        off[i] = o;
       }
+      st_off[wave][lane] = make_int4(off[0], off[1], off[2], 0);
       st_v[wave][lane] = ph.w[p][r];
     }
     __syncthreads();
-    if (tap_lane) {
-      for (int s = 0; s < ne; s += 2) {
-        bool ok[2];
-        float ww[2];
-        int idx[2];
+    for (int s = 0; s < ne; s += Q) {
+      const int sq = s + q;
+      const bool has = sq < ne;
+      const int sc = has ? sq : s;
+      const int4 of = st_off[wave][sc];
+      const float2 v = st_v[wave][sc];
+      if constexpr (NDIM == 3) {
+        const int l1 = of.y + tb, l2 = of.z + ta;
+        const bool ok12 = has && (unsigned)l1 < (unsigned)ext[1] && (unsigned)l2 < (unsigned)ext[2];
+        const float w12 = ((const float*)&st_w[wave][sc][1])[tb] * ((const float*)&st_w[wave][sc][2])[ta];
+        const float* w0 = (const float*)&st_w[wave][sc][0];
+        const int base = l1 * td.S1 + l2;
+        float2* ptr[2];
+        float2 a[2];
+        float wt[2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int sq = min(s + q, 63);
-          ok[q] = s + q < ne;
-          ww[q] = 1.0f;
-          idx[q] = 0;
+        for (int j = 0; j < 2; ++j) {
+          const int l0 = of.x + t0a + j;
+          const bool ok = ok12 && (unsigned)l0 < (unsigned)ext[0];
+          ptr[j] = ok ? copy + (l0 * td.S0 + base) : mydump + 64 * j;
+          wt[j] = w12 * w0[t0a + j];
+          a[j] = *ptr[j];
+        }
 #pragma unroll
-          for (int i = 0; i < NDIM; ++i) {
-            const int l = st_off[wave][sq][i] + tt[i];
-            ok[q] = ok[q] && l >= 0 && l < ext[i];
-            ww[q] *= st_w[wave][sq][i][tt[i]];
-            // 3D: l0 S0 + l1 S1 + l2; 2D: l0 S0 + l1
-            idx[q] += l * (i == NDIM - 1 ? 1 : (i == 0 ? td.S0 : td.S1));
-          }
-        }
-        const float2 v0 = st_v[wave][s], v1 = st_v[wave][min(s + 1, 63)];
-        float r0 = 0.f, i0 = 0.f, r1 = 0.f, i1 = 0.f;
-        if (ok[0]) {
-          r0 = are0[idx[0]];
-          i0 = aim0[idx[0]];
-        }
-        if (ok[1]) {
-          r1 = are1[idx[1]];
-          i1 = aim1[idx[1]];
-        }
-        if (ok[0]) {
-          are0[idx[0]] = fmaf(ww[0], v0.x, r0);
-          aim0[idx[0]] = fmaf(ww[0], v0.y, i0);
-        }
-        if (ok[1]) {
-          are1[idx[1]] = fmaf(ww[1], v1.x, r1);
-          aim1[idx[1]] = fmaf(ww[1], v1.y, i1);
-        }
+        for (int j = 0; j < 2; ++j) *ptr[j] = make_float2(fmaf(wt[j], v.x, a[j].x), fmaf(wt[j], v.y, a[j].y));
+      } else {
+        const int l0 = of.x + t0a, l1 = of.y + ta;
+        const bool ok = has && (unsigned)l0 < (unsigned)ext[0] && (unsigned)l1 < (unsigned)ext[1];
+        const float ww = ((const float*)&st_w[wave][sc][0])[t0a] * ((const float*)&st_w[wave][sc][1])[ta];
+        float2* pt = ok ? copy + (l0 * td.S0 + l1) : mydump;
+        const float2 a = *pt;
+        *pt = make_float2(fmaf(ww, v.x, a.x), fmaf(ww, v.y, a.y));
       }
     }
   }
   __syncthreads();
-  // sum the per-wave copies and write the tile: rows along the last axis are contiguous in U
+  // sum the copies and write the tile: rows along the last axis are contiguous in U
   for (int e = threadIdx.x; e < vol; e += kGridThreads) {
     int l[3] = {0, 0, 0};
     int t = e;
@@ -364,24 +393,59 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
     const int pi = NDIM == 3 ? l[0] * td.S0 + l[1] * td.S1 + l[2] : l[0] * td.S0 + l[1];
     float2 v = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int w = 0; w < 2 * kWarpWaves; ++w) {
-      v.x += accw[w * 2 * td.P + pi];
-      v.y += accw[w * 2 * td.P + td.P + pi];
-    }
+    for (int w = 0; w < kWarpWaves * Q; ++w) v = cadd(v, accw[(size_t)w * td.P + pi]);
     if (accumulate) v = cadd(v, U[gi]);
     U[gi] = v;
   }
-  }  // tiles
 }
 
 // ---------------------------------------------------------------------------
 // k-space taps, prepared at plan time: fractional offsets and the wrapped
 // base index (10 bits per axis) of every sample.
 // ---------------------------------------------------------------------------
+// k-space spread work unit: `count` samples of tile `tile` starting at
+// `start` in the tile-sorted sample list.  slot < 0: the unit is the whole
+// tile and writes the grid; slot >= 0: the unit writes a partial tile into
+// scratch slot `slot`, and a reduce step sums the slots of the tile.
+struct KUnit {
+  int tile, start, count, slot;
+};
+// a tile whose samples were cut into several units: partial slots
+// first_slot .. first_slot + nslots - 1
+struct KSplit {
+  int tile, first_slot, nslots;
+};
 struct KTap {
   float f[3];
   uint32_t base;  // b0 | b1 << 10 | b2 << 20
 };
+
+// k-space interpolation work of up to kMaxPhasesPerLaunch states in one
+// launch (each state has its own trajectory and its own grid): blocks
+// first[p] .. first[p + 1] - 1 belong to state p.  Uneven per-state sample
+// counts become one launch whose blocks are handed out across states.
+template <class T>
+struct KBatch {
+  int n;
+  int first[kMaxPhasesPerLaunch + 1];
+  const KTap* taps[kMaxPhasesPerLaunch];   // gather: taps per sample; spread: taps per visit
+  int64_t count[kMaxPhasesPerLaunch];      // gather: samples of the state
+  const KUnit* units[kMaxPhasesPerLaunch]; // spread: work units
+  const KSplit* splits[kMaxPhasesPerLaunch];
+  const int* vis_off[kMaxPhasesPerLaunch]; // gather into visit order: [M + 1] (null: sample order)
+  const int* vis[kMaxPhasesPerLaunch];
+  const float2* yin[kMaxPhasesPerLaunch];  // spread input, [visits][C]
+  float2* yout[kMaxPhasesPerLaunch];       // gather output
+  T* grid[kMaxPhasesPerLaunch];
+  float2* partial[kMaxPhasesPerLaunch];
+};
+
+// the state a block belongs to
+__device__ __forceinline__ int batch_member(const int* first, int n, int b) {
+  int p = 0;
+  while (p + 1 < n && b >= first[p + 1]) ++p;
+  return p;
+}
 
 // y[j][c] = sum_taps prod_i c(kappa_ji - q_i) grid[q][c], grid [G...][C].
 // Lane mapping: each wavefront holds spw = 64 / C samples and lane (s, c)
@@ -391,19 +455,22 @@ struct KTap {
 // visit of the sample (y_visit[v][c] for v in vis[vis_off[j] .. vis_off[j+1]))
 // instead of y[j][c], which lets the spread read its inputs contiguously.
 template <int NDIM, int S>
-__global__ __launch_bounds__(kGridThreads) void kgather_kernel(const typename Elem<S>::T* __restrict__ grid,
-                                                               const KTap* __restrict__ taps, int64_t M,
-                                                               float2* __restrict__ y, int C, Dims dm,
-                                                               KbPoly kb, const int* __restrict__ vis_off,
-                                                               const int* __restrict__ vis) {
+__global__ __launch_bounds__(kGridThreads) void kgather_kernel(KBatch<typename Elem<S>::T> bt, int C, Dims dm,
+                                                               KbPoly kb) {
+  const int p = batch_member(bt.first, bt.n, blockIdx.x);
+  const typename Elem<S>::T* __restrict__ grid = bt.grid[p];
+  const int64_t M = bt.count[p];
+  float2* __restrict__ y = bt.yout[p];
+  const int* __restrict__ vis_off = bt.vis_off[p];
+  const int* __restrict__ vis = bt.vis[p];
   const int lane = threadIdx.x & 63;
   const int spw = 64 / C;
   const int sub = lane / C;
   const int c = lane - sub * C;
-  const int64_t wave = (int64_t)blockIdx.x * (kGridThreads / 64) + (threadIdx.x >> 6);
+  const int64_t wave = (int64_t)(blockIdx.x - bt.first[p]) * (kGridThreads / 64) + (threadIdx.x >> 6);
   const int64_t j = wave * spw + sub;
   if (sub >= spw || j >= M) return;
-  const KTap tp = taps[j];
+  const KTap tp = bt.taps[p][j];
   float w[NDIM][4];
   int g[NDIM][4];
 #pragma unroll
@@ -465,14 +532,6 @@ __global__ __launch_bounds__(kGridThreads) void visit_permute_kernel(const float
   yv[e] = y[(int64_t)order[v] * C + (e - v * C)];
 }
 
-// k-space spread work unit: `count` samples of tile `tile` starting at
-// `start` in the tile-sorted sample list.  slot < 0: the unit is the whole
-// tile and writes the grid; slot >= 0: the unit writes a partial tile into
-// scratch slot `slot`, and a reduce step sums the slots of the tile.
-struct KUnit {
-  int tile, start, count, slot;
-};
-
 // Tile of the k-space spread.  The LDS accumulator holds one plane of P
 // complex values per coil; inside a plane the point (l0, l1, l2) sits at
 // l0 * S0 + l1 * S1 + l2.  P = 4 (mod 16) puts the four coils of a wave on
@@ -521,19 +580,20 @@ __host__ __device__ inline size_t kspread_lds_bytes(const KTile& kt, int C) {
 // has ceil(C/4) waves.  taps_v and yv are in visit order: the unit's
 // samples are taps_v[start .. start + count) and yv[(start ..)][C].
 template <int NDIM, int S>
-__global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ units, int nunits,
-                                                      const KTap* __restrict__ taps_v,
-                                                      const float2* __restrict__ yv, int C,
-                                                      typename Elem<S>::T* __restrict__ grid,
-                                                      float2* __restrict__ partial, Dims dm, KTile kt,
+__global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T> bt, int C, Dims dm, KTile kt,
                                                       KbPoly kb, FastDiv cdiv) {
+  const int bp = batch_member(bt.first, bt.n, blockIdx.x);
+  const KTap* __restrict__ taps_v = bt.taps[bp];
+  const float2* __restrict__ yv = bt.yin[bp];
+  typename Elem<S>::T* __restrict__ grid = bt.grid[bp];
+  float2* __restrict__ partial = bt.partial[bp];
   extern __shared__ float2 acc[];  // [C][P] accumulator, [4][64] garbage, [kSpreadBatch][C] coil values
   __shared__ int4 st_off[kSpreadBatch];
   __shared__ float4 st_w[kSpreadBatch][3];
   float2* dump = acc + (size_t)C * kt.P;
   float2* st_y = dump + kSpreadDump;
   const int nthr = blockDim.x;
-  const KUnit un = units[blockIdx.x];
+  const KUnit un = bt.units[bp][blockIdx.x - bt.first[bp]];
   int lo[3] = {0, 0, 0};
   ktile_origin(un.tile, kt, NDIM, lo);
   {
@@ -659,16 +719,14 @@ __global__ __launch_bounds__(512) void kspread_kernel(const KUnit* __restrict__ 
 }
 
 // sum the partial tiles of every split tile (fixed slot order) and write them
-struct KSplit {
-  int tile, first_slot, nslots;
-};
 
 template <int NDIM, int S>
-__global__ __launch_bounds__(kGridThreads) void kspread_reduce_kernel(const KSplit* __restrict__ splits,
-                                                                      const float2* __restrict__ partial,
-                                                                      int C, typename Elem<S>::T* __restrict__ grid,
+__global__ __launch_bounds__(kGridThreads) void kspread_reduce_kernel(KBatch<typename Elem<S>::T> bt, int C,
                                                                       Dims dm, KTile kt) {
-  const KSplit sp = splits[blockIdx.x];
+  const int bp = batch_member(bt.first, bt.n, blockIdx.x);
+  const float2* __restrict__ partial = bt.partial[bp];
+  typename Elem<S>::T* __restrict__ grid = bt.grid[bp];
+  const KSplit sp = bt.splits[bp][blockIdx.x - bt.first[bp]];
   int lo[3] = {0, 0, 0};
   ktile_origin(sp.tile, kt, NDIM, lo);
   const int volC = kt.vol * C;

@@ -126,6 +126,10 @@ struct isg_plan {
   int64_t N = 0, NG = 0;
   int C = 1, P = 1;
   int storage = 0;
+  // options (isg_plan_set_option)
+  int opt_spread_chunk = 512;  // samples per k-space spread work unit
+  int opt_phase_batch = 1;     // states per k-space gather / spread launch
+  int opt_graph = 0;           // isg_normal replays a captured graph
   hipStream_t stream = nullptr;
   int device = 0;
   int ncu = 256;  // compute units of the device
@@ -147,7 +151,7 @@ struct isg_plan {
   float2* bufC = nullptr;   // [G0][G1][n2]
   float2* mbuf = nullptr;   // [N]
   float2* wbuf = nullptr;   // [P][N]
-  void* kgrid = nullptr;    // [NG][C]
+  DevBuf kgrid;             // [batch][NG][C]
   void* k1buf = nullptr;
   void* k2buf = nullptr;
   DevBuf ybuf;              // normal-operator data, grown on demand
@@ -157,8 +161,18 @@ struct isg_plan {
   double* cg_part = nullptr;
   CgScalars* cg_sc = nullptr;
   DevBuf cg_hist;
+  DevBuf tune_out;  // autotuner output image
   hipStream_t own_stream = nullptr;  // CG capture stream when the caller's is the null stream
   int64_t bytes = 0;
+  // bumped whenever device memory a captured graph may reference is freed or
+  // moved (buffer growth, unit rebuilds, handle destruction, option changes)
+  uint64_t generation = 0;
+  struct NormalGraph {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<const void*> key;
+    double lam = 0;
+  } ngraph;
   // per-kernel event timing (off unless enabled)
   struct Pending {
     std::string tag;
@@ -243,6 +257,8 @@ struct isg_traj {
   KSplit* splits = nullptr;
   int nsplits = 0;
   int nslots = 0;
+  int chunk = 0;                  // spread chunk the units were built for
+  std::vector<int> tile_first;    // host: tile-sorted visits of tile t are tile_first[t] .. tile_first[t+1]
 };
 
 static void* dmalloc(isg_plan* pl, size_t bytes) {
@@ -265,6 +281,7 @@ static void* plan_alloc(isg_plan* pl, size_t bytes) {
 
 static void grow(isg_plan* pl, DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes) return;
+  pl->generation++;
   if (b.p) {
     HIP_OK(hipStreamSynchronize(pl->stream));
     HIP_OK(hipFree(b.p));
@@ -383,6 +400,13 @@ static bool fft2_supported(int L) {
   }
 }
 
+// the same tile with XCD-contiguous workgroup order (measured faster for the
+// axis-1 passes, whose lines are 30 KB apart; slower for the axis-0 passes)
+static Tile2 xcd_order(Tile2 g) {
+  g.tiles = -1;
+  return g;
+}
+
 static Tile2 make_tile2(int64_t A, int64_t B, int L, int nb_fixed) {
   int L1 = 4, L2 = 8;
   switch (L) {
@@ -413,6 +437,7 @@ static Tile2 make_tile2(int64_t A, int64_t B, int L, int nb_fixed) {
   int LS = L1 * (L2 + 1);
   if (!(LS & 1)) LS += 1;
   g.LS = LS;
+  g.tiles = 0;
   return g;
 }
 
@@ -427,10 +452,19 @@ static void launch_fft2(isg_plan* pl, const char* tag, const Ld& ld, const St& s
   auto kern = fft2_kernel<L1, L2, SG, M1, M2, Ld, St>;
   allow_lds(kern, lds);
   const int64_t tiles = ((g.A + g.na - 1) / g.na) * g.tiles_b;
-  const int64_t gx = std::min<int64_t>(tiles, 1 << 30);
-  const int64_t gy = (tiles + gx - 1) / gx;
+  Tile2 gl = g;
+  int64_t gx, gy;
+  if (g.tiles < 0 && tiles <= (1 << 30)) {  // XCD-contiguous order requested (see fft2_kernel)
+    gl.tiles = tiles;
+    gx = 8 * ((tiles + 7) / 8);
+    gy = 1;
+  } else {
+    gl.tiles = 0;
+    gx = std::min<int64_t>(tiles, 1 << 30);
+    gy = (tiles + gx - 1) / gx;
+  }
   Tick tick(pl, tag);
-  hipLaunchKernelGGL(kern, dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, pl->stream, ld, st, g);
+  hipLaunchKernelGGL(kern, dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, pl->stream, ld, st, gl);
   LAUNCH_OK();
 }
 
@@ -662,7 +696,7 @@ static int warp_ntiles(const isg_plan* pl) {
 
 // U = sum_p P_{d_p} w_p over the given states
 static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const float2* const* w, float2* U) {
-  const size_t lds = sizeof(float) * 4 * (size_t)pl->wtile.P * kWarpWaves;
+  const size_t lds = warp_spread_lds_bytes(pl->wtile, pl->ndim);
   for (int p0 = 0; p0 < P; p0 += kMaxPhasesPerLaunch) {
     WarpSpreadPhases ph;
     memset(&ph, 0, sizeof(ph));
@@ -675,7 +709,11 @@ static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const 
     }
     const int acc = p0 > 0 ? 1 : 0;
     const int nt = warp_ntiles(pl);
-    const unsigned nblk = (unsigned)nt;  // one workgroup per tile
+    const unsigned nblk = 8u * (unsigned)((nt + 7) / 8);  // one workgroup per tile, XCD-contiguous order
+    if (pl->ndim == 3)
+      allow_lds(warp_spread_kernel<3>, lds);
+    else
+      allow_lds(warp_spread_kernel<2>, lds);
     Tick tick(pl, "warp_spread");
     if (pl->ndim == 3)
       hipLaunchKernelGGL(warp_spread_kernel<3>, dim3(nblk), dim3(kGridThreads), lds, pl->stream, ph, U, acc, nt,
@@ -782,7 +820,7 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
                                  ld2<S>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
                                  st2<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, kDense,
                                         axis_store_scale(pl, 1)),
-                                 make_tile2(n0, (int64_t)G2 * C, G1, 0));
+                                 xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
     // centred pad, F along axis 0
     run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0,
                                  ld2<S>(pl, pl->k2buf, 0, (int64_t)G1 * G2 * C, kCentred, G0),
@@ -869,7 +907,7 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
                                  ld2<S>(pl, pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, kDense, G1),
                                  st2<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred,
                                         axis_store_scale(pl, 1)),
-                                 make_tile2(n0, (int64_t)G2 * C, G1, 0));
+                                 xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G2, ld2<S>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
                                  st2_reduce(pl, w, Sm, n2, n1, G2), make_tile2((int64_t)n0 * n1, C, G2, C));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
@@ -937,58 +975,110 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
 }
 
 // y[j][c] in sample order, or (to_visits) y[v][c] for every spread visit v
+// One state's share of a batched k-space interpolation: its trajectory, its
+// coil-expanded grid and its data.
+struct KJob {
+  const isg_traj* tr;
+  void* grid;
+  const float2* yin;  // spread input, visit order [nvis][C]
+  float2* yout;       // gather output ([M][C], or [nvis][C] in visit order)
+};
+
+// y = G_p grid_p for every job, kMaxPhasesPerLaunch states per launch
 template <int S>
-static void kgather_t(isg_plan* pl, const void* grid, const isg_traj* tr, float2* y, bool to_visits) {
-  const int* voff = to_visits ? tr->vis_off : nullptr;
-  const int* vl = to_visits ? tr->vis : nullptr;
-  auto grd = (const typename Elem<S>::T*)grid;
-  Tick tick(pl, "kgather");
+static void kgather_t(isg_plan* pl, const KJob* jobs, int n, bool to_visits) {
+  using T = typename Elem<S>::T;
   const int spw = 64 / pl->C;  // samples per wavefront
-  const int64_t waves = (tr->M + spw - 1) / spw;
-  const unsigned nblk = (unsigned)((waves + kGridThreads / 64 - 1) / (kGridThreads / 64));
-  if (pl->ndim == 3)
-    hipLaunchKernelGGL((kgather_kernel<3, S>), dim3(nblk), dim3(kGridThreads), 0, pl->stream, grd, tr->taps, tr->M,
-                       y, pl->C, pl->dims, pl->kb, voff, vl);
-  else
-    hipLaunchKernelGGL((kgather_kernel<2, S>), dim3(nblk), dim3(kGridThreads), 0, pl->stream, grd, tr->taps, tr->M,
-                       y, pl->C, pl->dims, pl->kb, voff, vl);
-  LAUNCH_OK();
+  for (int j0 = 0; j0 < n; j0 += kMaxPhasesPerLaunch) {
+    KBatch<T> bt;
+    memset(&bt, 0, sizeof(bt));
+    bt.n = std::min(kMaxPhasesPerLaunch, n - j0);
+    int64_t blocks = 0;
+    for (int i = 0; i < bt.n; ++i) {
+      const KJob& jb = jobs[j0 + i];
+      bt.first[i] = (int)blocks;
+      bt.taps[i] = jb.tr->taps;
+      bt.count[i] = jb.tr->M;
+      bt.vis_off[i] = to_visits ? jb.tr->vis_off : nullptr;
+      bt.vis[i] = to_visits ? jb.tr->vis : nullptr;
+      bt.yout[i] = jb.yout;
+      bt.grid[i] = (T*)jb.grid;
+      const int64_t waves = (jb.tr->M + spw - 1) / spw;
+      blocks += (waves + kGridThreads / 64 - 1) / (kGridThreads / 64);
+    }
+    bt.first[bt.n] = (int)blocks;
+    Tick tick(pl, "kgather");
+    if (pl->ndim == 3)
+      hipLaunchKernelGGL((kgather_kernel<3, S>), dim3((unsigned)blocks), dim3(kGridThreads), 0, pl->stream, bt,
+                         pl->C, pl->dims, pl->kb);
+    else
+      hipLaunchKernelGGL((kgather_kernel<2, S>), dim3((unsigned)blocks), dim3(kGridThreads), 0, pl->stream, bt,
+                         pl->C, pl->dims, pl->kb);
+    LAUNCH_OK();
+  }
 }
 
-// spread the visit-ordered data yv ([nvis][C]) of trajectory tr onto grid;
-// the "kspread" tag times the spread kernel alone, "kspread_reduce" the
-// fixed-order reduction of split tiles
+// grid_p = G_p^H y_p for every job (visit-ordered inputs), kMaxPhasesPerLaunch
+// states per launch; the "kspread" tag times the spread kernel alone,
+// "kspread_reduce" the fixed-order reduction of split tiles
 template <int NDIM, int S>
-static void kspread_nd(isg_plan* pl, const isg_traj* tr, const float2* yv, typename Elem<S>::T* grd, float2* part,
-                       size_t lds, int kthreads) {
-  auto k = kspread_kernel<NDIM, S>;
-  allow_lds(k, lds);
-  {
-    Tick tick(pl, "kspread");
-    hipLaunchKernelGGL(k, dim3(tr->nunits), dim3(kthreads), lds, pl->stream, tr->units, tr->nunits, tr->taps_v,
-                       yv, pl->C, grd, part, pl->dims, pl->ktile, pl->kb, make_fastdiv(pl->C));
-    LAUNCH_OK();
-  }
-  if (tr->nsplits) {
-    Tick tick(pl, "kspread_reduce");
-    hipLaunchKernelGGL((kspread_reduce_kernel<NDIM, S>), dim3(tr->nsplits), dim3(kGridThreads), 0, pl->stream,
-                       tr->splits, part, pl->C, grd, pl->dims, pl->ktile);
-    LAUNCH_OK();
-  }
-}
-
-template <int S>
-static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* yv, void* grid) {
-  auto grd = (typename Elem<S>::T*)grid;
+static void kspread_nd(isg_plan* pl, const KJob* jobs, int n) {
+  using T = typename Elem<S>::T;
   const size_t lds = kspread_lds_bytes(pl->ktile, pl->C);
   const size_t volC = (size_t)pl->ktile.vol * pl->C;
-  if (tr->nslots) grow(pl, pl->partial, sizeof(float2) * volC * tr->nslots);
-  float2* part = (float2*)pl->partial.p;
   const int kthreads = 64 * ((pl->C + 3) / 4);  // one wave per 4 coils
+  auto k = kspread_kernel<NDIM, S>;
+  allow_lds(k, lds);
+  for (int j0 = 0; j0 < n; j0 += kMaxPhasesPerLaunch) {
+    const int nb = std::min(kMaxPhasesPerLaunch, n - j0);
+    int64_t slots = 0;
+    for (int i = 0; i < nb; ++i) slots += jobs[j0 + i].tr->nslots;
+    if (slots) grow(pl, pl->partial, sizeof(float2) * volC * slots);
+    KBatch<T> bt;
+    memset(&bt, 0, sizeof(bt));
+    bt.n = nb;
+    int64_t units = 0, splits = 0, slot0 = 0;
+    for (int i = 0; i < nb; ++i) {
+      const KJob& jb = jobs[j0 + i];
+      bt.first[i] = (int)units;
+      bt.units[i] = jb.tr->units;
+      bt.taps[i] = jb.tr->taps_v;
+      bt.yin[i] = jb.yin;
+      bt.grid[i] = (T*)jb.grid;
+      bt.partial[i] = (float2*)pl->partial.p + slot0 * volC;
+      units += jb.tr->nunits;
+      splits += jb.tr->nsplits;
+      slot0 += jb.tr->nslots;
+    }
+    bt.first[nb] = (int)units;
+    {
+      Tick tick(pl, "kspread");
+      hipLaunchKernelGGL(k, dim3((unsigned)units), dim3(kthreads), lds, pl->stream, bt, pl->C, pl->dims, pl->ktile,
+                         pl->kb, make_fastdiv(pl->C));
+      LAUNCH_OK();
+    }
+    if (splits) {
+      int64_t s0 = 0;
+      for (int i = 0; i < nb; ++i) {
+        bt.first[i] = (int)s0;
+        bt.splits[i] = jobs[j0 + i].tr->splits;
+        s0 += jobs[j0 + i].tr->nsplits;
+      }
+      bt.first[nb] = (int)s0;
+      Tick tick(pl, "kspread_reduce");
+      hipLaunchKernelGGL((kspread_reduce_kernel<NDIM, S>), dim3((unsigned)splits), dim3(kGridThreads), 0, pl->stream,
+                         bt, pl->C, pl->dims, pl->ktile);
+      LAUNCH_OK();
+    }
+  }
+}
+
+template <int S>
+static void kspread_t(isg_plan* pl, const KJob* jobs, int n) {
   if (pl->ndim == 3)
-    kspread_nd<3, S>(pl, tr, yv, grd, part, lds, kthreads);
+    kspread_nd<3, S>(pl, jobs, n);
   else
-    kspread_nd<2, S>(pl, tr, yv, grd, part, lds, kthreads);
+    kspread_nd<2, S>(pl, jobs, n);
 }
 
 #define STORAGE_DISPATCH(pl, fn, ...)                                  \
@@ -1000,10 +1090,8 @@ static void kspread_t(isg_plan* pl, const isg_traj* tr, const float2* yv, void* 
     }                                                                  \
   } while (0)
 
-// data of one state in sample order -> spread-visit order (into ybuf)
-static float2* to_visit_order(isg_plan* pl, const isg_traj* tr, const float2* y) {
-  grow(pl, pl->ybuf, sizeof(float2) * (size_t)std::max<int64_t>(1, tr->nvis) * pl->C);
-  float2* yv = (float2*)pl->ybuf.p;
+// data of one state in sample order -> spread-visit order (into yv)
+static float2* to_visit_order(isg_plan* pl, const isg_traj* tr, const float2* y, float2* yv) {
   const int64_t n = tr->nvis * pl->C;
   if (n > 0) {
     Tick tick(pl, "visit_permute");
@@ -1014,47 +1102,88 @@ static float2* to_visit_order(isg_plan* pl, const isg_traj* tr, const float2* y)
   return yv;
 }
 
-static void ensure_kspace(isg_plan* pl) {
-  if (pl->kgrid) return;
+// scratch of the k-space stages for `nb` states processed together: their
+// grids (kgrid, [nb][NG][C]) and their visit-ordered data (ybuf)
+static void ensure_kspace(isg_plan* pl, int nb = 1, int64_t visits = 0) {
   const size_t es = pl->storage == kFP32 ? 8 : 4;
   const int64_t C = pl->C;
-  pl->kgrid = plan_alloc(pl, es * (size_t)pl->NG * C);
-  if (pl->ndim == 3) {
-    pl->k1buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->n[1] * pl->G[2] * C);
-    pl->k2buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->G[1] * pl->G[2] * C);
-  } else {
-    pl->k1buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->G[1] * C);
+  if (!pl->k1buf) {
+    if (pl->ndim == 3) {
+      pl->k1buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->n[1] * pl->G[2] * C);
+      pl->k2buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->G[1] * pl->G[2] * C);
+    } else {
+      pl->k1buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->G[1] * C);
+    }
+    pl->wbuf = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->N * pl->P);
   }
-  pl->wbuf = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->N * pl->P);
+  grow(pl, pl->kgrid, es * (size_t)pl->NG * C * (size_t)std::max(1, nb));
+  grow(pl, pl->ybuf, sizeof(float2) * (size_t)std::max<int64_t>(1, visits) * C);
+}
+
+static void* grid_of(const isg_plan* pl, int i) {
+  const size_t es = pl->storage == kFP32 ? 8 : 4;
+  return (char*)pl->kgrid.p + es * (size_t)pl->NG * pl->C * (size_t)i;
+}
+
+// states per batch of the k-space stages
+static int phase_batch(const isg_plan* pl, int P) { return std::max(1, std::min(P, pl->opt_phase_batch)); }
+
+static int64_t group_visits(const isg_traj* const* k, int p0, int nb) {
+  int64_t v = 0;
+  for (int i = 0; i < nb; ++i) v += k[p0 + i]->nvis;
+  return v;
 }
 
 // ---------------------------------------------------------------------------
-// operator sequences
+// operator sequences.  States go in groups of phase_batch(); within a group
+// the coil FFT passes run per state and the k-space gather and spread run
+// as one launch over the group.
 // ---------------------------------------------------------------------------
 static void op_sense_forward(isg_plan* pl, int P, const float2* x, const isg_motion* const* d, const float2* S,
                              const isg_traj* const* k, float2* y) {
-  ensure_kspace(pl);
+  const int B = phase_batch(pl, P);
+  ensure_kspace(pl, B);
   upsample(pl, x, pl->ugrid);
   int64_t off = 0;
-  for (int p = 0; p < P; ++p) {
-    warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
-    STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, pl->kgrid, k[p]);
-    STORAGE_DISPATCH(pl, kgather_t, pl, pl->kgrid, k[p], y + off, false);
-    off += k[p]->M * pl->C;
+  std::vector<KJob> jobs(B);
+  for (int p0 = 0; p0 < P; p0 += B) {
+    const int nb = std::min(B, P - p0);
+    for (int i = 0; i < nb; ++i) {
+      const int p = p0 + i;
+      warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
+      STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, grid_of(pl, i), k[p]);
+      jobs[i] = KJob{k[p], grid_of(pl, i), nullptr, y + off};
+      off += k[p]->M * pl->C;
+    }
+    STORAGE_DISPATCH(pl, kgather_t, pl, jobs.data(), nb, false);
   }
 }
 
 static void op_sense_adjoint(isg_plan* pl, int P, const float2* y, const isg_motion* const* d, const float2* S,
                              const isg_traj* const* k, float2* x) {
-  ensure_kspace(pl);
+  const int B = phase_batch(pl, P);
+  int64_t vmax = 1;
+  for (int p0 = 0; p0 < P; p0 += B) vmax = std::max(vmax, group_visits(k, p0, std::min(B, P - p0)));
+  ensure_kspace(pl, B, vmax);
   std::vector<const float2*> w(P);
+  std::vector<KJob> jobs(B);
   int64_t off = 0;
-  for (int p = 0; p < P; ++p) {
-    const float2* yv = to_visit_order(pl, k[p], y + off);
-    STORAGE_DISPATCH(pl, kspread_t, pl, k[p], yv, pl->kgrid);
-    STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, S, pl->wbuf + (int64_t)p * pl->N, k[p]);
-    w[p] = pl->wbuf + (int64_t)p * pl->N;
-    off += k[p]->M * pl->C;
+  for (int p0 = 0; p0 < P; p0 += B) {
+    const int nb = std::min(B, P - p0);
+    float2* yv = (float2*)pl->ybuf.p;
+    for (int i = 0; i < nb; ++i) {
+      const int p = p0 + i;
+      to_visit_order(pl, k[p], y + off, yv);
+      jobs[i] = KJob{k[p], grid_of(pl, i), yv, nullptr};
+      yv += k[p]->nvis * pl->C;
+      off += k[p]->M * pl->C;
+    }
+    STORAGE_DISPATCH(pl, kspread_t, pl, jobs.data(), nb);
+    for (int i = 0; i < nb; ++i) {
+      const int p = p0 + i;
+      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, grid_of(pl, i), S, pl->wbuf + (int64_t)p * pl->N, k[p]);
+      w[p] = pl->wbuf + (int64_t)p * pl->N;
+    }
   }
   warp_spread(pl, P, d, w.data(), pl->ugrid);
   upsample_adjoint(pl, pl->ugrid, x);
@@ -1062,20 +1191,30 @@ static void op_sense_adjoint(isg_plan* pl, int P, const float2* y, const isg_mot
 
 static void op_normal(isg_plan* pl, int P, const float2* x, double lam, const isg_motion* const* d, const float2* S,
                       const isg_traj* const* k, float2* out) {
-  ensure_kspace(pl);
-  int64_t Vmax = 1;
-  for (int p = 0; p < P; ++p) Vmax = std::max(Vmax, k[p]->nvis);
-  grow(pl, pl->ybuf, sizeof(float2) * (size_t)Vmax * pl->C);
-  float2* y = (float2*)pl->ybuf.p;
+  const int B = phase_batch(pl, P);
+  int64_t vmax = 1;
+  for (int p0 = 0; p0 < P; p0 += B) vmax = std::max(vmax, group_visits(k, p0, std::min(B, P - p0)));
+  ensure_kspace(pl, B, vmax);
   upsample(pl, x, pl->ugrid);
   std::vector<const float2*> w(P);
-  for (int p = 0; p < P; ++p) {
-    warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
-    STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, pl->kgrid, k[p]);
-    STORAGE_DISPATCH(pl, kgather_t, pl, pl->kgrid, k[p], y, true);  // straight into visit order
-    STORAGE_DISPATCH(pl, kspread_t, pl, k[p], y, pl->kgrid);
-    STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, S, pl->wbuf + (int64_t)p * pl->N, k[p]);
-    w[p] = pl->wbuf + (int64_t)p * pl->N;
+  std::vector<KJob> jobs(B);
+  for (int p0 = 0; p0 < P; p0 += B) {
+    const int nb = std::min(B, P - p0);
+    float2* yv = (float2*)pl->ybuf.p;
+    for (int i = 0; i < nb; ++i) {
+      const int p = p0 + i;
+      warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
+      STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, grid_of(pl, i), k[p]);
+      jobs[i] = KJob{k[p], grid_of(pl, i), yv, yv};  // gathered straight into visit order, spread from there
+      yv += k[p]->nvis * pl->C;
+    }
+    STORAGE_DISPATCH(pl, kgather_t, pl, jobs.data(), nb, true);
+    STORAGE_DISPATCH(pl, kspread_t, pl, jobs.data(), nb);
+    for (int i = 0; i < nb; ++i) {
+      const int p = p0 + i;
+      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, grid_of(pl, i), S, pl->wbuf + (int64_t)p * pl->N, k[p]);
+      w[p] = pl->wbuf + (int64_t)p * pl->N;
+    }
   }
   warp_spread(pl, P, d, w.data(), pl->ugrid);
   upsample_adjoint(pl, pl->ugrid, out);
@@ -1172,10 +1311,49 @@ static bool traj_masked(const isg_plan* pl) {
          (pl->ndim == 3 || fft2_supported(pl->G[1]));
 }
 
-static int kspread_chunk() {
-  const char* e = getenv("ISG_SPREAD_CHUNK");
-  const int v = e ? atoi(e) : 0;
-  return v > 0 ? v : 512;
+
+// Spread work units of a prepared trajectory for the plan's chunk size:
+// one unit per touched tile, or (tiles with more than `chunk` visits) one
+// unit per chunk writing a partial tile, summed afterwards in slot order.
+// Untouched tiles get no unit when the axis-0 passes skip them, else a unit
+// that writes zeros.  Units are ordered longest first.
+static void build_units(isg_plan* pl, isg_traj* tr) {
+  const int chunk = pl->opt_spread_chunk;
+  const bool masked = traj_masked(pl);
+  const std::vector<int>& cnt = tr->tile_first;
+  const int ntiles = (int)cnt.size() - 1;
+  std::vector<KUnit> units;
+  std::vector<KSplit> splits;
+  int slots = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    const int beg = cnt[t], c = cnt[t + 1] - cnt[t];
+    if (c == 0 && masked) continue;
+    if (c <= chunk) {
+      units.push_back(KUnit{t, beg, c, -1});
+    } else {
+      const int nch = (c + chunk - 1) / chunk;
+      splits.push_back(KSplit{t, slots, nch});
+      for (int q = 0; q < nch; ++q) units.push_back(KUnit{t, beg + q * chunk, std::min(chunk, c - q * chunk), slots + q});
+      slots += nch;
+    }
+  }
+  std::stable_sort(units.begin(), units.end(), [](const KUnit& a, const KUnit& b) { return a.count > b.count; });
+  if (units.empty()) units.push_back(KUnit{0, 0, 0, -1});  // keep the launch non-empty
+  HIP_OK(hipStreamSynchronize(pl->stream));
+  pl->generation++;
+  if (tr->units) HIP_OK(hipFree(tr->units));
+  if (tr->splits) HIP_OK(hipFree(tr->splits));
+  tr->units = nullptr;
+  tr->splits = nullptr;
+  tr->units = (KUnit*)dmalloc(pl, sizeof(KUnit) * units.size());
+  tr->nunits = (int)units.size();
+  tr->splits = (KSplit*)dmalloc(pl, sizeof(KSplit) * std::max<size_t>(1, splits.size()));
+  tr->nsplits = (int)splits.size();
+  tr->nslots = slots;
+  tr->chunk = chunk;
+  HIP_OK(hipMemcpy(tr->units, units.data(), sizeof(KUnit) * units.size(), hipMemcpyHostToDevice));
+  if (!splits.empty())
+    HIP_OK(hipMemcpy(tr->splits, splits.data(), sizeof(KSplit) * splits.size(), hipMemcpyHostToDevice));
 }
 
 static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_traj* tr) {
@@ -1193,12 +1371,13 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
     uint32_t packed = 0;
     for (int i = 0; i < nd; ++i) {
       const double kap = (double)pl->G[i] * (double)k[(size_t)j * nd + i];  // exact in FP64
-      double fl = std::floor(kap);
+      const double fl = std::floor(kap);
       float f = (float)(kap - fl);
-      if (f >= 1.0f) {  // fraction rounded up to 1 in FP32: move to the next cell
-        f = 0.0f;
-        fl += 1.0;
-      }
+      // a fraction just below 1 can round up to 1 in FP32.  The taps stay
+      // those of the FP64 cell and the fraction is clamped below 1: moving
+      // to the next cell instead would drop the first tap, whose weight is
+      // the kernel's non-zero edge value just inside its open support.
+      if (f >= 1.0f) f = 0.99999994f;
       t.f[i] = f;
       packed |= (uint32_t)iwrap((int64_t)fl - 1, pl->G[i]) << (10 * i);
     }
@@ -1230,28 +1409,12 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
   std::vector<int> pos(cnt.begin(), cnt.end() - 1);
   std::vector<int> order(std::max(1, cnt[ntiles]));
   for (int64_t j = 0; j < M; ++j) visit(j, [&](int t) { order[pos[t]++] = (int)j; });
-  const int chunk = kspread_chunk();
   const bool masked = traj_masked(pl);
-  std::vector<KUnit> units;
-  std::vector<KSplit> splits;
-  int slots = 0;
   tr->ntouched = 0;
-  for (int t = 0; t < ntiles; ++t) {
-    const int beg = cnt[t], c = cnt[t + 1] - cnt[t];
-    if (c > 0) tr->ntouched++;
-    if (c == 0 && masked) continue;  // untouched tile: the axis-0 passes skip it
-    if (c <= chunk) {
-      units.push_back(KUnit{t, beg, c, -1});
-    } else {
-      const int nch = (c + chunk - 1) / chunk;
-      splits.push_back(KSplit{t, slots, nch});
-      for (int q = 0; q < nch; ++q) units.push_back(KUnit{t, beg + q * chunk, std::min(chunk, c - q * chunk), slots + q});
-      slots += nch;
-    }
-  }
-  // split units first: they are the longest
-  std::stable_sort(units.begin(), units.end(), [](const KUnit& a, const KUnit& b) { return a.count > b.count; });
-  if (units.empty()) units.push_back(KUnit{0, 0, 0, -1});  // keep the launch non-empty
+  for (int t = 0; t < ntiles; ++t)
+    if (cnt[t + 1] > cnt[t]) tr->ntouched++;
+  tr->tile_first = cnt;
+  build_units(pl, tr);
   tr->M = M;
   if (masked) {
     const int ncols = nd == 3 ? pl->ktile.nt[1] * pl->ktile.nt[2] : pl->ktile.nt[1];
@@ -1266,11 +1429,6 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
   }
   tr->taps = (KTap*)dmalloc(pl, sizeof(KTap) * taps.size());
   tr->order = (int*)dmalloc(pl, sizeof(int) * order.size());
-  tr->units = (KUnit*)dmalloc(pl, sizeof(KUnit) * units.size());
-  tr->nunits = (int)units.size();
-  tr->splits = (KSplit*)dmalloc(pl, sizeof(KSplit) * std::max<size_t>(1, splits.size()));
-  tr->nsplits = (int)splits.size();
-  tr->nslots = slots;
   HIP_OK(hipMemcpy(tr->taps, taps.data(), sizeof(KTap) * taps.size(), hipMemcpyHostToDevice));
   {  // visit-ordered taps and, per sample, the list of its visits
     const int64_t nvis = cnt[ntiles];
@@ -1292,9 +1450,6 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
     HIP_OK(hipMemcpy(tr->vis, vlist.data(), sizeof(int) * vlist.size(), hipMemcpyHostToDevice));
   }
   HIP_OK(hipMemcpy(tr->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
-  HIP_OK(hipMemcpy(tr->units, units.data(), sizeof(KUnit) * units.size(), hipMemcpyHostToDevice));
-  if (!splits.empty())
-    HIP_OK(hipMemcpy(tr->splits, splits.data(), sizeof(KSplit) * splits.size(), hipMemcpyHostToDevice));
   return ISG_OK;
 }
 
@@ -1337,6 +1492,171 @@ static isg_status guarded(isg_plan* pl, F&& f) {
   } catch (const std::bad_alloc&) {
     return fail(ISG_ERR_OUT_OF_MEMORY, "device or host allocation failed");
   }
+}
+
+// ---------------------------------------------------------------------------
+// graph replay of the normal operator and the autotuner
+// ---------------------------------------------------------------------------
+static void drop_normal_graph(isg_plan* pl) {
+  if (pl->ngraph.exec) (void)hipGraphExecDestroy(pl->ngraph.exec);
+  if (pl->ngraph.graph) (void)hipGraphDestroy(pl->ngraph.graph);
+  pl->ngraph = isg_plan::NormalGraph{};
+}
+
+// op_normal, replayed from a captured graph when ISG_OPT_GRAPH is set and the
+// arguments, the stream and every buffer the graph references are unchanged
+// since the capture.  A call with new arguments runs eagerly (growing any
+// buffer it needs) and then captures the sequence for the next call.
+static void normal_maybe_graph(isg_plan* pl, int P, const float2* x, double lam, const isg_motion* const* d,
+                               const float2* S, const isg_traj* const* k, float2* out) {
+  if (!pl->opt_graph || pl->stream == nullptr || pl->timing) {
+    op_normal(pl, P, x, lam, d, S, k, out);
+    return;
+  }
+  std::vector<const void*> key = {(const void*)pl->stream, x, S, out, (const void*)(uintptr_t)P};
+  for (int p = 0; p < P; ++p) {
+    key.push_back(d[p]);
+    key.push_back(k[p]);
+  }
+  key.push_back((const void*)(uintptr_t)pl->generation);
+  if (pl->ngraph.exec && pl->ngraph.key == key && pl->ngraph.lam == lam) {
+    HIP_OK(hipGraphLaunch(pl->ngraph.exec, pl->stream));
+    return;
+  }
+  drop_normal_graph(pl);
+  op_normal(pl, P, x, lam, d, S, k, out);
+  const uint64_t gen = pl->generation;
+  hipGraph_t graph = nullptr;
+  HIP_OK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
+  pl->capturing = true;
+  try {
+    op_normal(pl, P, x, lam, d, S, k, out);
+  } catch (...) {
+    pl->capturing = false;
+    hipGraph_t g2 = nullptr;
+    (void)hipStreamEndCapture(pl->stream, &g2);
+    if (g2) (void)hipGraphDestroy(g2);
+    throw;
+  }
+  pl->capturing = false;
+  HIP_OK(hipStreamEndCapture(pl->stream, &graph));
+  if (pl->generation != gen) {  // a buffer moved while capturing: do not keep the graph
+    (void)hipGraphDestroy(graph);
+    return;
+  }
+  hipGraphExec_t exec = nullptr;
+  HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  pl->ngraph.graph = graph;
+  pl->ngraph.exec = exec;
+  pl->ngraph.key = key;
+  pl->ngraph.lam = lam;
+}
+
+// best of `reps` timed normal-operator applications (ms), after one warm-up
+static double time_normal(isg_plan* pl, int P, const float2* x, double lam, const isg_motion* const* d,
+                          const float2* S, const isg_traj* const* k, float2* out, int reps) {
+  normal_maybe_graph(pl, P, x, lam, d, S, k, out);  // warm-up (and capture)
+  hipEvent_t a, b;
+  HIP_OK(hipEventCreate(&a));
+  HIP_OK(hipEventCreate(&b));
+  double best = 1e30;
+  for (int r = 0; r < reps; ++r) {
+    HIP_OK(hipEventRecord(a, pl->stream));
+    normal_maybe_graph(pl, P, x, lam, d, S, k, out);
+    HIP_OK(hipEventRecord(b, pl->stream));
+    HIP_OK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, a, b));
+    best = std::min(best, (double)ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+
+static isg_status tune(isg_plan* pl, int P, const float2* x, const isg_motion* const* d, const float2* S,
+                       isg_traj* const* k, double lam, int reps, char* report, int64_t len) {
+  if (pl->timing) return fail(ISG_ERR_INVALID_ARG, "disable timing before tuning");
+  grow(pl, pl->tune_out, sizeof(float2) * (size_t)pl->N);
+  float2* out = (float2*)pl->tune_out.p;
+  const isg_traj* const* kc = (const isg_traj* const*)k;
+  struct Cand {
+    int chunk, batch, graph;
+    double ms;
+  };
+  std::vector<Cand> tried;
+  auto apply = [&](int chunk, int batch, int graph) {
+    pl->opt_spread_chunk = chunk;
+    pl->opt_phase_batch = batch;
+    pl->opt_graph = graph;
+    pl->generation++;
+    for (int p = 0; p < P; ++p)
+      if (k[p]->chunk != chunk) build_units(pl, k[p]);
+  };
+  auto measure = [&](int chunk, int batch, int graph) -> double {
+    apply(chunk, batch, graph);
+    double ms = 1e30;
+    try {
+      ms = time_normal(pl, P, x, lam, d, S, kc, out, reps);
+    } catch (const std::bad_alloc&) {
+      ms = 1e30;  // does not fit: skipped
+    }
+    tried.push_back(Cand{chunk, batch, graph, ms});
+    return ms;
+  };
+  // coordinate search: chunk (batch 1, no graph), then batch, then graph
+  int best_chunk = pl->opt_spread_chunk, best_batch = 1, best_graph = 0;
+  double best = 1e30;
+  for (int c : {256, 512, 1024, 2048}) {
+    const double ms = measure(c, 1, 0);
+    if (ms < best) {
+      best = ms;
+      best_chunk = c;
+    }
+  }
+  std::vector<int> batches;
+  for (int b : {2, 3, 4, 6, 8, 16})
+    if (b <= std::min(P, kMaxPhasesPerLaunch)) batches.push_back(b);
+  if (P > 1 && P <= kMaxPhasesPerLaunch && std::find(batches.begin(), batches.end(), P) == batches.end())
+    batches.push_back(P);
+  for (int b : batches) {
+    const double ms = measure(best_chunk, b, 0);
+    if (ms < best) {
+      best = ms;
+      best_batch = b;
+    }
+  }
+  if (pl->stream != nullptr) {
+    const double ms = measure(best_chunk, best_batch, 1);
+    if (ms < best) {
+      best = ms;
+      best_graph = 1;
+    }
+  }
+  apply(best_chunk, best_batch, best_graph);
+  drop_normal_graph(pl);
+  HIP_OK(hipStreamSynchronize(pl->stream));
+  if (report && len > 0) {
+    std::string js = "{\"candidates\": [";
+    char buf[160];
+    for (size_t i = 0; i < tried.size(); ++i) {
+      const Cand& c = tried[i];
+      if (c.ms >= 1e29)
+        snprintf(buf, sizeof(buf), "%s{\"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": null}", i ? ", " : "",
+                 c.chunk, c.batch, c.graph);
+      else
+        snprintf(buf, sizeof(buf), "%s{\"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": %.4f}", i ? ", " : "",
+                 c.chunk, c.batch, c.graph, c.ms);
+      js += buf;
+    }
+    snprintf(buf, sizeof(buf), "], \"chosen\": {\"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": %.4f}}",
+             best_chunk, best_batch, best_graph, best);
+    js += buf;
+    const size_t n = std::min<size_t>(js.size(), (size_t)len - 1);
+    memcpy(report, js.data(), n);
+    report[n] = 0;
+  }
+  return ISG_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1405,6 +1725,10 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
     pl->dims.G[i] = pl->G[i];
   }
   pl->dims.N = pl->N;
+  for (int i = 0; i < 3; ++i) {
+    pl->dims.nfd[i] = make_fastdiv((uint32_t)pl->n[i]);
+    pl->dims.invG[i] = (float)(1.0 / pl->G[i]);
+  }
   // spread tiles
   for (int i = 0; i < 3; ++i) {
     pl->wtile.TS[i] = 1;
@@ -1417,18 +1741,20 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
     pl->wtile.TS[i] = std::min(wts, pl->G[i]);
     pl->wtile.nt[i] = (pl->G[i] + pl->wtile.TS[i] - 1) / pl->wtile.TS[i];
   }
+  // dense planes of complex values; plane size = 4 (mod 16) staggers the
+  // copies across banks
   if (pl->ndim == 3) {
-    // rows of TS2, planes at S0 = 4 (mod 32): the 64 taps of an entry hit
-    // distinct banks within each half-wavefront
     pl->wtile.S1 = pl->wtile.TS[2];
-    int s0 = pl->wtile.TS[1] * pl->wtile.TS[2];
-    while (s0 % 32 != 4) ++s0;
-    pl->wtile.S0 = s0;
+    pl->wtile.S0 = pl->wtile.TS[1] * pl->wtile.TS[2];
   } else {
     pl->wtile.S1 = 1;
-    pl->wtile.S0 = pl->wtile.TS[1] + 1;
+    pl->wtile.S0 = pl->wtile.TS[1];
   }
-  pl->wtile.P = pl->wtile.TS[0] * pl->wtile.S0;
+  {
+    int P = pl->wtile.TS[0] * pl->wtile.S0;
+    while (P % 16 != 4) ++P;
+    pl->wtile.P = P;
+  }
   if (pl->ndim == 3) {
     const int t0 = pl->C > 16 ? 4 : 8;
     const int ts[3] = {t0, 8, 8};
@@ -1498,9 +1824,13 @@ isg_status isg_plan_destroy(isg_plan* pl) {
   if (!pl) return ISG_OK;
   if (pl->stream || true) (void)hipStreamSynchronize(pl->stream);
   for (void* p : pl->owned) (void)hipFree(p);
+  if (pl->ngraph.exec) (void)hipGraphExecDestroy(pl->ngraph.exec);
+  if (pl->ngraph.graph) (void)hipGraphDestroy(pl->ngraph.graph);
+  if (pl->kgrid.p) (void)hipFree(pl->kgrid.p);
   if (pl->ybuf.p) (void)hipFree(pl->ybuf.p);
   if (pl->partial.p) (void)hipFree(pl->partial.p);
   if (pl->cg_hist.p) (void)hipFree(pl->cg_hist.p);
+  if (pl->tune_out.p) (void)hipFree(pl->tune_out.p);
   if (pl->own_stream) (void)hipStreamDestroy(pl->own_stream);
   for (auto& p : pl->pending) {
     (void)hipEventDestroy(p.a);
@@ -1574,7 +1904,10 @@ isg_status isg_motion_create(isg_plan* pl, const float* d, isg_motion** out) {
 
 isg_status isg_motion_destroy(isg_motion* mo) {
   if (!mo) return ISG_OK;
-  if (mo->plan) (void)hipStreamSynchronize(mo->plan->stream);
+  if (mo->plan) {
+    (void)hipStreamSynchronize(mo->plan->stream);
+    mo->plan->generation++;
+  }
   for (void* p : {(void*)mo->d, (void*)mo->tile_off, (void*)mo->vox})
     if (p) (void)hipFree(p);
   delete mo;
@@ -1601,7 +1934,10 @@ isg_status isg_traj_create(isg_plan* pl, const float* k, int64_t M, isg_traj** o
 
 isg_status isg_traj_destroy(isg_traj* tr) {
   if (!tr) return ISG_OK;
-  if (tr->plan) (void)hipStreamSynchronize(tr->plan->stream);
+  if (tr->plan) {
+    (void)hipStreamSynchronize(tr->plan->stream);
+    tr->plan->generation++;
+  }
   for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->units, (void*)tr->splits, (void*)tr->colmask,
                   (void*)tr->taps_v, (void*)tr->vis_off, (void*)tr->vis})
     if (p) (void)hipFree(p);
@@ -1705,9 +2041,56 @@ isg_status isg_normal(isg_plan* pl, int P, const void* x, double lambda, const i
   st = check_phases(pl, P, d, k);
   if (st) return st;
   return guarded(pl, [&]() {
-    op_normal(pl, P, (const float2*)x, lambda, d, (const float2*)S, k, (float2*)out);
+    normal_maybe_graph(pl, P, (const float2*)x, lambda, d, (const float2*)S, k, (float2*)out);
     return ISG_OK;
   });
+}
+
+isg_status isg_plan_set_option(isg_plan* pl, isg_option option, int64_t value) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  switch (option) {
+    case ISG_OPT_SPREAD_CHUNK:
+      if (value < 32 || value > 65536) return fail(ISG_ERR_INVALID_ARG, "spread chunk must be in 32..65536");
+      pl->opt_spread_chunk = (int)value;
+      break;
+    case ISG_OPT_PHASE_BATCH:
+      if (value < 1 || value > kMaxPhasesPerLaunch) return fail(ISG_ERR_INVALID_ARG, "phase batch must be in 1..16");
+      pl->opt_phase_batch = (int)value;
+      break;
+    case ISG_OPT_GRAPH:
+      if (value != 0 && value != 1) return fail(ISG_ERR_INVALID_ARG, "graph option must be 0 or 1");
+      pl->opt_graph = (int)value;
+      break;
+    default:
+      return fail(ISG_ERR_INVALID_ARG, "unknown option");
+  }
+  pl->generation++;
+  return ISG_OK;
+}
+
+isg_status isg_plan_get_option(const isg_plan* pl, isg_option option, int64_t* value) {
+  if (!pl || !value) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  switch (option) {
+    case ISG_OPT_SPREAD_CHUNK: *value = pl->opt_spread_chunk; break;
+    case ISG_OPT_PHASE_BATCH: *value = pl->opt_phase_batch; break;
+    case ISG_OPT_GRAPH: *value = pl->opt_graph; break;
+    default: return fail(ISG_ERR_INVALID_ARG, "unknown option");
+  }
+  return ISG_OK;
+}
+
+isg_status isg_plan_tune(isg_plan* pl, int P, const void* x, const isg_motion* const* d, const void* S,
+                         isg_traj* const* k, double lambda, int reps, char* report, int64_t len) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!x || !S) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (reps < 1 || reps > 1000) return fail(ISG_ERR_INVALID_ARG, "reps must be in 1..1000");
+  if (!std::isfinite(lambda)) return fail(ISG_ERR_INVALID_ARG, "lambda must be finite");
+  st = check_phases(pl, P, d, (const isg_traj* const*)k);
+  if (st) return st;
+  return guarded(pl, [&]() -> isg_status { return tune(pl, P, (const float2*)x, d, (const float2*)S, k, lambda,
+                                                       reps, report, len); });
 }
 
 isg_status isg_sense_grad(isg_plan* pl, int P, const void* x, const isg_motion* const* d, const void* S,
@@ -1719,7 +2102,9 @@ isg_status isg_sense_grad(isg_plan* pl, int P, const void* x, const isg_motion* 
   st = check_phases(pl, P, d, k);
   if (st) return st;
   return guarded(pl, [&]() {
-    ensure_kspace(pl);
+    int64_t vmax = 1;
+    for (int p = 0; p < P; ++p) vmax = std::max(vmax, k[p]->nvis);
+    ensure_kspace(pl, 1, vmax);
     const float2* Sm = (const float2*)S;
     // u = the upsampled x, needed by every d-gradient (before the spread reuses ugrid)
     if (grad_d) upsample(pl, (const float2*)x, pl->ugrid);
@@ -1727,10 +2112,11 @@ isg_status isg_sense_grad(isg_plan* pl, int P, const void* x, const isg_motion* 
     int64_t off = 0;
     for (int p = 0; p < P; ++p) {
       // v_p = sum_c conj(S_c) G_p^H r_{p,c}
-      const float2* yv = to_visit_order(pl, k[p], (const float2*)r + off);
-      STORAGE_DISPATCH(pl, kspread_t, pl, k[p], yv, pl->kgrid);
+      float2* yv = to_visit_order(pl, k[p], (const float2*)r + off, (float2*)pl->ybuf.p);
+      const KJob job{k[p], grid_of(pl, 0), yv, nullptr};
+      STORAGE_DISPATCH(pl, kspread_t, pl, &job, 1);
       float2* v = pl->wbuf + (int64_t)p * pl->N;
-      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, pl->kgrid, Sm, v, k[p]);
+      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, grid_of(pl, 0), Sm, v, k[p]);
       w[p] = v;
       if (grad_d) {
         Tick tick(pl, "warp_grad");

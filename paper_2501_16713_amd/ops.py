@@ -158,6 +158,28 @@ class Plan:
         check(self.lib.isg_plan_read_timing(self.handle, buf, len(buf)))
         return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
 
+    def set_option(self, name: str, value: int) -> None:
+        """Set an execution option: "spread_chunk", "phase_batch" or "graph"
+        (include/isg.h, isg_option)."""
+        check(self.lib.isg_plan_set_option(self.handle, _lib.OPTIONS[name], int(value)))
+
+    def get_option(self, name: str) -> int:
+        v = C.c_int64(0)
+        check(self.lib.isg_plan_get_option(self.handle, _lib.OPTIONS[name], C.byref(v)))
+        return v.value
+
+    def tune(self, x, lam, motions, S, trajs, reps: int = 3) -> dict:
+        """Autotune spread chunk, phase batch and graph replay on these
+        inputs; keeps the fastest setting and returns the timing report."""
+        import json
+        x = self._image(x)
+        S = _require(S, torch.complex64, (self.ncoils,) + self.shape, "S")
+        P, dm, km = self._handles(motions, trajs)
+        buf = C.create_string_buffer(1 << 16)
+        self._sync_stream()
+        check(self.lib.isg_plan_tune(self.handle, P, _ptr(x), dm, _ptr(S), km, float(lam), int(reps), buf, len(buf)))
+        return json.loads(buf.value.decode())
+
     def _sync_stream(self):
         check(self.lib.isg_plan_set_stream(self.handle, torch.cuda.current_stream(self.device).cuda_stream))
 

@@ -1,0 +1,141 @@
+"""Batched execution: the k-space gather and spread of several states in one
+launch, graph replay of the normal operator, the spread chunk size and the
+autotuner that picks among them.  None of these may change a result beyond
+floating-point summation order:
+
+* phase batching runs every state's work exactly as the unbatched launch
+  does, so results are compared bit for bit;
+* graph replays re-run the captured kernels, so they are compared bit for
+  bit with the eager call, replay after replay, with eager work between;
+* a different spread chunk changes only the order in which split tiles are
+  summed: 1e-6 relative (a few FP32 roundings), and the result is still held
+  to the oracle's 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_inputs, small_workload
+
+from gpu_util import rel, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2501_16713_amd as isg
+    # uneven per-state sample counts; 36 x 40 x 48 gives ragged spread tiles
+    w = small_workload(shape=(36, 40, 48), ncoils=5, nphases=3, spokes=(30, 90, 55), cfg=140)
+    inp = make_inputs(w)
+    return isg, w, inp
+
+
+def _plan(isg, w, inp, stream=None):
+    import torch
+    plan = isg.Plan(w.shape, ncoils=w.ncoils, nphases=w.nphases)
+    S = to_dev(inp["S"])
+    mots = [plan.motion(to_dev(d)) for d in inp["d"]]
+    trs = [plan.traj(to_dev(k)) for k in inp["k"]]
+    return plan, S, mots, trs
+
+
+def test_phase_batch_is_bit_exact(setup):
+    import torch
+    isg, w, inp = setup
+    plan, S, mots, trs = _plan(isg, w, inp)
+    x = to_dev(inp["x"])
+    M = sum(k.shape[0] for k in inp["k"])
+    y = to_dev((np.random.default_rng(3).standard_normal((M, w.ncoils, 2)) @ [1, 1j]).astype(np.complex64))
+    ref = {}
+    for b in (1, 2, 3):
+        say(f"phase batch {b}")
+        plan.set_option("phase_batch", b)
+        assert plan.get_option("phase_batch") == b
+        res = (plan.sense_forward(x, mots, S, trs), plan.sense_adjoint(y, mots, S, trs),
+               plan.normal(x, 0.3, mots, S, trs))
+        torch.cuda.synchronize()
+        if b == 1:
+            ref = [r.clone() for r in res]
+        else:
+            for a, r in zip(res, ref):
+                assert torch.equal(a, r)
+
+
+def test_graph_replay_is_bit_exact(setup):
+    import torch
+    isg, w, inp = setup
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan, S, mots, trs = _plan(isg, w, inp)
+        x = to_dev(inp["x"])
+        x2 = to_dev(inp["x"][::-1].copy())
+        eager = plan.normal(x, 0.1, mots, S, trs).clone()
+        eager2 = plan.normal(x2, 0.1, mots, S, trs).clone()
+        plan.set_option("graph", 1)
+        out = torch.empty_like(x)
+        for rep in range(4):
+            say(f"graph replay {rep}")
+            plan.normal(x, 0.1, mots, S, trs, out=out)
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager)
+            # eager work of the program between replays
+            z = (x * 2).sum()
+            torch.cuda.synchronize()
+        # new arguments: a new capture, still exact
+        plan.normal(x2, 0.1, mots, S, trs, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager2)
+        # a destroyed and re-created trajectory must not replay a stale graph
+        trs[1].close()
+        trs[1] = plan.traj(to_dev(inp["k"][1]))
+        plan.normal(x2, 0.1, mots, S, trs, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager2)
+        del z
+
+
+def test_spread_chunk_and_oracle(setup):
+    import torch
+    isg, w, inp = setup
+    M = sum(k.shape[0] for k in inp["k"])
+    y = (np.random.default_rng(4).standard_normal((M, w.ncoils, 2)) @ [1, 1j]).astype(np.complex64)
+    outs = {}
+    for chunk in (32, 512):
+        say(f"spread chunk {chunk}")
+        plan = isg.Plan(w.shape, ncoils=w.ncoils, nphases=w.nphases)
+        plan.set_option("spread_chunk", chunk)
+        S = to_dev(inp["S"])
+        mots = [plan.motion(to_dev(d)) for d in inp["d"]]
+        trs = [plan.traj(to_dev(k)) for k in inp["k"]]
+        outs[chunk] = plan.sense_adjoint(to_dev(y), mots, S, trs).cpu().numpy()
+    assert rel(outs[32], outs[512]) < 1e-6
+    ys, off = [], 0
+    for k in inp["k"]:
+        ys.append(y[off:off + k.shape[0]].T)
+        off += k.shape[0]
+    ref = oracle.sense.sense_adjoint(ys, inp["d"], inp["S"], inp["k"], w.shape)
+    assert rel(outs[32], ref) < 1e-5
+
+
+def test_tune_keeps_results(setup):
+    import torch
+    isg, w, inp = setup
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan, S, mots, trs = _plan(isg, w, inp)
+        x = to_dev(inp["x"])
+        before = plan.normal(x, 0.2, mots, S, trs).cpu().numpy()
+        say("tune")
+        rep = plan.tune(x, 0.2, mots, S, trs, reps=2)
+        chosen = rep["chosen"]
+        assert chosen["chunk"] == plan.get_option("spread_chunk")
+        assert chosen["batch"] == plan.get_option("phase_batch")
+        assert chosen["graph"] == plan.get_option("graph")
+        assert len(rep["candidates"]) >= 5
+        after = plan.normal(x, 0.2, mots, S, trs).cpu().numpy()
+        after2 = plan.normal(x, 0.2, mots, S, trs).cpu().numpy()
+    assert rel(after, before) < 1e-6
+    assert np.array_equal(after, after2)

@@ -130,6 +130,36 @@ def test_sense_forward_adjoint(isg, shape, C, P):
     assert rel(xa, want_a) < TOL
 
 
+def test_samples_on_grid_lines(isg):
+    """Readouts along the array axes at (j - L/2)/L: in FP64 some grid
+    coordinates G k fall a few 1e-8 below an integer, so their FP32 fraction
+    rounds to 1.  The taps must stay those of the FP64 cell (the first tap
+    keeps the kernel's non-zero edge value), sample by sample."""
+    shape, C = (36, 40, 48), 2
+    G = [2 * n for n in shape]
+    ks = []
+    for a, L in ((0, 36), (1, 40), (2, 48)):
+        k = np.zeros((L, 3), dtype=np.float32)
+        k[:, a] = (np.arange(-L // 2, L // 2) / L).astype(np.float32)
+        ks.append(k)
+    k = np.concatenate(ks)
+    kap = k.astype(np.float64) * np.array(G)
+    assert ((kap - np.floor(kap)).astype(np.float32) >= 1.0).any()  # the case is exercised
+    x = ellipsoid_phantom(shape, 10, rng(41, 0)).astype(np.complex64)
+    S = coil_maps(shape, C, rng(41, 2))
+    d = np.zeros((3,) + shape, dtype=np.float32)
+    say("samples on grid lines")
+    plan = isg.Plan(shape, ncoils=C)
+    mo, tr = plan.motion(to_dev(d)), plan.traj(to_dev(k))
+    y = plan.sense_forward(to_dev(x), [mo], to_dev(S), [tr]).cpu().numpy()
+    want = pack(oracle.sense.sense_forward(x, [d], S, [k]))
+    per_sample = np.linalg.norm(y - want, axis=1) / np.linalg.norm(want, axis=1).max()
+    assert per_sample.max() < TOL
+    yr = _rand_c(np.random.default_rng(5), y.shape)
+    xa = plan.sense_adjoint(to_dev(yr), [mo], to_dev(S), [tr]).cpu().numpy()
+    assert rel(xa, oracle.sense.sense_adjoint(unpack(yr, [k]), [d], S, [k], shape)) < TOL
+
+
 def test_normal_operator(isg):
     shape, C, P = (16, 20, 24), 3, 2
     say("normal small")
