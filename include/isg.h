@@ -137,11 +137,19 @@ isg_status isg_plan_read_timing(isg_plan* plan, char* buf, int64_t len);
  *   ISG_OPT_GRAPH         1: isg_normal captures its kernel sequence in a HIP
  *                         graph and replays it while its arguments stay the
  *                         same (not on the null stream, not while timing);
- *                         default 0 */
+ *                         default 0
+ *   ISG_OPT_KTILE_T1      extent along axis 1 of the k-space spread tiles
+ *                         (4, 8 or 16; default 8 in 3D, 16 in 2D).  Smaller
+ *                         tiles follow sparse trajectories more closely (the
+ *                         axis-0 passes skip untouched tiles) at more
+ *                         sample visits.  Trajectories prepared for another
+ *                         extent fail with ISG_ERR_STATE until re-created or
+ *                         passed to isg_plan_tune. */
 typedef enum {
   ISG_OPT_SPREAD_CHUNK = 1,
   ISG_OPT_PHASE_BATCH = 2,
-  ISG_OPT_GRAPH = 3
+  ISG_OPT_GRAPH = 3,
+  ISG_OPT_KTILE_T1 = 4
 } isg_option;
 
 /* Set / read an option.  INVALID_ARG for an unknown option or a value out of
@@ -150,12 +158,13 @@ isg_status isg_plan_set_option(isg_plan* plan, isg_option option, int64_t value)
 isg_status isg_plan_get_option(const isg_plan* plan, isg_option option, int64_t* value);
 
 /* Autotuner: times the normal operator sum_p A_p^H A_p x + lambda x on the
- * given inputs for candidate spread chunk sizes, phase batch sizes and graph
- * replay (a coordinate search, each candidate the best of `reps` timed
- * applications after one warm-up), keeps the fastest setting in the plan and
- * re-prepares the trajectories for its chunk size.  Candidates that do not
+ * given inputs for candidate k-space tile extents, spread chunk sizes, phase
+ * batch sizes and graph replay (a coordinate search, each candidate the best
+ * of `reps` timed applications after one warm-up), keeps the fastest setting
+ * in the plan and re-prepares the given trajectories for it (others prepared
+ * on this plan must be re-created if the tile extent changed).  Candidates that do not
  * fit in device memory are skipped.  report (host, may be NULL) receives a
- * JSON object {"candidates": [{"chunk", "batch", "graph", "ms"}...],
+ * JSON object {"candidates": [{"ktile_t1", "chunk", "batch", "graph", "ms"}...],
  * "chosen": {...}} (NUL-terminated, truncated to len bytes).  Synchronizes
  * the stream. */
 isg_status isg_plan_tune(isg_plan* plan, int nphases, const void* x, const isg_motion* const* d,

@@ -680,41 +680,49 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
   }
   __syncthreads();
   // write out, row by row: a tile row (fixed l0, l1) is TS_last * C
-  // contiguous values of the [G...][C] grid
+  // contiguous values of the [G...][C] grid.  Thread t takes element
+  // t mod rowlen of rows t / rowlen, + rpi, + 2 rpi, ... (rpi >= 1 rows per
+  // round, since blockDim >= 16 C >= TS_last C)
   const int volC = kt.vol * C;
   const int rowlen = kt.TS[NDIM - 1] * C;
-  const FastDiv rdiv = kt.rowdiv;  // divides by rowlen
-  for (int e = threadIdx.x; e < volC; e += nthr) {
-    const int row = (int)rdiv.div((uint32_t)e);
-    const int within = e - row * rowlen;
+  const int rpi = nthr / rowlen;
+  const int r0 = threadIdx.x / rowlen;
+  if (r0 < rpi) {
+    const int within = threadIdx.x - r0 * rowlen;
     const int l2 = (int)cdiv.div((uint32_t)within);  // point along the last axis
     const int cc = within - l2 * C;
-    int pi, gl0, gl1 = 0;
-    if constexpr (NDIM == 3) {
-      const int l1 = row % kt.TS[1], l0 = row / kt.TS[1];
-      pi = l0 * kt.S0 + l1 * kt.S1 + l2;
-      gl0 = lo[0] + l0;
-      gl1 = lo[1] + l1;
-    } else {
-      pi = row * kt.S0 + l2;
-      gl0 = lo[0] + row;
-    }
-    const float2 v = acc[(size_t)cc * kt.P + pi];
-    if (un.slot >= 0) {
-      // partial tiles keep the point-major layout e = point * C + coil
-      partial[(int64_t)un.slot * volC + e] = v;
-      continue;
-    }
+    const float2* src = acc + (size_t)cc * kt.P + l2;
     const int gl = lo[NDIM - 1] + l2;
-    bool ok = gl0 < dm.G[0] && gl < dm.G[NDIM - 1];
-    int64_t gi;
-    if constexpr (NDIM == 3) {
-      ok = ok && gl1 < dm.G[1];
-      gi = ((int64_t)gl0 * dm.G[1] + gl1) * dm.G[2] + gl;
-    } else {
-      gi = (int64_t)gl0 * dm.G[1] + gl;
+    const bool okl = gl < dm.G[NDIM - 1];
+    const int nrows = kt.vol / kt.TS[NDIM - 1];
+    for (int row = r0; row < nrows; row += rpi) {
+      int l0, l1 = 0, pi;
+      if constexpr (NDIM == 3) {
+        l0 = row / kt.TS[1];
+        l1 = row - l0 * kt.TS[1];
+        pi = l0 * kt.S0 + l1 * kt.S1;
+      } else {
+        l0 = row;
+        pi = row * kt.S0;
+      }
+      const float2 v = src[pi];
+      if (un.slot >= 0) {
+        // partial tiles keep the point-major layout e = point * C + coil
+        partial[(int64_t)un.slot * volC + row * rowlen + within] = v;
+        continue;
+      }
+      const int gl0 = lo[0] + l0;
+      bool ok = okl && gl0 < dm.G[0];
+      int64_t gi;
+      if constexpr (NDIM == 3) {
+        const int gl1 = lo[1] + l1;
+        ok = ok && gl1 < dm.G[1];
+        gi = ((int64_t)gl0 * dm.G[1] + gl1) * dm.G[2] + gl;
+      } else {
+        gi = (int64_t)gl0 * dm.G[1] + gl;
+      }
+      if (ok) Elem<S>::store(grid + gi * C + cc, v);
     }
-    if (ok) Elem<S>::store(grid + gi * C + cc, v);
   }
 }
 

@@ -130,6 +130,7 @@ struct isg_plan {
   int opt_spread_chunk = 512;  // samples per k-space spread work unit
   int opt_phase_batch = 1;     // states per k-space gather / spread launch
   int opt_graph = 0;           // isg_normal replays a captured graph
+  int opt_ktile_t1 = 8;        // k-space spread tile extent along axis 1
   hipStream_t stream = nullptr;
   int device = 0;
   int ncu = 256;  // compute units of the device
@@ -258,7 +259,9 @@ struct isg_traj {
   int nsplits = 0;
   int nslots = 0;
   int chunk = 0;                  // spread chunk the units were built for
+  int ts[3] = {0, 0, 0};          // k-space tile shape the bins were built for
   std::vector<int> tile_first;    // host: tile-sorted visits of tile t are tile_first[t] .. tile_first[t+1]
+  std::vector<KTap> taps_h;       // host copy of taps (re-binning for another tile shape)
 };
 
 static void* dmalloc(isg_plan* pl, size_t bytes) {
@@ -1027,6 +1030,8 @@ static void kspread_nd(isg_plan* pl, const KJob* jobs, int n) {
   const size_t lds = kspread_lds_bytes(pl->ktile, pl->C);
   const size_t volC = (size_t)pl->ktile.vol * pl->C;
   const int kthreads = 64 * ((pl->C + 3) / 4);  // one wave per 4 coils
+  if (pl->ktile.TS[NDIM - 1] * pl->C > kthreads)  // the write-out takes at least one tile row per round
+    throw HipError{hipErrorInvalidConfiguration, "k-space tile row longer than the spread workgroup"};
   auto k = kspread_kernel<NDIM, S>;
   allow_lds(k, lds);
   for (int j0 = 0; j0 < n; j0 += kMaxPhasesPerLaunch) {
@@ -1301,6 +1306,42 @@ static isg_status prepare_motion(isg_plan* pl, const float* d_dev, isg_motion* m
 static bool fft2_supported(int L);
 // untouched-tile skipping needs the two-step FFT on axis 0 and at most 64
 // tiles along it (one 64-bit mask per tile column)
+// k-space spread tiles with extent t1 along axis 1 (3D: 8 along axes 0 and 2,
+// 4 along axis 0 for more than 16 coils to bound the LDS accumulator; 2D:
+// 16 along axis 0)
+static void set_ktile(isg_plan* pl, int t1) {
+  for (int i = 0; i < 3; ++i) {
+    pl->ktile.TS[i] = 1;
+    pl->ktile.nt[i] = 1;
+  }
+  if (pl->ndim == 3) {
+    const int ts[3] = {pl->C > 16 ? 4 : 8, t1, 8};
+    for (int i = 0; i < 3; ++i) pl->ktile.TS[i] = std::min(ts[i], pl->G[i]);
+  } else {
+    const int ts[2] = {16, t1};
+    for (int i = 0; i < 2; ++i) pl->ktile.TS[i] = std::min(ts[i], pl->G[i]);
+  }
+  pl->ktile.vol = 1;
+  for (int i = 0; i < pl->ndim; ++i) {
+    pl->ktile.nt[i] = (pl->G[i] + pl->ktile.TS[i] - 1) / pl->ktile.TS[i];
+    pl->ktile.vol *= pl->ktile.TS[i];
+  }
+  // dense planes of complex values; plane size = 4 (mod 16) puts the four
+  // coils of a spread wave on distinct banks
+  if (pl->ndim == 3) {
+    pl->ktile.S1 = pl->ktile.TS[2];
+    pl->ktile.S0 = pl->ktile.TS[1] * pl->ktile.TS[2];
+  } else {
+    pl->ktile.S1 = 1;
+    pl->ktile.S0 = pl->ktile.TS[1];
+  }
+  int P = pl->ktile.TS[0] * pl->ktile.S0;
+  while (P % 16 != 4) ++P;
+  pl->ktile.P = P;
+  pl->ktile.rowdiv = make_fastdiv((uint32_t)(pl->ktile.TS[pl->ndim - 1] * pl->C));
+  pl->opt_ktile_t1 = t1;
+}
+
 static bool traj_masked(const isg_plan* pl) {
   const char* e = getenv("ISG_NO_TILE_MASK");
   if (e && atoi(e)) return false;
@@ -1356,35 +1397,26 @@ static void build_units(isg_plan* pl, isg_traj* tr) {
     HIP_OK(hipMemcpy(tr->splits, splits.data(), sizeof(KSplit) * splits.size(), hipMemcpyHostToDevice));
 }
 
-static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_traj* tr) {
+// free a device array of a trajectory (its memory leaves the plan's count)
+static void traj_free(isg_plan* pl, void*& p) {
+  if (p) {
+    HIP_OK(hipFree(p));
+    p = nullptr;
+  }
+}
+
+// Tile bookkeeping of a trajectory for the plan's current k-space tile
+// shape: the tile-sorted visit order, touched-tile masks, visit-ordered taps,
+// each sample's visit list and the spread work units.
+static void bin_traj(isg_plan* pl, isg_traj* tr) {
   const int nd = pl->ndim;
-  std::vector<float> k((size_t)M * nd);
-  HIP_OK(hipMemcpy(k.data(), k_dev, sizeof(float) * k.size(), hipMemcpyDeviceToHost));
-  for (float v : k) {
-    if (!std::isfinite(v)) return fail(ISG_ERR_NOT_FINITE, "trajectory holds NaN or Inf");
-    if (std::fabs(v) > 1.0e6f) return fail(ISG_ERR_INVALID_ARG, "trajectory magnitude exceeds 1e6 cycles/voxel");
-  }
-  std::vector<KTap> taps(M);
-  for (int64_t j = 0; j < M; ++j) {
-    KTap t;
-    t.f[0] = t.f[1] = t.f[2] = 0.f;
-    uint32_t packed = 0;
-    for (int i = 0; i < nd; ++i) {
-      const double kap = (double)pl->G[i] * (double)k[(size_t)j * nd + i];  // exact in FP64
-      const double fl = std::floor(kap);
-      float f = (float)(kap - fl);
-      // a fraction just below 1 can round up to 1 in FP32.  The taps stay
-      // those of the FP64 cell and the fraction is clamped below 1: moving
-      // to the next cell instead would drop the first tap, whose weight is
-      // the kernel's non-zero edge value just inside its open support.
-      if (f >= 1.0f) f = 0.99999994f;
-      t.f[i] = f;
-      packed |= (uint32_t)iwrap((int64_t)fl - 1, pl->G[i]) << (10 * i);
-    }
-    t.base = packed;
-    taps[j] = t;
-  }
-  // bin samples by the spread tiles their taps touch
+  const int64_t M = tr->M;
+  const std::vector<KTap>& taps = tr->taps_h;
+  HIP_OK(hipStreamSynchronize(pl->stream));
+  pl->generation++;
+  for (void** q : {(void**)&tr->order, (void**)&tr->colmask, (void**)&tr->taps_v, (void**)&tr->vis_off,
+                   (void**)&tr->vis})
+    traj_free(pl, *q);
   int ntiles = 1;
   for (int i = 0; i < nd; ++i) ntiles *= pl->ktile.nt[i];
   std::vector<int> cnt(ntiles + 1, 0);
@@ -1409,14 +1441,10 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
   std::vector<int> pos(cnt.begin(), cnt.end() - 1);
   std::vector<int> order(std::max(1, cnt[ntiles]));
   for (int64_t j = 0; j < M; ++j) visit(j, [&](int t) { order[pos[t]++] = (int)j; });
-  const bool masked = traj_masked(pl);
   tr->ntouched = 0;
   for (int t = 0; t < ntiles; ++t)
     if (cnt[t + 1] > cnt[t]) tr->ntouched++;
-  tr->tile_first = cnt;
-  build_units(pl, tr);
-  tr->M = M;
-  if (masked) {
+  if (traj_masked(pl)) {
     const int ncols = nd == 3 ? pl->ktile.nt[1] * pl->ktile.nt[2] : pl->ktile.nt[1];
     std::vector<uint64_t> cm(ncols, 0ull);
     for (int t = 0; t < ntiles; ++t) {
@@ -1427,9 +1455,8 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
     tr->colmask = (uint64_t*)dmalloc(pl, sizeof(uint64_t) * ncols);
     HIP_OK(hipMemcpy(tr->colmask, cm.data(), sizeof(uint64_t) * ncols, hipMemcpyHostToDevice));
   }
-  tr->taps = (KTap*)dmalloc(pl, sizeof(KTap) * taps.size());
   tr->order = (int*)dmalloc(pl, sizeof(int) * order.size());
-  HIP_OK(hipMemcpy(tr->taps, taps.data(), sizeof(KTap) * taps.size(), hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(tr->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
   {  // visit-ordered taps and, per sample, the list of its visits
     const int64_t nvis = cnt[ntiles];
     std::vector<KTap> tv(std::max<int64_t>(1, nvis));
@@ -1449,7 +1476,44 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
     HIP_OK(hipMemcpy(tr->vis_off, voff.data(), sizeof(int) * voff.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(tr->vis, vlist.data(), sizeof(int) * vlist.size(), hipMemcpyHostToDevice));
   }
-  HIP_OK(hipMemcpy(tr->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
+  tr->tile_first = cnt;
+  for (int i = 0; i < 3; ++i) tr->ts[i] = pl->ktile.TS[i];
+  build_units(pl, tr);
+}
+
+static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_traj* tr) {
+  const int nd = pl->ndim;
+  std::vector<float> k((size_t)M * nd);
+  HIP_OK(hipMemcpy(k.data(), k_dev, sizeof(float) * k.size(), hipMemcpyDeviceToHost));
+  for (float v : k) {
+    if (!std::isfinite(v)) return fail(ISG_ERR_NOT_FINITE, "trajectory holds NaN or Inf");
+    if (std::fabs(v) > 1.0e6f) return fail(ISG_ERR_INVALID_ARG, "trajectory magnitude exceeds 1e6 cycles/voxel");
+  }
+  std::vector<KTap>& taps = tr->taps_h;
+  taps.resize(M);
+  for (int64_t j = 0; j < M; ++j) {
+    KTap t;
+    t.f[0] = t.f[1] = t.f[2] = 0.f;
+    uint32_t packed = 0;
+    for (int i = 0; i < nd; ++i) {
+      const double kap = (double)pl->G[i] * (double)k[(size_t)j * nd + i];  // exact in FP64
+      const double fl = std::floor(kap);
+      float f = (float)(kap - fl);
+      // a fraction just below 1 can round up to 1 in FP32.  The taps stay
+      // those of the FP64 cell and the fraction is clamped below 1: moving
+      // to the next cell instead would drop the first tap, whose weight is
+      // the kernel's non-zero edge value just inside its open support.
+      if (f >= 1.0f) f = 0.99999994f;
+      t.f[i] = f;
+      packed |= (uint32_t)iwrap((int64_t)fl - 1, pl->G[i]) << (10 * i);
+    }
+    t.base = packed;
+    taps[j] = t;
+  }
+  tr->M = M;
+  tr->taps = (KTap*)dmalloc(pl, sizeof(KTap) * taps.size());
+  HIP_OK(hipMemcpy(tr->taps, taps.data(), sizeof(KTap) * taps.size(), hipMemcpyHostToDevice));
+  bin_traj(pl, tr);
   return ISG_OK;
 }
 
@@ -1474,6 +1538,10 @@ static isg_status check_phases(const isg_plan* pl, int P, const isg_motion* cons
   for (int p = 0; p < P; ++p) {
     if (!d[p] || !k[p]) return fail(ISG_ERR_INVALID_ARG, "NULL motion or trajectory handle");
     if (d[p]->plan != pl || k[p]->plan != pl) return fail(ISG_ERR_INVALID_ARG, "handle belongs to another plan");
+    for (int i = 0; i < 3; ++i)
+      if (k[p]->ts[i] != pl->ktile.TS[i])
+        return fail(ISG_ERR_STATE, "trajectory was prepared for another k-space tile shape: re-create it or run "
+                                   "isg_plan_tune with it");
   }
   return ISG_OK;
 }
@@ -1581,59 +1649,77 @@ static isg_status tune(isg_plan* pl, int P, const float2* x, const isg_motion* c
   float2* out = (float2*)pl->tune_out.p;
   const isg_traj* const* kc = (const isg_traj* const*)k;
   struct Cand {
-    int chunk, batch, graph;
+    int t1, chunk, batch, graph;
     double ms;
   };
   std::vector<Cand> tried;
-  auto apply = [&](int chunk, int batch, int graph) {
+  auto apply = [&](int t1, int chunk, int batch, int graph) {
+    const bool retile = t1 != pl->opt_ktile_t1;
+    if (retile) {
+      HIP_OK(hipStreamSynchronize(pl->stream));
+      set_ktile(pl, t1);
+    }
     pl->opt_spread_chunk = chunk;
     pl->opt_phase_batch = batch;
     pl->opt_graph = graph;
     pl->generation++;
-    for (int p = 0; p < P; ++p)
-      if (k[p]->chunk != chunk) build_units(pl, k[p]);
+    for (int p = 0; p < P; ++p) {
+      if (retile || k[p]->ts[1] != pl->ktile.TS[1])
+        bin_traj(pl, k[p]);
+      else if (k[p]->chunk != chunk)
+        build_units(pl, k[p]);
+    }
   };
-  auto measure = [&](int chunk, int batch, int graph) -> double {
-    apply(chunk, batch, graph);
+  auto measure = [&](int t1, int chunk, int batch, int graph) -> double {
+    apply(t1, chunk, batch, graph);
     double ms = 1e30;
     try {
       ms = time_normal(pl, P, x, lam, d, S, kc, out, reps);
     } catch (const std::bad_alloc&) {
       ms = 1e30;  // does not fit: skipped
     }
-    tried.push_back(Cand{chunk, batch, graph, ms});
+    tried.push_back(Cand{t1, chunk, batch, graph, ms});
     return ms;
   };
-  // coordinate search: chunk (batch 1, no graph), then batch, then graph
-  int best_chunk = pl->opt_spread_chunk, best_batch = 1, best_graph = 0;
+  // coordinate search: tile extent, chunk (batch 1, no graph), batch, graph
+  int best_t1 = pl->opt_ktile_t1, best_chunk = pl->opt_spread_chunk, best_batch = 1, best_graph = 0;
   double best = 1e30;
-  for (int c : {256, 512, 1024, 2048}) {
-    const double ms = measure(c, 1, 0);
+  const std::vector<int> t1s = pl->ndim == 3 ? std::vector<int>{8, 4} : std::vector<int>{16, 8};
+  for (int t1 : t1s) {
+    const double ms = measure(t1, 512, 1, 0);
+    if (ms < best) {
+      best = ms;
+      best_t1 = t1;
+    }
+  }
+  for (int c : {256, 1024, 2048}) {
+    const double ms = measure(best_t1, c, 1, 0);
     if (ms < best) {
       best = ms;
       best_chunk = c;
     }
   }
+  if (best_chunk != 256 && best_chunk != 1024 && best_chunk != 2048) best_chunk = 512;
   std::vector<int> batches;
   for (int b : {2, 3, 4, 6, 8, 16})
     if (b <= std::min(P, kMaxPhasesPerLaunch)) batches.push_back(b);
   if (P > 1 && P <= kMaxPhasesPerLaunch && std::find(batches.begin(), batches.end(), P) == batches.end())
     batches.push_back(P);
   for (int b : batches) {
-    const double ms = measure(best_chunk, b, 0);
+    const double ms = measure(best_t1, best_chunk, b, 0);
     if (ms < best) {
       best = ms;
       best_batch = b;
     }
   }
   if (pl->stream != nullptr) {
-    const double ms = measure(best_chunk, best_batch, 1);
+    const double ms = measure(best_t1, best_chunk, best_batch, 1);
     if (ms < best) {
       best = ms;
       best_graph = 1;
     }
   }
-  apply(best_chunk, best_batch, best_graph);
+  apply(best_t1, best_chunk, best_batch, best_graph);
   drop_normal_graph(pl);
   HIP_OK(hipStreamSynchronize(pl->stream));
   if (report && len > 0) {
@@ -1642,15 +1728,16 @@ static isg_status tune(isg_plan* pl, int P, const float2* x, const isg_motion* c
     for (size_t i = 0; i < tried.size(); ++i) {
       const Cand& c = tried[i];
       if (c.ms >= 1e29)
-        snprintf(buf, sizeof(buf), "%s{\"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": null}", i ? ", " : "",
-                 c.chunk, c.batch, c.graph);
+        snprintf(buf, sizeof(buf), "%s{\"ktile_t1\": %d, \"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": null}",
+                 i ? ", " : "", c.t1, c.chunk, c.batch, c.graph);
       else
-        snprintf(buf, sizeof(buf), "%s{\"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": %.4f}", i ? ", " : "",
-                 c.chunk, c.batch, c.graph, c.ms);
+        snprintf(buf, sizeof(buf), "%s{\"ktile_t1\": %d, \"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": %.4f}",
+                 i ? ", " : "", c.t1, c.chunk, c.batch, c.graph, c.ms);
       js += buf;
     }
-    snprintf(buf, sizeof(buf), "], \"chosen\": {\"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": %.4f}}",
-             best_chunk, best_batch, best_graph, best);
+    snprintf(buf, sizeof(buf),
+             "], \"chosen\": {\"ktile_t1\": %d, \"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": %.4f}}",
+             best_t1, best_chunk, best_batch, best_graph, best);
     js += buf;
     const size_t n = std::min<size_t>(js.size(), (size_t)len - 1);
     memcpy(report, js.data(), n);
@@ -1755,33 +1842,7 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
     while (P % 16 != 4) ++P;
     pl->wtile.P = P;
   }
-  if (pl->ndim == 3) {
-    const int t0 = pl->C > 16 ? 4 : 8;
-    const int ts[3] = {t0, 8, 8};
-    for (int i = 0; i < 3; ++i) pl->ktile.TS[i] = std::min(ts[i], pl->G[i]);
-  } else {
-    for (int i = 0; i < 2; ++i) pl->ktile.TS[i] = std::min(16, pl->G[i]);
-  }
-  pl->ktile.vol = 1;
-  for (int i = 0; i < pl->ndim; ++i) {
-    pl->ktile.nt[i] = (pl->G[i] + pl->ktile.TS[i] - 1) / pl->ktile.TS[i];
-    pl->ktile.vol *= pl->ktile.TS[i];
-  }
-  // dense planes of complex values; plane size = 4 (mod 16) puts the four
-  // coils of a spread wave on distinct banks
-  if (pl->ndim == 3) {
-    pl->ktile.S1 = pl->ktile.TS[2];
-    pl->ktile.S0 = pl->ktile.TS[1] * pl->ktile.TS[2];
-  } else {
-    pl->ktile.S1 = 1;
-    pl->ktile.S0 = pl->ktile.TS[1];
-  }
-  {
-    int P = pl->ktile.TS[0] * pl->ktile.S0;
-    while (P % 16 != 4) ++P;
-    pl->ktile.P = P;
-  }
-  pl->ktile.rowdiv = make_fastdiv((uint32_t)(pl->ktile.TS[pl->ndim - 1] * pl->C));
+  set_ktile(pl, pl->ndim == 3 ? 8 : 16);
   isg_status st = guarded(pl, [&]() -> isg_status {
     HIP_OK(hipGetDevice(&pl->device));
     HIP_OK(hipDeviceGetAttribute(&pl->ncu, hipDeviceAttributeMultiprocessorCount, pl->device));
@@ -2062,6 +2123,17 @@ isg_status isg_plan_set_option(isg_plan* pl, isg_option option, int64_t value) {
       if (value != 0 && value != 1) return fail(ISG_ERR_INVALID_ARG, "graph option must be 0 or 1");
       pl->opt_graph = (int)value;
       break;
+    case ISG_OPT_KTILE_T1:
+      if (value != 4 && value != 8 && value != 16) return fail(ISG_ERR_INVALID_ARG, "k-space tile extent must be 4, 8 or 16");
+      {
+        const isg_status s2 = guarded(pl, [&]() -> isg_status {
+          HIP_OK(hipStreamSynchronize(pl->stream));
+          set_ktile(pl, (int)value);
+          return ISG_OK;
+        });
+        if (s2 != ISG_OK) return s2;
+      }
+      break;
     default:
       return fail(ISG_ERR_INVALID_ARG, "unknown option");
   }
@@ -2075,6 +2147,7 @@ isg_status isg_plan_get_option(const isg_plan* pl, isg_option option, int64_t* v
     case ISG_OPT_SPREAD_CHUNK: *value = pl->opt_spread_chunk; break;
     case ISG_OPT_PHASE_BATCH: *value = pl->opt_phase_batch; break;
     case ISG_OPT_GRAPH: *value = pl->opt_graph; break;
+    case ISG_OPT_KTILE_T1: *value = pl->opt_ktile_t1; break;
     default: return fail(ISG_ERR_INVALID_ARG, "unknown option");
   }
   return ISG_OK;

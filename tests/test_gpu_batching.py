@@ -7,9 +7,9 @@ floating-point summation order:
   does, so results are compared bit for bit;
 * graph replays re-run the captured kernels, so they are compared bit for
   bit with the eager call, replay after replay, with eager work between;
-* a different spread chunk changes only the order in which split tiles are
-  summed: 1e-6 relative (a few FP32 roundings), and the result is still held
-  to the oracle's 1e-5.
+* a different spread chunk or k-space tile extent changes only the order in
+  which contributions are summed: 1e-6 relative (a few FP32 roundings), and
+  the result is still held to the oracle's 1e-5.
 """
 import numpy as np
 import pytest
@@ -139,3 +139,31 @@ def test_tune_keeps_results(setup):
         after2 = plan.normal(x, 0.2, mots, S, trs).cpu().numpy()
     assert rel(after, before) < 1e-6
     assert np.array_equal(after, after2)
+
+
+def test_ktile_extent(setup):
+    """narrower k-space spread tiles: same operator (summation order only),
+    and trajectories binned for another tile shape are refused.  32 x 40 x 48
+    takes the register-FFT path whose axis-0 passes skip untouched tiles."""
+    import torch
+    isg = setup[0]
+    w = small_workload(shape=(32, 40, 48), ncoils=6, nphases=2, spokes=(25, 70), cfg=141)
+    inp = make_inputs(w)
+    x = to_dev(inp["x"])
+    res = {}
+    for t1 in (8, 4):
+        say(f"k-space tile extent {t1}")
+        plan = isg.Plan(w.shape, ncoils=w.ncoils, nphases=w.nphases)
+        plan.set_option("ktile_t1", t1)
+        assert plan.get_option("ktile_t1") == t1
+        S = to_dev(inp["S"])
+        mots = [plan.motion(to_dev(d)) for d in inp["d"]]
+        trs = [plan.traj(to_dev(k)) for k in inp["k"]]
+        res[t1] = plan.normal(x, 0.1, mots, S, trs).cpu().numpy()
+        if t1 == 4:
+            plan.set_option("ktile_t1", 8)
+            with pytest.raises(isg.IsgError):
+                plan.normal(x, 0.1, mots, S, trs)
+    assert rel(res[4], res[8]) < 1e-6
+    want = oracle.sense.normal(inp["x"], 0.1, inp["d"], inp["S"], inp["k"])
+    assert rel(res[4], want) < 1e-5
