@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--batch", type=int, default=1, help="phase batch with --no-tune")
     ap.add_argument("--graph", type=int, default=0, help="graph replay (0/1) with --no-tune")
     ap.add_argument("--ktile", type=int, default=8, help="k-space spread tile extent along axis 1 with --no-tune")
+    ap.add_argument("--kblock", type=int, default=3, help="k-space array row blocking (log2, 0 = plain) with --no-tune")
     ap.add_argument("--cg-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="print a per-stage timing table to stderr")
@@ -139,13 +140,13 @@ def main():
             for _ in range(args.warmup):
                 plan.normal(x, lam, mots, S, trs, out=out)
         ms = time_steps(plan, mots, trs, out, args.steps)
-        opts = {k: plan.get_option(k) for k in ("ktile_t1", "spread_chunk", "phase_batch", "graph")}
+        opts = {k: plan.get_option(k) for k in ("kblock", "ktile_t1", "spread_chunk", "phase_batch", "graph")}
         log(f"{storage} {'tuned' if tune else 'plain'}: {ms:.3f} ms/apply, options {opts}")
         return plan, mots, trs, out, ms, opts, report
 
     # ---- headline form ------------------------------------------------------
     # the tile extent first: it decides how trajectories are binned
-    fixed = None if not args.no_tune else {"ktile_t1": args.ktile, "spread_chunk": args.chunk,
+    fixed = None if not args.no_tune else {"kblock": args.kblock, "ktile_t1": args.ktile, "spread_chunk": args.chunk,
                                            "phase_batch": args.batch, "graph": args.graph}
     plan, mots, trs, out, ms_per_step, opts, tune_report = run_form(args.storage, not args.no_tune, fixed)
     value = 1000.0 / ms_per_step
@@ -227,7 +228,8 @@ def main():
     if not args.no_tune:
         head = "tuned"
     else:
-        head = "plain" if (args.ktile, args.chunk, args.batch, args.graph) == (8, 512, 1, 0) else "fixed"
+        head = "plain" if (args.kblock, args.ktile, args.chunk, args.batch, args.graph) == (0, 8, 512, 1, 0) \
+            else "fixed"
     forms = {f"{head}_{args.storage}": {"ms": round(ms_per_step, 4), "options": opts}}
     del plan, mots, trs
     for f in [f.strip() for f in args.forms.split(",") if f.strip()]:
@@ -236,7 +238,8 @@ def main():
         name = f"{'tuned' if tune else 'plain'}_{storage}"
         if name in forms:
             continue
-        p2, m2, t2, o2, ms2, opts2, _ = run_form(storage, tune)
+        plain_opts = {"kblock": 0, "ktile_t1": 8, "spread_chunk": 512, "phase_batch": 1, "graph": 0}
+        p2, m2, t2, o2, ms2, opts2, _ = run_form(storage, tune, None if tune else plain_opts)
         entry = {"ms": round(ms2, 4), "options": opts2}
         if storage != args.storage:  # relative difference from the headline form's output
             diff = torch.linalg.vector_norm(o2 - ref_out) / torch.linalg.vector_norm(ref_out)

@@ -144,12 +144,21 @@ isg_status isg_plan_read_timing(isg_plan* plan, char* buf, int64_t len);
  *                         axis-0 passes skip untouched tiles) at more
  *                         sample visits.  Trajectories prepared for another
  *                         extent fail with ISG_ERR_STATE until re-created or
- *                         passed to isg_plan_tune. */
+ *                         passed to isg_plan_tune.
+ *   ISG_OPT_KBLOCK        layout of the coil-expanded k-space arrays in 3D:
+ *                         b in 1..6 keeps blocks of 2^b consecutive rows of
+ *                         axis 1 together for each index of axis 0 (the
+ *                         axis-0 FFT passes then step 2^b G2 C elements
+ *                         rather than G1 G2 C); 0 is plain row-major.
+ *                         Default 3; plain where 2^b does not divide G1 or
+ *                         a length has no register FFT.  Internal arrays
+ *                         only: no input or output layout changes. */
 typedef enum {
   ISG_OPT_SPREAD_CHUNK = 1,
   ISG_OPT_PHASE_BATCH = 2,
   ISG_OPT_GRAPH = 3,
-  ISG_OPT_KTILE_T1 = 4
+  ISG_OPT_KTILE_T1 = 4,
+  ISG_OPT_KBLOCK = 5
 } isg_option;
 
 /* Set / read an option.  INVALID_ARG for an unknown option or a value out of
@@ -158,13 +167,15 @@ isg_status isg_plan_set_option(isg_plan* plan, isg_option option, int64_t value)
 isg_status isg_plan_get_option(const isg_plan* plan, isg_option option, int64_t* value);
 
 /* Autotuner: times the normal operator sum_p A_p^H A_p x + lambda x on the
- * given inputs for candidate k-space tile extents, spread chunk sizes, phase
+ * given inputs for candidate k-space array blockings, k-space tile extents,
+ * spread chunk sizes, phase
  * batch sizes and graph replay (a coordinate search, each candidate the best
  * of `reps` timed applications after one warm-up), keeps the fastest setting
  * in the plan and re-prepares the given trajectories for it (others prepared
  * on this plan must be re-created if the tile extent changed).  Candidates that do not
  * fit in device memory are skipped.  report (host, may be NULL) receives a
- * JSON object {"candidates": [{"ktile_t1", "chunk", "batch", "graph", "ms"}...],
+ * JSON object {"candidates": [{"kblock", "ktile_t1", "chunk", "batch", "graph",
+ * "ms"}...],
  * "chosen": {...}} (NUL-terminated, truncated to len bytes).  Synchronizes
  * the stream. */
 isg_status isg_plan_tune(isg_plan* plan, int nphases, const void* x, const isg_motion* const* d,

@@ -20,6 +20,28 @@ struct FastDiv {
   __device__ __forceinline__ uint32_t mod(uint32_t n) const { return n - div(n) * d; }
 };
 
+// Row-blocked layout of a coil-expanded array [R][G1][G2][C] (2D: [R][G1][C],
+// with G2 C read as C): blocks of T = 2^tlog consecutive i1 keep their R rows
+// together, so consecutive i0 are T G2 C elements apart instead of
+// G1 G2 C.  Element (i0, i1, rest), rest = i2 C + c, sits at
+//   (i1 >> tlog) bs + i0 rs + (i1 & (T - 1)) g2c + rest.
+// tlog = 30 is the plain row-major layout (rs = G1 G2 C).
+struct Blk {
+  int tlog;
+  int64_t rs;   // i0 stride
+  int64_t bs;   // stride of a block of T values of i1
+  int64_t g2c;  // i1 stride inside a block (G2 C)
+  FastDiv g2cdiv;
+  __device__ __forceinline__ int64_t off(int64_t i0, int i1, int64_t rest) const {
+    return (int64_t)(i1 >> tlog) * bs + i0 * rs + (int64_t)(i1 & ((1 << tlog) - 1)) * g2c + rest;
+  }
+  // offset of column b = i1 G2 C + rest at i0 = 0 (b < 2^31)
+  __device__ __forceinline__ int64_t col(int64_t b) const {
+    const uint32_t i1 = g2cdiv.div((uint32_t)b);
+    return off(0, (int)i1, b - (int64_t)i1 * g2c);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // complex64 helpers
 // ---------------------------------------------------------------------------

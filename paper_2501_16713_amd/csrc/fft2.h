@@ -191,19 +191,22 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
   const int64_t b0 = (tile - ta * g.tiles_b) * g.nb;
   if (a0 >= g.A) return;
   const int nl = g.na * g.nb;
-  __syncthreads();
 
-  // ---- step 1 ----
-  if (tid < nl * L2) {
-    int bl, n2, al;
+  // ---- step 1: loads and the L1-point DFTs overlap the twiddle copy ----
+  const bool act1 = tid < nl * L2;
+  int bl = 0, n2 = 0, al = 0;
+  float2 v[L1];
+  if (act1) {
     decode<MAP1>(tid, g.nb, L2, bl, n2, al);
     const int64_t a = a0 + al, b = b0 + bl;
     const bool valid = a < g.A && b < g.B;
-    float2 v[L1];
     auto line = ld.setup(a, b, valid);
 #pragma unroll
     for (int n1 = 0; n1 < L1; ++n1) v[n1] = ld.template get<L>(line, L2 * n1 + n2, valid);
     reg_dft<L1, S>(v);
+  }
+  __syncthreads();  // twiddle table in LDS
+  if (act1) {
     float2* dst = lines + (al * g.nb + bl) * g.LS;
 #pragma unroll
     for (int k1 = 0; k1 < L1; ++k1) {
@@ -264,6 +267,8 @@ template <int S>
 struct Ld2Strided {
   const typename Elem<S>::T* p;
   int64_t sa, sj;
+  int tlog;     // stored position j sits at (j >> tlog) bs + (j & (2^tlog - 1)) sj
+  int64_t bs;   // (tlog = 30: j sj, the plain stride)
   int map;
   const float2* tw;
   struct Line {
@@ -274,7 +279,26 @@ struct Ld2Strided {
   __device__ float2 get(const Line& ln, int pos, bool valid) const {
     const int j = pad_src<L>(map, pos);
     if (!valid || j < 0) return make_float2(0.f, 0.f);
-    return Elem<S>::load(ln.base + (int64_t)j * sj);
+    return Elem<S>::load(ln.base + (int64_t)(j >> tlog) * bs + (int64_t)(j & ((1 << tlog) - 1)) * sj);
+  }
+};
+
+// load along axis 0 of a row-blocked array: column b, stored rows j
+template <int S>
+struct Ld2Rows {
+  const typename Elem<S>::T* p;
+  Blk blk;
+  int map;
+  const float2* tw;
+  struct Line {
+    const typename Elem<S>::T* base;
+  };
+  __device__ Line setup(int64_t, int64_t b, bool valid) const { return Line{valid ? p + blk.col(b) : p}; }
+  template <int L>
+  __device__ float2 get(const Line& ln, int pos, bool valid) const {
+    const int j = pad_src<L>(map, pos);
+    if (!valid || j < 0) return make_float2(0.f, 0.f);
+    return Elem<S>::load(ln.base + (int64_t)j * blk.rs);
   }
 };
 
@@ -283,6 +307,8 @@ struct St2Strided {
   static constexpr bool kEpilogue = false;
   typename Elem<S>::T* p;
   int64_t sa, sj;
+  int tlog;     // as in Ld2Strided
+  int64_t bs;
   int map;      // dense, or crop to L/2 values (centred or spectral)
   float scale;  // applied to half-precision stores only
   struct Line {
@@ -292,7 +318,28 @@ struct St2Strided {
   template <int L>
   __device__ void put(const Line& ln, int pos, float2 v, bool valid) const {
     const int j = pad_src<L>(map, pos);
-    if (valid && j >= 0) Elem<S>::store(ln.base + (int64_t)j * sj, store_scaled<S>(v, scale));
+    if (valid && j >= 0)
+      Elem<S>::store(ln.base + (int64_t)(j >> tlog) * bs + (int64_t)(j & ((1 << tlog) - 1)) * sj,
+                     store_scaled<S>(v, scale));
+  }
+};
+
+// store along axis 0 of a row-blocked array (crop maps as St2Strided)
+template <int S>
+struct St2Rows {
+  static constexpr bool kEpilogue = false;
+  typename Elem<S>::T* p;
+  Blk blk;
+  int map;
+  float scale;  // applied to half-precision stores only
+  struct Line {
+    typename Elem<S>::T* base;
+  };
+  __device__ Line setup(int64_t, int64_t b, bool valid) const { return Line{valid ? p + blk.col(b) : p}; }
+  template <int L>
+  __device__ void put(const Line& ln, int pos, float2 v, bool valid) const {
+    const int j = pad_src<L>(map, pos);
+    if (valid && j >= 0) Elem<S>::store(ln.base + (int64_t)j * blk.rs, store_scaled<S>(v, scale));
   }
 };
 
@@ -322,7 +369,7 @@ struct TileMask {
 template <int S>
 struct Ld2Masked {
   const typename Elem<S>::T* p;
-  int64_t sj;
+  Blk blk;  // the grid's row-blocked layout
   TileMask tm;
   const float2* tw;
   struct Line {
@@ -330,12 +377,12 @@ struct Ld2Masked {
     uint64_t mask;
   };
   __device__ Line setup(int64_t a, int64_t b, bool valid) const {
-    return Line{p + b, valid ? tm.column(b) : 0ull};
+    return Line{valid ? p + blk.col(b) : p, valid ? tm.column(b) : 0ull};
   }
   template <int L>
   __device__ float2 get(const Line& ln, int pos, bool valid) const {
     if (!valid || !((ln.mask >> (pos >> tm.ts0_log2)) & 1ull)) return make_float2(0.f, 0.f);
-    return Elem<S>::load(ln.base + (int64_t)pos * sj);
+    return Elem<S>::load(ln.base + (int64_t)pos * blk.rs);
   }
 };
 
@@ -344,18 +391,20 @@ template <int S>
 struct St2Masked {
   static constexpr bool kEpilogue = false;
   typename Elem<S>::T* p;
-  int64_t sj;
+  Blk blk;  // the grid's row-blocked layout
   TileMask tm;
   float scale;  // applied to half-precision stores only
   struct Line {
     typename Elem<S>::T* base;
     uint64_t mask;
   };
-  __device__ Line setup(int64_t a, int64_t b, bool valid) const { return Line{p + b, valid ? tm.column(b) : 0ull}; }
+  __device__ Line setup(int64_t a, int64_t b, bool valid) const {
+    return Line{valid ? p + blk.col(b) : p, valid ? tm.column(b) : 0ull};
+  }
   template <int L>
   __device__ void put(const Line& ln, int pos, float2 v, bool valid) const {
     if (valid && ((ln.mask >> (pos >> tm.ts0_log2)) & 1ull))
-      Elem<S>::store(ln.base + (int64_t)pos * sj, store_scaled<S>(v, scale));
+      Elem<S>::store(ln.base + (int64_t)pos * blk.rs, store_scaled<S>(v, scale));
   }
 };
 

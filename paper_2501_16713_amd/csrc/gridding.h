@@ -438,6 +438,7 @@ struct KBatch {
   float2* yout[kMaxPhasesPerLaunch];       // gather output
   T* grid[kMaxPhasesPerLaunch];
   float2* partial[kMaxPhasesPerLaunch];
+  Blk blk;  // row-blocked layout of every grid of the batch
 };
 
 // the state a block belongs to
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(kGridThreads) void kgather_kernel(KBatch<typename E
 #pragma unroll
       for (int t1 = 0; t1 < 4; ++t1) {
         const float w01 = w[0][t0] * w[1][t1];
-        const typename Elem<S>::T* row = grid + ((int64_t)g[0][t0] * dm.G[1] + g[1][t1]) * dm.G[2] * C + c;
+        const typename Elem<S>::T* row = grid + bt.blk.off(g[0][t0], g[1][t1], c);
         float2 s = make_float2(0.f, 0.f);
 #pragma unroll
         for (int t2 = 0; t2 < 4; ++t2) {
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(kGridThreads) void kgather_kernel(KBatch<typename E
   } else {
 #pragma unroll
     for (int t0 = 0; t0 < 4; ++t0) {
-      const typename Elem<S>::T* row = grid + (int64_t)g[0][t0] * dm.G[1] * C + c;
+      const typename Elem<S>::T* row = grid + (int64_t)g[0][t0] * bt.blk.rs + c;
       float2 s = make_float2(0.f, 0.f);
 #pragma unroll
       for (int t1 = 0; t1 < 4; ++t1) {
@@ -717,11 +718,11 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
       if constexpr (NDIM == 3) {
         const int gl1 = lo[1] + l1;
         ok = ok && gl1 < dm.G[1];
-        gi = ((int64_t)gl0 * dm.G[1] + gl1) * dm.G[2] + gl;
+        gi = bt.blk.off(gl0, gl1, (int64_t)gl * C + cc);
       } else {
-        gi = (int64_t)gl0 * dm.G[1] + gl;
+        gi = bt.blk.off(gl0, gl, cc);
       }
-      if (ok) Elem<S>::store(grid + gi * C + cc, v);
+      if (ok) Elem<S>::store(grid + gi, v);
     }
   }
 }
@@ -760,13 +761,13 @@ __global__ __launch_bounds__(kGridThreads) void kspread_reduce_kernel(KBatch<typ
       t /= kt.TS[i];
     }
     bool ok = true;
-    int64_t gi = 0;
+    int g[3] = {0, 0, 0};
     for (int i = 0; i < NDIM; ++i) {
-      const int g = lo[i] + l[i];
-      ok = ok && g < dm.G[i];
-      gi = gi * dm.G[i] + g;
+      g[i] = lo[i] + l[i];
+      ok = ok && g[i] < dm.G[i];
     }
-    if (ok) Elem<S>::store(grid + gi * C + c, s);
+    const int64_t gi = NDIM == 3 ? bt.blk.off(g[0], g[1], (int64_t)g[2] * C + c) : bt.blk.off(g[0], g[1], c);
+    if (ok) Elem<S>::store(grid + gi, s);
   }
 }
 

@@ -131,6 +131,8 @@ struct isg_plan {
   int opt_phase_batch = 1;     // states per k-space gather / spread launch
   int opt_graph = 0;           // isg_normal replays a captured graph
   int opt_ktile_t1 = 8;        // k-space spread tile extent along axis 1
+  int opt_blk_tlog = 3;        // log2 of the i1 block of the row-blocked k-space arrays
+  Blk blk_grid, blk_k2;        // layouts of the coil-expanded grid and of k2buf
   hipStream_t stream = nullptr;
   int device = 0;
   int ncu = 256;  // compute units of the device
@@ -496,6 +498,8 @@ static Ld2Strided<S> ld2(const isg_plan* pl, const void* p, int64_t sa, int64_t 
   l.p = (const typename Elem<S>::T*)p;
   l.sa = sa;
   l.sj = sj;
+  l.tlog = 30;
+  l.bs = 0;
   l.map = map;
   l.tw = pl->lines.at(L).tw;
   return l;
@@ -507,6 +511,46 @@ static St2Strided<S> st2(void* p, int64_t sa, int64_t sj, int map, float scale =
   s.p = (typename Elem<S>::T*)p;
   s.sa = sa;
   s.sj = sj;
+  s.tlog = 30;
+  s.bs = 0;
+  s.map = map;
+  s.scale = scale;
+  return s;
+}
+
+// lines along axis 1 of a row-blocked array: a = i0, b = i2 C + c, j = i1
+template <int S>
+static Ld2Strided<S> ld2_axis1(const isg_plan* pl, const void* p, const Blk& blk, int map, int L) {
+  Ld2Strided<S> l = ld2<S>(pl, p, blk.rs, blk.g2c, map, L);
+  l.tlog = blk.tlog;
+  l.bs = blk.bs;
+  return l;
+}
+
+template <int S>
+static St2Strided<S> st2_axis1(void* p, const Blk& blk, int map, float scale) {
+  St2Strided<S> s = st2<S>(p, blk.rs, blk.g2c, map, scale);
+  s.tlog = blk.tlog;
+  s.bs = blk.bs;
+  return s;
+}
+
+// lines along axis 0 of a row-blocked array: b = column, j = i0
+template <int S>
+static Ld2Rows<S> ld2_rows(const isg_plan* pl, const void* p, const Blk& blk, int map, int L) {
+  Ld2Rows<S> l;
+  l.p = (const typename Elem<S>::T*)p;
+  l.blk = blk;
+  l.map = map;
+  l.tw = pl->lines.at(L).tw;
+  return l;
+}
+
+template <int S>
+static St2Rows<S> st2_rows(void* p, const Blk& blk, int map, float scale) {
+  St2Rows<S> s;
+  s.p = (typename Elem<S>::T*)p;
+  s.blk = blk;
   s.map = map;
   s.scale = scale;
   return s;
@@ -786,20 +830,20 @@ static TileMask tile_mask(const isg_plan* pl, const isg_traj* tr) {
 }
 
 template <int S>
-static St2Masked<S> st2_masked(void* p, int64_t sj, const TileMask& tm, float scale) {
+static St2Masked<S> st2_masked(void* p, const Blk& blk, const TileMask& tm, float scale) {
   St2Masked<S> st;
   st.p = (typename Elem<S>::T*)p;
-  st.sj = sj;
+  st.blk = blk;
   st.tm = tm;
   st.scale = scale;
   return st;
 }
 
 template <int S>
-static Ld2Masked<S> ld2_masked(isg_plan* pl, const void* p, int64_t sj, const TileMask& tm, int L) {
+static Ld2Masked<S> ld2_masked(isg_plan* pl, const void* p, const Blk& blk, const TileMask& tm, int L) {
   Ld2Masked<S> ld;
   ld.p = (const typename Elem<S>::T*)p;
-  ld.sj = sj;
+  ld.blk = blk;
   ld.tm = tm;
   ld.tw = line_plan(pl, L).tw;
   return ld;
@@ -818,22 +862,20 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
     run_fft2<-1, kJFast, kBFast>(pl, "fft_coil_fwd_last", G2, ld2_expand(pl, m, Sm, n2, n1, G2),
                                  st2<S>(pl->k1buf, (int64_t)G2 * C, C, kDense),
                                  make_tile2((int64_t)n0 * n1, C, G2, C));
-    // centred pad, F along axis 1
+    // centred pad, F along axis 1 (into the row-blocked k2buf)
     run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax1", G1,
                                  ld2<S>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
-                                 st2<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, kDense,
-                                        axis_store_scale(pl, 1)),
+                                 st2_axis1<S>(pl->k2buf, pl->blk_k2, kDense, axis_store_scale(pl, 1)),
                                  xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
     // centred pad, F along axis 0
-    run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0,
-                                 ld2<S>(pl, pl->k2buf, 0, (int64_t)G1 * G2 * C, kCentred, G0),
-                                 st2_masked<S>(grid, (int64_t)G1 * G2 * C, tile_mask(pl, tr), axis_store_scale(pl, 0)),
+    run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0, ld2_rows<S>(pl, pl->k2buf, pl->blk_k2, kCentred, G0),
+                                 st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), axis_store_scale(pl, 0)),
                                  make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
     run_fft2<-1, kJFast, kBFast>(pl, "fft_coil_fwd_last", G1, ld2_expand(pl, m, Sm, n1, 0, G1),
                                  st2<S>(pl->k1buf, (int64_t)G1 * C, C, kDense), make_tile2(n0, C, G1, C));
     run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0, ld2<S>(pl, pl->k1buf, 0, (int64_t)G1 * C, kCentred, G0),
-                                 st2_masked<S>(grid, (int64_t)G1 * C, tile_mask(pl, tr), axis_store_scale(pl, 0)),
+                                 st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), axis_store_scale(pl, 0)),
                                  make_tile2(1, (int64_t)G1 * C, G0, 0));
   } else if (pl->ndim == 3) {
     {  // S_c m / c(x/G) |N|^{-1/2}, centred pad, F along axis 2
@@ -903,18 +945,18 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
   const float scale = image_end_scale(pl);
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0,
-                                 ld2_masked<S>(pl, grid, (int64_t)G1 * G2 * C, tile_mask(pl, tr), G0),
-                                 st2<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, kCentred, axis_store_scale(pl, 0)),
+                                 ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
+                                 st2_rows<S>(pl->k2buf, pl->blk_k2, kCentred, axis_store_scale(pl, 0)),
                                  make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax1", G1,
-                                 ld2<S>(pl, pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, kDense, G1),
+                                 ld2_axis1<S>(pl, pl->k2buf, pl->blk_k2, kDense, G1),
                                  st2<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred,
                                         axis_store_scale(pl, 1)),
                                  xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G2, ld2<S>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
                                  st2_reduce(pl, w, Sm, n2, n1, G2), make_tile2((int64_t)n0 * n1, C, G2, C));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
-    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2_masked<S>(pl, grid, (int64_t)G1 * C, tile_mask(pl, tr), G0),
+    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
                                  st2<S>(pl->k1buf, 0, (int64_t)G1 * C, kCentred, axis_store_scale(pl, 0)),
                                  make_tile2(1, (int64_t)G1 * C, G0, 0));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G1, ld2<S>(pl, pl->k1buf, (int64_t)G1 * C, C, kDense, G1),
@@ -1010,6 +1052,7 @@ static void kgather_t(isg_plan* pl, const KJob* jobs, int n, bool to_visits) {
       blocks += (waves + kGridThreads / 64 - 1) / (kGridThreads / 64);
     }
     bt.first[bt.n] = (int)blocks;
+    bt.blk = pl->blk_grid;
     Tick tick(pl, "kgather");
     if (pl->ndim == 3)
       hipLaunchKernelGGL((kgather_kernel<3, S>), dim3((unsigned)blocks), dim3(kGridThreads), 0, pl->stream, bt,
@@ -1056,6 +1099,7 @@ static void kspread_nd(isg_plan* pl, const KJob* jobs, int n) {
       slot0 += jb.tr->nslots;
     }
     bt.first[nb] = (int)units;
+    bt.blk = pl->blk_grid;
     {
       Tick tick(pl, "kspread");
       hipLaunchKernelGGL(k, dim3((unsigned)units), dim3(kthreads), lds, pl->stream, bt, pl->C, pl->dims, pl->ktile,
@@ -1340,6 +1384,35 @@ static void set_ktile(isg_plan* pl, int t1) {
   pl->ktile.P = P;
   pl->ktile.rowdiv = make_fastdiv((uint32_t)(pl->ktile.TS[pl->ndim - 1] * pl->C));
   pl->opt_ktile_t1 = t1;
+}
+
+// Layouts of the coil-expanded grid [G0][G1][G2][C] and of k2buf
+// [n0][G1][G2][C]: row-blocked in blocks of 2^opt_blk_tlog values of i1 on the
+// 3D register-FFT path (the axis-0 passes then step T G2 C elements instead
+// of G1 G2 C and touch far fewer translation pages), plain row-major
+// elsewhere or when the block does not divide G1.
+static void set_layouts(isg_plan* pl) {
+  auto make = [&](int64_t rows, int tlog, int64_t g2c) {
+    Blk b;
+    b.g2c = g2c;
+    b.g2cdiv = make_fastdiv((uint32_t)g2c);
+    if (tlog < 30) {
+      b.tlog = tlog;
+      b.rs = ((int64_t)1 << tlog) * g2c;
+      b.bs = rows * b.rs;
+    } else {
+      b.tlog = 30;
+      b.rs = (int64_t)pl->G[1] * g2c;
+      b.bs = 0;
+    }
+    return b;
+  };
+  const bool fast3 = pl->ndim == 3 && fft2_supported(pl->G[0]) && fft2_supported(pl->G[1]) && fft2_supported(pl->G[2]);
+  int tlog = 30;
+  if (fast3 && pl->opt_blk_tlog < 30 && pl->G[1] % (1 << pl->opt_blk_tlog) == 0) tlog = pl->opt_blk_tlog;
+  const int64_t g2c = (int64_t)(pl->ndim == 3 ? pl->G[2] : 1) * pl->C;
+  pl->blk_grid = make(pl->G[0], tlog, g2c);
+  pl->blk_k2 = make(pl->n[0], tlog, g2c);
 }
 
 static bool traj_masked(const isg_plan* pl) {
@@ -1649,16 +1722,16 @@ static isg_status tune(isg_plan* pl, int P, const float2* x, const isg_motion* c
   float2* out = (float2*)pl->tune_out.p;
   const isg_traj* const* kc = (const isg_traj* const*)k;
   struct Cand {
-    int t1, chunk, batch, graph;
+    int kb, t1, chunk, batch, graph;
     double ms;
   };
   std::vector<Cand> tried;
-  auto apply = [&](int t1, int chunk, int batch, int graph) {
+  auto apply = [&](int kb, int t1, int chunk, int batch, int graph) {
     const bool retile = t1 != pl->opt_ktile_t1;
-    if (retile) {
-      HIP_OK(hipStreamSynchronize(pl->stream));
-      set_ktile(pl, t1);
-    }
+    HIP_OK(hipStreamSynchronize(pl->stream));
+    if (retile) set_ktile(pl, t1);
+    pl->opt_blk_tlog = kb == 0 ? 30 : kb;
+    set_layouts(pl);
     pl->opt_spread_chunk = chunk;
     pl->opt_phase_batch = batch;
     pl->opt_graph = graph;
@@ -1670,56 +1743,65 @@ static isg_status tune(isg_plan* pl, int P, const float2* x, const isg_motion* c
         build_units(pl, k[p]);
     }
   };
-  auto measure = [&](int t1, int chunk, int batch, int graph) -> double {
-    apply(t1, chunk, batch, graph);
+  auto measure = [&](int kb, int t1, int chunk, int batch, int graph) -> double {
+    apply(kb, t1, chunk, batch, graph);
     double ms = 1e30;
     try {
       ms = time_normal(pl, P, x, lam, d, S, kc, out, reps);
     } catch (const std::bad_alloc&) {
       ms = 1e30;  // does not fit: skipped
     }
-    tried.push_back(Cand{t1, chunk, batch, graph, ms});
+    tried.push_back(Cand{kb, t1, chunk, batch, graph, ms});
     return ms;
   };
-  // coordinate search: tile extent, chunk (batch 1, no graph), batch, graph
-  int best_t1 = pl->opt_ktile_t1, best_chunk = pl->opt_spread_chunk, best_batch = 1, best_graph = 0;
-  double best = 1e30;
+  // coordinate search: k-space array blocking, tile extent, chunk (batch 1,
+  // no graph), batch, graph
   const std::vector<int> t1s = pl->ndim == 3 ? std::vector<int>{8, 4} : std::vector<int>{16, 8};
+  int best_kb = 0, best_t1 = t1s[0], best_chunk = 512, best_batch = 1, best_graph = 0;
+  double best = 1e30;
+  const std::vector<int> kbs = pl->ndim == 3 ? std::vector<int>{3, 2, 4, 0} : std::vector<int>{0};
+  for (int kb : kbs) {
+    const double ms = measure(kb, t1s[0], 512, 1, 0);
+    if (ms < best) {
+      best = ms;
+      best_kb = kb;
+    }
+  }
   for (int t1 : t1s) {
-    const double ms = measure(t1, 512, 1, 0);
+    if (t1 == t1s[0]) continue;
+    const double ms = measure(best_kb, t1, 512, 1, 0);
     if (ms < best) {
       best = ms;
       best_t1 = t1;
     }
   }
   for (int c : {256, 1024, 2048}) {
-    const double ms = measure(best_t1, c, 1, 0);
+    const double ms = measure(best_kb, best_t1, c, 1, 0);
     if (ms < best) {
       best = ms;
       best_chunk = c;
     }
   }
-  if (best_chunk != 256 && best_chunk != 1024 && best_chunk != 2048) best_chunk = 512;
   std::vector<int> batches;
   for (int b : {2, 3, 4, 6, 8, 16})
     if (b <= std::min(P, kMaxPhasesPerLaunch)) batches.push_back(b);
   if (P > 1 && P <= kMaxPhasesPerLaunch && std::find(batches.begin(), batches.end(), P) == batches.end())
     batches.push_back(P);
   for (int b : batches) {
-    const double ms = measure(best_t1, best_chunk, b, 0);
+    const double ms = measure(best_kb, best_t1, best_chunk, b, 0);
     if (ms < best) {
       best = ms;
       best_batch = b;
     }
   }
   if (pl->stream != nullptr) {
-    const double ms = measure(best_t1, best_chunk, best_batch, 1);
+    const double ms = measure(best_kb, best_t1, best_chunk, best_batch, 1);
     if (ms < best) {
       best = ms;
       best_graph = 1;
     }
   }
-  apply(best_t1, best_chunk, best_batch, best_graph);
+  apply(best_kb, best_t1, best_chunk, best_batch, best_graph);
   drop_normal_graph(pl);
   HIP_OK(hipStreamSynchronize(pl->stream));
   if (report && len > 0) {
@@ -1728,16 +1810,19 @@ static isg_status tune(isg_plan* pl, int P, const float2* x, const isg_motion* c
     for (size_t i = 0; i < tried.size(); ++i) {
       const Cand& c = tried[i];
       if (c.ms >= 1e29)
-        snprintf(buf, sizeof(buf), "%s{\"ktile_t1\": %d, \"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": null}",
-                 i ? ", " : "", c.t1, c.chunk, c.batch, c.graph);
+        snprintf(buf, sizeof(buf),
+                 "%s{\"kblock\": %d, \"ktile_t1\": %d, \"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": null}",
+                 i ? ", " : "", c.kb, c.t1, c.chunk, c.batch, c.graph);
       else
-        snprintf(buf, sizeof(buf), "%s{\"ktile_t1\": %d, \"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": %.4f}",
-                 i ? ", " : "", c.t1, c.chunk, c.batch, c.graph, c.ms);
+        snprintf(buf, sizeof(buf),
+                 "%s{\"kblock\": %d, \"ktile_t1\": %d, \"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": %.4f}",
+                 i ? ", " : "", c.kb, c.t1, c.chunk, c.batch, c.graph, c.ms);
       js += buf;
     }
     snprintf(buf, sizeof(buf),
-             "], \"chosen\": {\"ktile_t1\": %d, \"chunk\": %d, \"batch\": %d, \"graph\": %d, \"ms\": %.4f}}",
-             best_t1, best_chunk, best_batch, best_graph, best);
+             "], \"chosen\": {\"kblock\": %d, \"ktile_t1\": %d, \"chunk\": %d, \"batch\": %d, \"graph\": %d, "
+             "\"ms\": %.4f}}",
+             best_kb, best_t1, best_chunk, best_batch, best_graph, best);
     js += buf;
     const size_t n = std::min<size_t>(js.size(), (size_t)len - 1);
     memcpy(report, js.data(), n);
@@ -1843,6 +1928,7 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
     pl->wtile.P = P;
   }
   set_ktile(pl, pl->ndim == 3 ? 8 : 16);
+  set_layouts(pl);
   isg_status st = guarded(pl, [&]() -> isg_status {
     HIP_OK(hipGetDevice(&pl->device));
     HIP_OK(hipDeviceGetAttribute(&pl->ncu, hipDeviceAttributeMultiprocessorCount, pl->device));
@@ -2123,6 +2209,18 @@ isg_status isg_plan_set_option(isg_plan* pl, isg_option option, int64_t value) {
       if (value != 0 && value != 1) return fail(ISG_ERR_INVALID_ARG, "graph option must be 0 or 1");
       pl->opt_graph = (int)value;
       break;
+    case ISG_OPT_KBLOCK:
+      if (value != 0 && (value < 1 || value > 6)) return fail(ISG_ERR_INVALID_ARG, "k-space block must be 0 or 1..6");
+      {
+        const isg_status s2 = guarded(pl, [&]() -> isg_status {
+          HIP_OK(hipStreamSynchronize(pl->stream));
+          pl->opt_blk_tlog = value == 0 ? 30 : (int)value;
+          set_layouts(pl);
+          return ISG_OK;
+        });
+        if (s2 != ISG_OK) return s2;
+      }
+      break;
     case ISG_OPT_KTILE_T1:
       if (value != 4 && value != 8 && value != 16) return fail(ISG_ERR_INVALID_ARG, "k-space tile extent must be 4, 8 or 16");
       {
@@ -2148,6 +2246,7 @@ isg_status isg_plan_get_option(const isg_plan* pl, isg_option option, int64_t* v
     case ISG_OPT_PHASE_BATCH: *value = pl->opt_phase_batch; break;
     case ISG_OPT_GRAPH: *value = pl->opt_graph; break;
     case ISG_OPT_KTILE_T1: *value = pl->opt_ktile_t1; break;
+    case ISG_OPT_KBLOCK: *value = pl->opt_blk_tlog >= 30 ? 0 : pl->opt_blk_tlog; break;
     default: return fail(ISG_ERR_INVALID_ARG, "unknown option");
   }
   return ISG_OK;

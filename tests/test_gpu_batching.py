@@ -7,6 +7,8 @@ floating-point summation order:
   does, so results are compared bit for bit;
 * graph replays re-run the captured kernels, so they are compared bit for
   bit with the eager call, replay after replay, with eager work between;
+* the row-blocked layout of the internal k-space arrays changes addresses
+  only, so results are compared bit for bit;
 * a different spread chunk or k-space tile extent changes only the order in
   which contributions are summed: 1e-6 relative (a few FP32 roundings), and
   the result is still held to the oracle's 1e-5.
@@ -167,3 +169,30 @@ def test_ktile_extent(setup):
     assert rel(res[4], res[8]) < 1e-6
     want = oracle.sense.normal(inp["x"], 0.1, inp["d"], inp["S"], inp["k"])
     assert rel(res[4], want) < 1e-5
+
+
+def test_kspace_blocking_is_bit_exact(setup):
+    """row-blocked internal k-space arrays (32 x 40 x 48: register-FFT path)"""
+    import torch
+    isg = setup[0]
+    w = small_workload(shape=(32, 40, 48), ncoils=6, nphases=2, spokes=(25, 70), cfg=142)
+    inp = make_inputs(w)
+    x = to_dev(inp["x"])
+    M = sum(k.shape[0] for k in inp["k"])
+    y = to_dev((np.random.default_rng(6).standard_normal((M, w.ncoils, 2)) @ [1, 1j]).astype(np.complex64))
+    plan, S, mots, trs = _plan(isg, w, inp)
+    ref = None
+    for kb in (0, 3, 2, 4):
+        say(f"k-space blocking {kb}")
+        plan.set_option("kblock", kb)
+        assert plan.get_option("kblock") == kb
+        res = (plan.sense_forward(x, mots, S, trs), plan.sense_adjoint(y, mots, S, trs),
+               plan.normal(x, 0.3, mots, S, trs))
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = [r.clone() for r in res]
+            want = oracle.sense.normal(inp["x"], 0.3, inp["d"], inp["S"], inp["k"])
+            assert rel(res[2].cpu().numpy(), want) < 1e-5
+        else:
+            for a, r in zip(res, ref):
+                assert torch.equal(a, r)
