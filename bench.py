@@ -258,7 +258,7 @@ def main():
 
     total_samples = sum(k.shape[0] for k in inp["k"])
     line = {
-        "metric": "nonrigid-SENSE A^H A applies/s at 160^3x12 coils",
+        "metric": f"nonrigid-SENSE A^H A applies/s at {w.shape[0]}^3x{w.ncoils} coils",
         "value": round(value, 3),
         "unit": "applies/s",
         "n_gpus": 1,
