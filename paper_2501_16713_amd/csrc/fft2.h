@@ -408,6 +408,43 @@ struct St2Masked {
   }
 };
 
+// axis-0 load of a tile-major spread output (3D): the touched tiles of each
+// tile column are stored one after another from colbase[col]; the k-th
+// touched tile of the column (k = touched tiles below it) holds rows t0 of
+// that column.  Untouched tiles read as zero.
+template <int S>
+struct Ld2Tiles {
+  const typename Elem<S>::T* p;
+  const uint64_t* colmask;
+  const int* colbase;
+  int C, G2, ts0_log2, ts1, ts2, nt2;
+  int64_t volC;   // elements per tile
+  int64_t rowC;   // elements per tile row of axis 0 (TS1 TS2 C)
+  FastDiv cdiv, g2div;
+  const float2* tw;
+  struct Line {
+    const typename Elem<S>::T* base;
+    uint64_t mask;
+  };
+  __device__ Line setup(int64_t, int64_t b, bool valid) const {
+    if (!valid) return Line{p, 0ull};
+    const uint32_t q = cdiv.div((uint32_t)b);
+    const int c = (int)(b - (int64_t)q * C);
+    const uint32_t i1 = g2div.div(q);
+    const int i2 = (int)(q - i1 * (uint32_t)G2);
+    const int col = (int)(i1 / (uint32_t)ts1) * nt2 + i2 / ts2;
+    const int l1 = (int)(i1 % (uint32_t)ts1), l2 = i2 % ts2;
+    return Line{p + (int64_t)colbase[col] * volC + (int64_t)(l1 * ts2 + l2) * C + c, colmask[col]};
+  }
+  template <int L>
+  __device__ float2 get(const Line& ln, int pos, bool valid) const {
+    const int t0 = pos >> ts0_log2;
+    if (!valid || !((ln.mask >> t0) & 1ull)) return make_float2(0.f, 0.f);
+    const int k = __popcll(ln.mask & ((1ull << t0) - 1ull));
+    return Elem<S>::load(ln.base + (int64_t)k * volC + (int64_t)(pos & ((1 << ts0_log2) - 1)) * rowC);
+  }
+};
+
 // first pass of inverse k-space gridding: S_c . m / c(x/G) |N|^{-1/2},
 // zero-padded (centred) along the last axis; lines are (a, c)
 struct Ld2CoilExpand {

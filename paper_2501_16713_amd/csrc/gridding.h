@@ -409,11 +409,13 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
 // scratch slot `slot`, and a reduce step sums the slots of the tile.
 struct KUnit {
   int tile, start, count, slot;
+  int gslot;  // tile-major grids: the tile's slot among the touched tiles
 };
 // a tile whose samples were cut into several units: partial slots
 // first_slot .. first_slot + nslots - 1
 struct KSplit {
   int tile, first_slot, nslots;
+  int gslot;  // as in KUnit
 };
 struct KTap {
   float f[3];
@@ -439,6 +441,9 @@ struct KBatch {
   T* grid[kMaxPhasesPerLaunch];
   float2* partial[kMaxPhasesPerLaunch];
   Blk blk;  // row-blocked layout of every grid of the batch
+  // spread output tile-major instead: the touched tiles one after another,
+  // each [TS0][TS1][TS2][C] contiguous at gslot * vol * C (spread and reduce)
+  int tiled;
 };
 
 // the state a block belongs to
@@ -696,6 +701,14 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
     const int gl = lo[NDIM - 1] + l2;
     const bool okl = gl < dm.G[NDIM - 1];
     const int nrows = kt.vol / kt.TS[NDIM - 1];
+    if (bt.tiled && un.slot < 0) {  // tile-major: one contiguous tile
+      typename Elem<S>::T* dst = grid + (int64_t)un.gslot * volC + within;
+      for (int row = r0; row < nrows; row += rpi) {
+        const int pi = NDIM == 3 ? (row / kt.TS[1]) * kt.S0 + (row % kt.TS[1]) * kt.S1 : row * kt.S0;
+        Elem<S>::store(dst + row * rowlen, src[pi]);
+      }
+      return;
+    }
     for (int row = r0; row < nrows; row += rpi) {
       int l0, l1 = 0, pi;
       if constexpr (NDIM == 3) {
@@ -752,6 +765,10 @@ __global__ __launch_bounds__(kGridThreads) void kspread_reduce_kernel(KBatch<typ
     float2 s = acc[0];
 #pragma unroll
     for (int q = 1; q < 8; ++q) s = cadd(s, acc[q]);
+    if (bt.tiled) {  // tile-major: the point-major partial layout is the tile's
+      Elem<S>::store(grid + (int64_t)sp.gslot * volC + e, s);
+      continue;
+    }
     const int pt = e / C;
     const int c = e - pt * C;
     int l[3] = {0, 0, 0};

@@ -155,6 +155,7 @@ struct isg_plan {
   float2* mbuf = nullptr;   // [N]
   float2* wbuf = nullptr;   // [P][N]
   DevBuf kgrid;             // [batch][NG][C]
+  DevBuf kgrid_adj;         // [batch][touched tiles][tile][C], tile-major spread output
   void* k1buf = nullptr;
   void* k2buf = nullptr;
   DevBuf ybuf;              // normal-operator data, grown on demand
@@ -248,6 +249,9 @@ struct isg_traj {
   isg_plan* plan = nullptr;
   int64_t M = 0;
   uint64_t* colmask = nullptr;  // touched-tile masks (null: all tiles written)
+  int* colbase = nullptr;       // tile-major spread output: first slot of each tile column
+  std::vector<uint64_t> colmask_h;
+  std::vector<int> colbase_h;
   int64_t nvis = 0;             // spread visits (sample, tile) in tile order
   int64_t ntouched = 0;         // spread tiles any sample touches
   KTap* taps_v = nullptr;       // tap record of every visit
@@ -265,6 +269,8 @@ struct isg_traj {
   std::vector<int> tile_first;    // host: tile-sorted visits of tile t are tile_first[t] .. tile_first[t+1]
   std::vector<KTap> taps_h;       // host copy of taps (re-binning for another tile shape)
 };
+
+static bool tiled_adjoint(const isg_plan* pl);
 
 static void* dmalloc(isg_plan* pl, size_t bytes) {
   void* p = nullptr;
@@ -840,6 +846,28 @@ static St2Masked<S> st2_masked(void* p, const Blk& blk, const TileMask& tm, floa
 }
 
 template <int S>
+static Ld2Tiles<S> ld2_tiles(isg_plan* pl, const void* p, const isg_traj* tr, int L) {
+  Ld2Tiles<S> ld;
+  ld.p = (const typename Elem<S>::T*)p;
+  ld.colmask = tr->colmask;
+  ld.colbase = tr->colbase;
+  ld.C = pl->C;
+  ld.G2 = pl->G[2];
+  int lg = 0;
+  while ((1 << lg) < pl->ktile.TS[0]) ++lg;
+  ld.ts0_log2 = lg;
+  ld.ts1 = pl->ktile.TS[1];
+  ld.ts2 = pl->ktile.TS[2];
+  ld.nt2 = pl->ktile.nt[2];
+  ld.volC = (int64_t)pl->ktile.vol * pl->C;
+  ld.rowC = (int64_t)pl->ktile.TS[1] * pl->ktile.TS[2] * pl->C;
+  ld.cdiv = make_fastdiv((uint32_t)pl->C);
+  ld.g2div = make_fastdiv((uint32_t)pl->G[2]);
+  ld.tw = line_plan(pl, L).tw;
+  return ld;
+}
+
+template <int S>
 static Ld2Masked<S> ld2_masked(isg_plan* pl, const void* p, const Blk& blk, const TileMask& tm, int L) {
   Ld2Masked<S> ld;
   ld.p = (const typename Elem<S>::T*)p;
@@ -944,10 +972,15 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
   const int C = pl->C;
   const float scale = image_end_scale(pl);
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
-    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0,
-                                 ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
-                                 st2_rows<S>(pl->k2buf, pl->blk_k2, kCentred, axis_store_scale(pl, 0)),
-                                 make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
+    if (tr && tiled_adjoint(pl))  // spread output tile-major (touched tiles only)
+      run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2_tiles<S>(pl, grid, tr, G0),
+                                   st2_rows<S>(pl->k2buf, pl->blk_k2, kCentred, axis_store_scale(pl, 0)),
+                                   make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
+    else
+      run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0,
+                                   ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
+                                   st2_rows<S>(pl->k2buf, pl->blk_k2, kCentred, axis_store_scale(pl, 0)),
+                                   make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax1", G1,
                                  ld2_axis1<S>(pl, pl->k2buf, pl->blk_k2, kDense, G1),
                                  st2<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred,
@@ -1024,9 +1057,10 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
 // coil-expanded grid and its data.
 struct KJob {
   const isg_traj* tr;
-  void* grid;
+  void* grid;         // gather input (and spread output unless sgrid is set)
   const float2* yin;  // spread input, visit order [nvis][C]
   float2* yout;       // gather output ([M][C], or [nvis][C] in visit order)
+  void* sgrid;        // spread output when it differs from grid (tile-major)
 };
 
 // y = G_p grid_p for every job, kMaxPhasesPerLaunch states per launch
@@ -1092,7 +1126,7 @@ static void kspread_nd(isg_plan* pl, const KJob* jobs, int n) {
       bt.units[i] = jb.tr->units;
       bt.taps[i] = jb.tr->taps_v;
       bt.yin[i] = jb.yin;
-      bt.grid[i] = (T*)jb.grid;
+      bt.grid[i] = (T*)(jb.sgrid ? jb.sgrid : jb.grid);
       bt.partial[i] = (float2*)pl->partial.p + slot0 * volC;
       units += jb.tr->nunits;
       splits += jb.tr->nsplits;
@@ -1100,6 +1134,7 @@ static void kspread_nd(isg_plan* pl, const KJob* jobs, int n) {
     }
     bt.first[nb] = (int)units;
     bt.blk = pl->blk_grid;
+    bt.tiled = NDIM == 3 && tiled_adjoint(pl);
     {
       Tick tick(pl, "kspread");
       hipLaunchKernelGGL(k, dim3((unsigned)units), dim3(kthreads), lds, pl->stream, bt, pl->C, pl->dims, pl->ktile,
@@ -1153,7 +1188,7 @@ static float2* to_visit_order(isg_plan* pl, const isg_traj* tr, const float2* y,
 
 // scratch of the k-space stages for `nb` states processed together: their
 // grids (kgrid, [nb][NG][C]) and their visit-ordered data (ybuf)
-static void ensure_kspace(isg_plan* pl, int nb = 1, int64_t visits = 0) {
+static void ensure_kspace(isg_plan* pl, int nb = 1, int64_t visits = 0, int64_t adj_tiles = 0) {
   const size_t es = pl->storage == kFP32 ? 8 : 4;
   const int64_t C = pl->C;
   if (!pl->k1buf) {
@@ -1167,11 +1202,27 @@ static void ensure_kspace(isg_plan* pl, int nb = 1, int64_t visits = 0) {
   }
   grow(pl, pl->kgrid, es * (size_t)pl->NG * C * (size_t)std::max(1, nb));
   grow(pl, pl->ybuf, sizeof(float2) * (size_t)std::max<int64_t>(1, visits) * C);
+  if (adj_tiles > 0)
+    grow(pl, pl->kgrid_adj, es * (size_t)adj_tiles * pl->ktile.vol * C * (size_t)std::max(1, nb));
 }
 
 static void* grid_of(const isg_plan* pl, int i) {
   const size_t es = pl->storage == kFP32 ? 8 : 4;
   return (char*)pl->kgrid.p + es * (size_t)pl->NG * pl->C * (size_t)i;
+}
+
+// tile-major spread output of batch member i (tiles: the largest touched-tile
+// count of the call's states), or the member's grid when not tile-major
+static void* sgrid_of(const isg_plan* pl, int i, int64_t tiles) {
+  if (!tiled_adjoint(pl)) return grid_of(pl, i);
+  const size_t es = pl->storage == kFP32 ? 8 : 4;
+  return (char*)pl->kgrid_adj.p + es * (size_t)tiles * pl->ktile.vol * pl->C * (size_t)i;
+}
+
+static int64_t max_touched(const isg_traj* const* k, int P) {
+  int64_t t = 1;
+  for (int p = 0; p < P; ++p) t = std::max(t, k[p]->ntouched);
+  return t;
 }
 
 // states per batch of the k-space stages
@@ -1201,7 +1252,7 @@ static void op_sense_forward(isg_plan* pl, int P, const float2* x, const isg_mot
       const int p = p0 + i;
       warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
       STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, grid_of(pl, i), k[p]);
-      jobs[i] = KJob{k[p], grid_of(pl, i), nullptr, y + off};
+      jobs[i] = KJob{k[p], grid_of(pl, i), nullptr, y + off, nullptr};
       off += k[p]->M * pl->C;
     }
     STORAGE_DISPATCH(pl, kgather_t, pl, jobs.data(), nb, false);
@@ -1213,7 +1264,8 @@ static void op_sense_adjoint(isg_plan* pl, int P, const float2* y, const isg_mot
   const int B = phase_batch(pl, P);
   int64_t vmax = 1;
   for (int p0 = 0; p0 < P; p0 += B) vmax = std::max(vmax, group_visits(k, p0, std::min(B, P - p0)));
-  ensure_kspace(pl, B, vmax);
+  const int64_t tiles = max_touched(k, P);
+  ensure_kspace(pl, B, vmax, tiled_adjoint(pl) ? tiles : 0);
   std::vector<const float2*> w(P);
   std::vector<KJob> jobs(B);
   int64_t off = 0;
@@ -1223,14 +1275,14 @@ static void op_sense_adjoint(isg_plan* pl, int P, const float2* y, const isg_mot
     for (int i = 0; i < nb; ++i) {
       const int p = p0 + i;
       to_visit_order(pl, k[p], y + off, yv);
-      jobs[i] = KJob{k[p], grid_of(pl, i), yv, nullptr};
+      jobs[i] = KJob{k[p], grid_of(pl, i), yv, nullptr, sgrid_of(pl, i, tiles)};
       yv += k[p]->nvis * pl->C;
       off += k[p]->M * pl->C;
     }
     STORAGE_DISPATCH(pl, kspread_t, pl, jobs.data(), nb);
     for (int i = 0; i < nb; ++i) {
       const int p = p0 + i;
-      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, grid_of(pl, i), S, pl->wbuf + (int64_t)p * pl->N, k[p]);
+      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, sgrid_of(pl, i, tiles), S, pl->wbuf + (int64_t)p * pl->N, k[p]);
       w[p] = pl->wbuf + (int64_t)p * pl->N;
     }
   }
@@ -1243,7 +1295,8 @@ static void op_normal(isg_plan* pl, int P, const float2* x, double lam, const is
   const int B = phase_batch(pl, P);
   int64_t vmax = 1;
   for (int p0 = 0; p0 < P; p0 += B) vmax = std::max(vmax, group_visits(k, p0, std::min(B, P - p0)));
-  ensure_kspace(pl, B, vmax);
+  const int64_t tiles = max_touched(k, P);
+  ensure_kspace(pl, B, vmax, tiled_adjoint(pl) ? tiles : 0);
   upsample(pl, x, pl->ugrid);
   std::vector<const float2*> w(P);
   std::vector<KJob> jobs(B);
@@ -1254,14 +1307,15 @@ static void op_normal(isg_plan* pl, int P, const float2* x, double lam, const is
       const int p = p0 + i;
       warp_gather(pl, pl->ugrid, d[p], pl->mbuf);
       STORAGE_DISPATCH(pl, coil_forward_t, pl, pl->mbuf, S, grid_of(pl, i), k[p]);
-      jobs[i] = KJob{k[p], grid_of(pl, i), yv, yv};  // gathered straight into visit order, spread from there
+      // gathered straight into visit order, spread from there
+      jobs[i] = KJob{k[p], grid_of(pl, i), yv, yv, sgrid_of(pl, i, tiles)};
       yv += k[p]->nvis * pl->C;
     }
     STORAGE_DISPATCH(pl, kgather_t, pl, jobs.data(), nb, true);
     STORAGE_DISPATCH(pl, kspread_t, pl, jobs.data(), nb);
     for (int i = 0; i < nb; ++i) {
       const int p = p0 + i;
-      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, grid_of(pl, i), S, pl->wbuf + (int64_t)p * pl->N, k[p]);
+      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, sgrid_of(pl, i, tiles), S, pl->wbuf + (int64_t)p * pl->N, k[p]);
       w[p] = pl->wbuf + (int64_t)p * pl->N;
     }
   }
@@ -1431,6 +1485,20 @@ static bool traj_masked(const isg_plan* pl) {
 // unit per chunk writing a partial tile, summed afterwards in slot order.
 // Untouched tiles get no unit when the axis-0 passes skip them, else a unit
 // that writes zeros.  Units are ordered longest first.
+// The spread output is stored tile-major (touched tiles only, each tile
+// contiguous, columns in order) on the 3D register-FFT path with masks; the
+// adjoint axis-0 pass then reads each column's rows from consecutive tiles.
+static bool tiled_adjoint(const isg_plan* pl) { return pl->ndim == 3 && traj_masked(pl); }
+
+// slot of tile t in the tile-major spread output of trajectory tr
+static int tile_gslot(const isg_plan* pl, const isg_traj* tr, int t) {
+  if (!tiled_adjoint(pl)) return -1;
+  const int ncols = pl->ktile.nt[1] * pl->ktile.nt[2];
+  const int t0 = t / ncols, col = t - t0 * ncols;
+  const uint64_t below = tr->colmask_h[col] & ((1ull << t0) - 1ull);
+  return tr->colbase_h[col] + __builtin_popcountll(below);
+}
+
 static void build_units(isg_plan* pl, isg_traj* tr) {
   const int chunk = pl->opt_spread_chunk;
   const bool masked = traj_masked(pl);
@@ -1442,17 +1510,19 @@ static void build_units(isg_plan* pl, isg_traj* tr) {
   for (int t = 0; t < ntiles; ++t) {
     const int beg = cnt[t], c = cnt[t + 1] - cnt[t];
     if (c == 0 && masked) continue;
+    const int gs = c > 0 ? tile_gslot(pl, tr, t) : -1;
     if (c <= chunk) {
-      units.push_back(KUnit{t, beg, c, -1});
+      units.push_back(KUnit{t, beg, c, -1, gs});
     } else {
       const int nch = (c + chunk - 1) / chunk;
-      splits.push_back(KSplit{t, slots, nch});
-      for (int q = 0; q < nch; ++q) units.push_back(KUnit{t, beg + q * chunk, std::min(chunk, c - q * chunk), slots + q});
+      splits.push_back(KSplit{t, slots, nch, gs});
+      for (int q = 0; q < nch; ++q)
+        units.push_back(KUnit{t, beg + q * chunk, std::min(chunk, c - q * chunk), slots + q, gs});
       slots += nch;
     }
   }
   std::stable_sort(units.begin(), units.end(), [](const KUnit& a, const KUnit& b) { return a.count > b.count; });
-  if (units.empty()) units.push_back(KUnit{0, 0, 0, -1});  // keep the launch non-empty
+  if (units.empty()) units.push_back(KUnit{0, 0, 0, -1, -1});  // keep the launch non-empty
   HIP_OK(hipStreamSynchronize(pl->stream));
   pl->generation++;
   if (tr->units) HIP_OK(hipFree(tr->units));
@@ -1487,9 +1557,11 @@ static void bin_traj(isg_plan* pl, isg_traj* tr) {
   const std::vector<KTap>& taps = tr->taps_h;
   HIP_OK(hipStreamSynchronize(pl->stream));
   pl->generation++;
-  for (void** q : {(void**)&tr->order, (void**)&tr->colmask, (void**)&tr->taps_v, (void**)&tr->vis_off,
-                   (void**)&tr->vis})
+  for (void** q : {(void**)&tr->order, (void**)&tr->colmask, (void**)&tr->colbase, (void**)&tr->taps_v,
+                   (void**)&tr->vis_off, (void**)&tr->vis})
     traj_free(pl, *q);
+  tr->colmask_h.clear();
+  tr->colbase_h.clear();
   int ntiles = 1;
   for (int i = 0; i < nd; ++i) ntiles *= pl->ktile.nt[i];
   std::vector<int> cnt(ntiles + 1, 0);
@@ -1527,6 +1599,15 @@ static void bin_traj(isg_plan* pl, isg_traj* tr) {
     }
     tr->colmask = (uint64_t*)dmalloc(pl, sizeof(uint64_t) * ncols);
     HIP_OK(hipMemcpy(tr->colmask, cm.data(), sizeof(uint64_t) * ncols, hipMemcpyHostToDevice));
+    tr->colmask_h = cm;
+    tr->colbase_h.assign(ncols, 0);
+    int base = 0;
+    for (int col = 0; col < ncols; ++col) {
+      tr->colbase_h[col] = base;
+      base += __builtin_popcountll(cm[col]);
+    }
+    tr->colbase = (int*)dmalloc(pl, sizeof(int) * ncols);
+    HIP_OK(hipMemcpy(tr->colbase, tr->colbase_h.data(), sizeof(int) * ncols, hipMemcpyHostToDevice));
   }
   tr->order = (int*)dmalloc(pl, sizeof(int) * order.size());
   HIP_OK(hipMemcpy(tr->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
@@ -1974,6 +2055,7 @@ isg_status isg_plan_destroy(isg_plan* pl) {
   if (pl->ngraph.exec) (void)hipGraphExecDestroy(pl->ngraph.exec);
   if (pl->ngraph.graph) (void)hipGraphDestroy(pl->ngraph.graph);
   if (pl->kgrid.p) (void)hipFree(pl->kgrid.p);
+  if (pl->kgrid_adj.p) (void)hipFree(pl->kgrid_adj.p);
   if (pl->ybuf.p) (void)hipFree(pl->ybuf.p);
   if (pl->partial.p) (void)hipFree(pl->partial.p);
   if (pl->cg_hist.p) (void)hipFree(pl->cg_hist.p);
@@ -2086,7 +2168,7 @@ isg_status isg_traj_destroy(isg_traj* tr) {
     tr->plan->generation++;
   }
   for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->units, (void*)tr->splits, (void*)tr->colmask,
-                  (void*)tr->taps_v, (void*)tr->vis_off, (void*)tr->vis})
+                  (void*)tr->colbase, (void*)tr->taps_v, (void*)tr->vis_off, (void*)tr->vis})
     if (p) (void)hipFree(p);
   delete tr;
   return ISG_OK;
@@ -2276,7 +2358,8 @@ isg_status isg_sense_grad(isg_plan* pl, int P, const void* x, const isg_motion* 
   return guarded(pl, [&]() {
     int64_t vmax = 1;
     for (int p = 0; p < P; ++p) vmax = std::max(vmax, k[p]->nvis);
-    ensure_kspace(pl, 1, vmax);
+    const int64_t tiles = max_touched(k, P);
+    ensure_kspace(pl, 1, vmax, tiled_adjoint(pl) ? tiles : 0);
     const float2* Sm = (const float2*)S;
     // u = the upsampled x, needed by every d-gradient (before the spread reuses ugrid)
     if (grad_d) upsample(pl, (const float2*)x, pl->ugrid);
@@ -2285,10 +2368,10 @@ isg_status isg_sense_grad(isg_plan* pl, int P, const void* x, const isg_motion* 
     for (int p = 0; p < P; ++p) {
       // v_p = sum_c conj(S_c) G_p^H r_{p,c}
       float2* yv = to_visit_order(pl, k[p], (const float2*)r + off, (float2*)pl->ybuf.p);
-      const KJob job{k[p], grid_of(pl, 0), yv, nullptr};
+      const KJob job{k[p], grid_of(pl, 0), yv, nullptr, sgrid_of(pl, 0, tiles)};
       STORAGE_DISPATCH(pl, kspread_t, pl, &job, 1);
       float2* v = pl->wbuf + (int64_t)p * pl->N;
-      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, grid_of(pl, 0), Sm, v, k[p]);
+      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, sgrid_of(pl, 0, tiles), Sm, v, k[p]);
       w[p] = v;
       if (grad_d) {
         Tick tick(pl, "warp_grad");
