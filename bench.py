@@ -193,6 +193,7 @@ def main():
             cg = {"iters": args.cg_iters, "seconds": round(cg_s, 4),
                   "ms_per_iter": round(1000 * cg_s / args.cg_iters, 3),
                   "resnorm_first_last": [hist[0], hist[-1]]}
+            cg_y, cg_ref = y, xs
         ref_out = out.clone()
     torch.cuda.synchronize()
 
@@ -244,6 +245,11 @@ def main():
         if storage != args.storage:  # relative difference from the headline form's output
             diff = torch.linalg.vector_norm(o2 - ref_out) / torch.linalg.vector_norm(ref_out)
             entry["rel_diff_vs_" + args.storage] = float(diff.item())
+            if cg is not None:  # the same CG solve with this form's grids
+                with torch.cuda.stream(stream):
+                    xs2, _ = p2.cg_solve(cg_y, m2, S, t2, lam, args.cg_iters)
+                    cdiff = torch.linalg.vector_norm(xs2 - cg_ref) / torch.linalg.vector_norm(cg_ref)
+                entry["cg_rel_diff_vs_" + args.storage] = float(cdiff.item())
         forms[name] = entry
         del p2, m2, t2, o2
         torch.cuda.synchronize()

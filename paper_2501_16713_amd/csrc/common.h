@@ -149,4 +149,61 @@ __device__ __forceinline__ float2 store_scaled(float2 v, float s) {
   }
 }
 
+// Half-precision spread output.  Radial sampling piles thousands of samples
+// onto the cells near the k-space centre, so an unscaled spread of data of
+// any magnitude overflows FP16.  Each state's spread output is stored times
+// 2^e with e the largest exponent keeping dens * 2 * ymax * 2^e below
+// kHalfSpreadTarget: dens bounds how many samples reach one cell (every
+// kernel weight is at most 1), ymax is the largest |re| or |im| of the data
+// (|z| <= sqrt 2 max(|re|, |im|)), so no stored cell can exceed the target.
+// The target leaves headroom for the next pass (a line of 2n values summed
+// and scaled by n^{-1/2}).  Powers of two scale exactly; zero or non-finite
+// data takes e = 0.
+// ymax of one state is kept over kYmaxSlots words (wavefronts pick one by
+// index, readers take the largest), so the atomics of a launch do not all
+// meet at one address.
+constexpr float kHalfSpreadTarget = 1024.f;
+constexpr int kYmaxSlots = 64;
+__device__ __forceinline__ int spread_exp(const unsigned* ymax, float dens) {
+  unsigned b = 0u;
+  const uint4* y4 = reinterpret_cast<const uint4*>(ymax);
+#pragma unroll
+  for (int i = 0; i < kYmaxSlots / 4; ++i) {
+    const uint4 v = y4[i];
+    b = max(b, max(max(v.x, v.y), max(v.z, v.w)));
+  }
+  const float m = __uint_as_float(b);
+  if (!(m > 0.f) || !(m < __builtin_inff())) return 0;
+  const float v = kHalfSpreadTarget / (2.f * dens * m);
+  if (!(v < __builtin_inff())) return 120;
+  int e;
+  (void)frexpf(v, &e);  // v = f 2^e with f in [0.5, 1)
+  return max(-120, min(120, e - 1));
+}
+
+// ymax[slot] = max(ymax[slot], m) over the 64 lanes of the calling
+// wavefront, slot chosen by the wavefront's index (m >= 0; every lane must be
+// active; one atomic per wavefront; non-negative floats order as their bit
+// patterns)
+__device__ __forceinline__ void wave_max_to(unsigned* ymax, float m) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  const unsigned w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if ((threadIdx.x & 63) == 0) atomicMax(ymax + (w & (kYmaxSlots - 1)), __float_as_uint(m));
+}
+
+// What the coil reduction multiplies by to undo the half-precision scales:
+// dsc[0] (the inverse of the input scale of a normal-operator call) unless
+// null, times 2^-e of the state's spread output unless ymax is null.
+struct HalfUndo {
+  const float* dsc = nullptr;
+  const unsigned* ymax = nullptr;
+  float dens = 1.f;
+  __device__ __forceinline__ float factor() const {
+    float f = dsc ? dsc[0] : 1.f;
+    if (ymax) f *= ldexpf(1.f, -spread_exp(ymax, dens));
+    return f;
+  }
+};
+
 }  // namespace isg

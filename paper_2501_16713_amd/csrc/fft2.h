@@ -452,6 +452,7 @@ struct Ld2CoilExpand {
   const float2* S;
   AxisTabs dx;
   float scale;
+  const float* dsc;  // half-precision grids: per-call input scale dsc[0] (device), else null
   int64_t N;
   int n;    // stored length (L/2)
   int n1;   // axis-1 extent in 3D, 0 in 2D
@@ -464,7 +465,7 @@ struct Ld2CoilExpand {
   __device__ Line setup(int64_t a, int64_t c, bool valid) const {
     Line ln{m, S, 0.f};
     if (!valid) return ln;
-    float f = scale;
+    float f = dsc ? scale * dsc[0] : scale;
     if (n1) {
       const int i0 = (int)(a / n1), i1 = (int)(a - (int64_t)i0 * n1);
       f *= dx.t[0][i0] * dx.t[1][i1];
@@ -493,18 +494,20 @@ struct St2CoilReduce {
   const float2* S;
   AxisTabs dx;
   float scale;
+  HalfUndo undo;         // half-precision grids: scales to undo (none for FP32)
   int64_t N;
   int n, L, C;
   int n1;
   struct Line {};
   __device__ void epilogue(const float2* lines, const Tile2& g, int64_t a0, int64_t) const {
     const int total = g.na * n;
+    const float hs = scale * undo.factor();
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       const int al = e / n;
       const int j = e - al * n;
       const int64_t a = a0 + al;
       if (a >= g.A) continue;
-      float f = scale * dx.t[n1 ? 2 : 1][j];
+      float f = hs * dx.t[n1 ? 2 : 1][j];
       if (n1) {
         const int i0 = (int)(a / n1), i1 = (int)(a - (int64_t)i0 * n1);
         f *= dx.t[0][i0] * dx.t[1][i1];

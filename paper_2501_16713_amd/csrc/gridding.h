@@ -441,6 +441,12 @@ struct KBatch {
   T* grid[kMaxPhasesPerLaunch];
   float2* partial[kMaxPhasesPerLaunch];
   Blk blk;  // row-blocked layout of every grid of the batch
+  const float* oscale;  // gather: results multiplied by oscale[0] (device), unless null
+  // half-precision grids, else null: the gather into visit order takes the
+  // largest |re|, |im| of member i into ymax[i kYmaxSlots ...] (zeroed
+  // beforehand); the spread stores member i times 2^spread_exp(those, dens[i])
+  unsigned* ymax;
+  float dens[kMaxPhasesPerLaunch];
   // spread output tile-major instead: the touched tiles one after another,
   // each [TS0][TS1][TS2][C] contiguous at gslot * vol * C (spread and reduce)
   int tiled;
@@ -451,6 +457,58 @@ __device__ __forceinline__ int batch_member(const int* first, int n, int b) {
   int p = 0;
   while (p + 1 < n && b >= first[p + 1]) ++p;
   return p;
+}
+
+// one interpolated value: sum over the 4^NDIM taps of tp of the weights
+// times coil c of the grid (times oscale[0] unless null)
+template <int NDIM, int S>
+__device__ __forceinline__ float2 gather_one(const typename Elem<S>::T* __restrict__ grid, const KTap& tp,
+                                             const Blk& blk, int c, int C, const Dims& dm, const KbPoly& kb,
+                                             const float* oscale) {
+  float w[NDIM][4];
+  int g[NDIM][4];
+#pragma unroll
+  for (int i = 0; i < NDIM; ++i) {
+    kb_weights(kb, tp.f[i], w[i]);
+    const int b = (tp.base >> (10 * i)) & 1023;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) g[i][t] = b + t >= dm.G[i] ? b + t - dm.G[i] : b + t;
+  }
+  float2 acc = make_float2(0.f, 0.f);
+  if constexpr (NDIM == 3) {
+#pragma unroll
+    for (int t0 = 0; t0 < 4; ++t0) {
+#pragma unroll
+      for (int t1 = 0; t1 < 4; ++t1) {
+        const float w01 = w[0][t0] * w[1][t1];
+        const typename Elem<S>::T* row = grid + blk.off(g[0][t0], g[1][t1], c);
+        float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int t2 = 0; t2 < 4; ++t2) {
+          const float2 v = Elem<S>::load(row + (int64_t)g[2][t2] * C);
+          s.x = fmaf(w[2][t2], v.x, s.x);
+          s.y = fmaf(w[2][t2], v.y, s.y);
+        }
+        acc.x = fmaf(w01, s.x, acc.x);
+        acc.y = fmaf(w01, s.y, acc.y);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int t0 = 0; t0 < 4; ++t0) {
+      const typename Elem<S>::T* row = grid + (int64_t)g[0][t0] * blk.rs + c;
+      float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int t1 = 0; t1 < 4; ++t1) {
+        const float2 v = Elem<S>::load(row + (int64_t)g[1][t1] * C);
+        s.x = fmaf(w[1][t1], v.x, s.x);
+        s.y = fmaf(w[1][t1], v.y, s.y);
+      }
+      acc.x = fmaf(w[0][t0], s.x, acc.x);
+      acc.y = fmaf(w[0][t0], s.y, acc.y);
+    }
+  }
+  return oscale ? cscale(acc, oscale[0]) : acc;
 }
 
 // y[j][c] = sum_taps prod_i c(kappa_ji - q_i) grid[q][c], grid [G...][C].
@@ -475,67 +533,39 @@ __global__ __launch_bounds__(kGridThreads) void kgather_kernel(KBatch<typename E
   const int c = lane - sub * C;
   const int64_t wave = (int64_t)(blockIdx.x - bt.first[p]) * (kGridThreads / 64) + (threadIdx.x >> 6);
   const int64_t j = wave * spw + sub;
-  if (sub >= spw || j >= M) return;
-  const KTap tp = bt.taps[p][j];
-  float w[NDIM][4];
-  int g[NDIM][4];
-#pragma unroll
-  for (int i = 0; i < NDIM; ++i) {
-    kb_weights(kb, tp.f[i], w[i]);
-    const int b = (tp.base >> (10 * i)) & 1023;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) g[i][t] = b + t >= dm.G[i] ? b + t - dm.G[i] : b + t;
-  }
-  float2 acc = make_float2(0.f, 0.f);
-  if constexpr (NDIM == 3) {
-#pragma unroll
-    for (int t0 = 0; t0 < 4; ++t0) {
-#pragma unroll
-      for (int t1 = 0; t1 < 4; ++t1) {
-        const float w01 = w[0][t0] * w[1][t1];
-        const typename Elem<S>::T* row = grid + bt.blk.off(g[0][t0], g[1][t1], c);
-        float2 s = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int t2 = 0; t2 < 4; ++t2) {
-          const float2 v = Elem<S>::load(row + (int64_t)g[2][t2] * C);
-          s.x = fmaf(w[2][t2], v.x, s.x);
-          s.y = fmaf(w[2][t2], v.y, s.y);
-        }
-        acc.x = fmaf(w01, s.x, acc.x);
-        acc.y = fmaf(w01, s.y, acc.y);
-      }
-    }
-  } else {
-#pragma unroll
-    for (int t0 = 0; t0 < 4; ++t0) {
-      const typename Elem<S>::T* row = grid + (int64_t)g[0][t0] * bt.blk.rs + c;
-      float2 s = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int t1 = 0; t1 < 4; ++t1) {
-        const float2 v = Elem<S>::load(row + (int64_t)g[1][t1] * C);
-        s.x = fmaf(w[1][t1], v.x, s.x);
-        s.y = fmaf(w[1][t1], v.y, s.y);
-      }
-      acc.x = fmaf(w[0][t0], s.x, acc.x);
-      acc.y = fmaf(w[0][t0], s.y, acc.y);
+  if (wave * spw >= M) return;  // wavefront-uniform
+  const bool ok = sub < spw && j < M;
+  float m = 0.f;
+  if (ok) {
+    const float2 acc = gather_one<NDIM, S>(grid, bt.taps[p][j], bt.blk, c, C, dm, kb, bt.oscale);
+    m = fmaxf(fabsf(acc.x), fabsf(acc.y));
+    if (vis_off) {
+      const int v1 = vis_off[j + 1];
+      for (int v = vis_off[j]; v < v1; ++v) y[(int64_t)vis[v] * C + c] = acc;
+    } else {
+      y[j * C + c] = acc;
     }
   }
-  if (vis_off) {
-    const int v1 = vis_off[j + 1];
-    for (int v = vis_off[j]; v < v1; ++v) y[(int64_t)vis[v] * C + c] = acc;
-  } else {
-    y[j * C + c] = acc;
-  }
+  // every lane of the wavefront is active again here
+  if (bt.ymax && vis_off) wave_max_to(bt.ymax + p * kYmaxSlots, m);
 }
 
 // y_visit[v][c] = y[order[v]][c]: data in sample order to spread-visit order
+// (half-precision grids: also the largest |re|, |im| into the kYmaxSlots
+// words at ymax unless null)
 __global__ __launch_bounds__(kGridThreads) void visit_permute_kernel(const float2* __restrict__ y,
                                                                      const int* __restrict__ order, int64_t nvis,
-                                                                     int C, float2* __restrict__ yv) {
+                                                                     int C, float2* __restrict__ yv,
+                                                                     unsigned* __restrict__ ymax) {
   const int64_t e = (int64_t)blockIdx.x * kGridThreads + threadIdx.x;
-  if (e >= nvis * C) return;
-  const int64_t v = e / C;
-  yv[e] = y[(int64_t)order[v] * C + (e - v * C)];
+  float m = 0.f;
+  if (e < nvis * C) {
+    const int64_t v = e / C;
+    const float2 val = y[(int64_t)order[v] * C + (e - v * C)];
+    yv[e] = val;
+    m = fmaxf(fabsf(val.x), fabsf(val.y));
+  }
+  if (ymax) wave_max_to(ymax, m);
 }
 
 // Tile of the k-space spread.  The LDS accumulator holds one plane of P
@@ -692,6 +722,7 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
   const int volC = kt.vol * C;
   const int rowlen = kt.TS[NDIM - 1] * C;
   const int rpi = nthr / rowlen;
+  const float hs = bt.ymax ? ldexpf(1.f, spread_exp(bt.ymax + bp * kYmaxSlots, bt.dens[bp])) : 1.f;
   const int r0 = threadIdx.x / rowlen;
   if (r0 < rpi) {
     const int within = threadIdx.x - r0 * rowlen;
@@ -705,7 +736,7 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
       typename Elem<S>::T* dst = grid + (int64_t)un.gslot * volC + within;
       for (int row = r0; row < nrows; row += rpi) {
         const int pi = NDIM == 3 ? (row / kt.TS[1]) * kt.S0 + (row % kt.TS[1]) * kt.S1 : row * kt.S0;
-        Elem<S>::store(dst + row * rowlen, src[pi]);
+        Elem<S>::store(dst + row * rowlen, store_scaled<S>(src[pi], hs));
       }
       return;
     }
@@ -735,7 +766,7 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
       } else {
         gi = bt.blk.off(gl0, gl, cc);
       }
-      if (ok) Elem<S>::store(grid + gi, v);
+      if (ok) Elem<S>::store(grid + gi, store_scaled<S>(v, hs));
     }
   }
 }
@@ -752,6 +783,7 @@ __global__ __launch_bounds__(kGridThreads) void kspread_reduce_kernel(KBatch<typ
   int lo[3] = {0, 0, 0};
   ktile_origin(sp.tile, kt, NDIM, lo);
   const int volC = kt.vol * C;
+  const float hs = bt.ymax ? ldexpf(1.f, spread_exp(bt.ymax + bp * kYmaxSlots, bt.dens[bp])) : 1.f;
   for (int e = threadIdx.x; e < volC; e += kGridThreads) {
     float2 acc[8];
 #pragma unroll
@@ -766,7 +798,7 @@ __global__ __launch_bounds__(kGridThreads) void kspread_reduce_kernel(KBatch<typ
 #pragma unroll
     for (int q = 1; q < 8; ++q) s = cadd(s, acc[q]);
     if (bt.tiled) {  // tile-major: the point-major partial layout is the tile's
-      Elem<S>::store(grid + (int64_t)sp.gslot * volC + e, s);
+      Elem<S>::store(grid + (int64_t)sp.gslot * volC + e, store_scaled<S>(s, hs));
       continue;
     }
     const int pt = e / C;
@@ -784,7 +816,7 @@ __global__ __launch_bounds__(kGridThreads) void kspread_reduce_kernel(KBatch<typ
       ok = ok && g[i] < dm.G[i];
     }
     const int64_t gi = NDIM == 3 ? bt.blk.off(g[0], g[1], (int64_t)g[2] * C + c) : bt.blk.off(g[0], g[1], c);
-    if (ok) Elem<S>::store(grid + gi, s);
+    if (ok) Elem<S>::store(grid + gi, store_scaled<S>(s, hs));
   }
 }
 

@@ -131,6 +131,10 @@ struct isg_plan {
   int opt_phase_batch = 1;     // states per k-space gather / spread launch
   int opt_graph = 0;           // isg_normal replays a captured graph
   int opt_ktile_t1 = 8;        // k-space spread tile extent along axis 1
+  float* hsc = nullptr;        // half-precision grids: per-call scale [s, 1/s] (device)
+  double* hs_part = nullptr;   // partial sums for hsc
+  unsigned* ymax = nullptr;    // half-precision grids: largest |re|, |im| of each batch slot's spread data
+                               // ([kMaxPhasesPerLaunch][kYmaxSlots])
   int opt_blk_tlog = 3;        // log2 of the i1 block of the row-blocked k-space arrays
   Blk blk_grid, blk_k2;        // layouts of the coil-expanded grid and of k2buf
   hipStream_t stream = nullptr;
@@ -266,6 +270,7 @@ struct isg_traj {
   int nslots = 0;
   int chunk = 0;                  // spread chunk the units were built for
   int ts[3] = {0, 0, 0};          // k-space tile shape the bins were built for
+  float dens = 1.f;               // bound on the samples whose kernel reaches one grid cell
   std::vector<int> tile_first;    // host: tile-sorted visits of tile t are tile_first[t] .. tile_first[t+1]
   std::vector<KTap> taps_h;       // host copy of taps (re-binning for another tile shape)
 };
@@ -799,6 +804,7 @@ static Ld2CoilExpand ld2_expand(isg_plan* pl, const float2* m, const float2* Sm,
   ld.S = Sm;
   ld.dx = tabs(pl->dx);
   ld.scale = image_end_scale(pl);
+  ld.dsc = pl->hsc;
   ld.N = pl->N;
   ld.n = n;
   ld.n1 = n1;
@@ -806,12 +812,14 @@ static Ld2CoilExpand ld2_expand(isg_plan* pl, const float2* m, const float2* Sm,
   return ld;
 }
 
-static St2CoilReduce st2_reduce(isg_plan* pl, float2* w, const float2* Sm, int n, int n1, int L) {
+static St2CoilReduce st2_reduce(isg_plan* pl, float2* w, const float2* Sm, int n, int n1, int L,
+                                const HalfUndo& undo) {
   St2CoilReduce st;
   st.out = w;
   st.S = Sm;
   st.dx = tabs(pl->dx);
   st.scale = image_end_scale(pl);
+  st.undo = undo;
   st.N = pl->N;
   st.n = n;
   st.L = L;
@@ -913,6 +921,7 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
       ld.S = Sm;
       ld.dx = tabs(pl->dx);
       ld.scale = scale;
+      ld.dsc = pl->hsc;
       ld.N = pl->N;
       ld.n = n2;
       ld.L = G2;
@@ -944,6 +953,7 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
       ld.S = Sm;
       ld.dx = tabs(pl->dx);
       ld.scale = scale;
+      ld.dsc = pl->hsc;
       ld.N = pl->N;
       ld.n = n1;
       ld.L = G1;
@@ -966,7 +976,8 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
 // w = sum_c conj(S_c) crop(F_G^H grid) / c(x/G) |N|^{-1/2}; tiles of `tr`
 // that no sample touches are read as zero (tr may be null)
 template <int S>
-static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, float2* w, const isg_traj* tr) {
+static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, float2* w, const isg_traj* tr,
+                           const HalfUndo& undo) {
   const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
   const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
   const int C = pl->C;
@@ -987,13 +998,13 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
                                         axis_store_scale(pl, 1)),
                                  xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G2, ld2<S>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
-                                 st2_reduce(pl, w, Sm, n2, n1, G2), make_tile2((int64_t)n0 * n1, C, G2, C));
+                                 st2_reduce(pl, w, Sm, n2, n1, G2, undo), make_tile2((int64_t)n0 * n1, C, G2, C));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
                                  st2<S>(pl->k1buf, 0, (int64_t)G1 * C, kCentred, axis_store_scale(pl, 0)),
                                  make_tile2(1, (int64_t)G1 * C, G0, 0));
     run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G1, ld2<S>(pl, pl->k1buf, (int64_t)G1 * C, C, kDense, G1),
-                                 st2_reduce(pl, w, Sm, n1, 0, G1), make_tile2(n0, C, G1, C));
+                                 st2_reduce(pl, w, Sm, n1, 0, G1, undo), make_tile2(n0, C, G1, C));
   } else if (pl->ndim == 3) {
     {  // F^H along axis 0, centred crop
       TileGeom g = make_geom(1, (int64_t)G1 * G2 * C, G0, 0);
@@ -1016,6 +1027,7 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
       st.S = Sm;
       st.dx = tabs(pl->dx);
       st.scale = scale;
+      st.undo = undo;
       st.N = pl->N;
       st.n = n2;
       st.L = G2;
@@ -1040,6 +1052,7 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
       st.S = Sm;
       st.dx = tabs(pl->dx);
       st.scale = scale;
+      st.undo = undo;
       st.N = pl->N;
       st.n = n1;
       st.L = G1;
@@ -1063,13 +1076,21 @@ struct KJob {
   void* sgrid;        // spread output when it differs from grid (tile-major)
 };
 
+// the ymax words of n batch slots = 0 before the gather or permutes that fill them
+static void zero_ymax(isg_plan* pl, unsigned* ymax, int n) {
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, pl->stream, ymax, n * kYmaxSlots);
+  LAUNCH_OK();
+}
+
 // y = G_p grid_p for every job, kMaxPhasesPerLaunch states per launch
 template <int S>
-static void kgather_t(isg_plan* pl, const KJob* jobs, int n, bool to_visits) {
+static void kgather_t(isg_plan* pl, const KJob* jobs, int n, bool to_visits, const float* oscale = nullptr) {
   using T = typename Elem<S>::T;
+  if (pl->ymax && n > kMaxPhasesPerLaunch)  // one spread-scale slot per state of a batch
+    throw HipError{hipErrorInvalidValue, "k-space batch larger than the spread-scale slots"};
   const int spw = 64 / pl->C;  // samples per wavefront
   for (int j0 = 0; j0 < n; j0 += kMaxPhasesPerLaunch) {
-    KBatch<T> bt;
+    KBatch<T> bt{};
     memset(&bt, 0, sizeof(bt));
     bt.n = std::min(kMaxPhasesPerLaunch, n - j0);
     int64_t blocks = 0;
@@ -1087,6 +1108,9 @@ static void kgather_t(isg_plan* pl, const KJob* jobs, int n, bool to_visits) {
     }
     bt.first[bt.n] = (int)blocks;
     bt.blk = pl->blk_grid;
+    bt.oscale = oscale;
+    bt.ymax = to_visits && pl->ymax ? pl->ymax + (size_t)j0 * kYmaxSlots : nullptr;
+    if (bt.ymax) zero_ymax(pl, bt.ymax, bt.n);
     Tick tick(pl, "kgather");
     if (pl->ndim == 3)
       hipLaunchKernelGGL((kgather_kernel<3, S>), dim3((unsigned)blocks), dim3(kGridThreads), 0, pl->stream, bt,
@@ -1111,12 +1135,14 @@ static void kspread_nd(isg_plan* pl, const KJob* jobs, int n) {
     throw HipError{hipErrorInvalidConfiguration, "k-space tile row longer than the spread workgroup"};
   auto k = kspread_kernel<NDIM, S>;
   allow_lds(k, lds);
+  if (pl->ymax && n > kMaxPhasesPerLaunch)  // one spread-scale slot per state of a batch
+    throw HipError{hipErrorInvalidValue, "k-space batch larger than the spread-scale slots"};
   for (int j0 = 0; j0 < n; j0 += kMaxPhasesPerLaunch) {
     const int nb = std::min(kMaxPhasesPerLaunch, n - j0);
     int64_t slots = 0;
     for (int i = 0; i < nb; ++i) slots += jobs[j0 + i].tr->nslots;
     if (slots) grow(pl, pl->partial, sizeof(float2) * volC * slots);
-    KBatch<T> bt;
+    KBatch<T> bt{};
     memset(&bt, 0, sizeof(bt));
     bt.n = nb;
     int64_t units = 0, splits = 0, slot0 = 0;
@@ -1128,12 +1154,14 @@ static void kspread_nd(isg_plan* pl, const KJob* jobs, int n) {
       bt.yin[i] = jb.yin;
       bt.grid[i] = (T*)(jb.sgrid ? jb.sgrid : jb.grid);
       bt.partial[i] = (float2*)pl->partial.p + slot0 * volC;
+      bt.dens[i] = jb.tr->dens;
       units += jb.tr->nunits;
       splits += jb.tr->nsplits;
       slot0 += jb.tr->nslots;
     }
     bt.first[nb] = (int)units;
     bt.blk = pl->blk_grid;
+    bt.ymax = pl->ymax ? pl->ymax + (size_t)j0 * kYmaxSlots : nullptr;
     bt.tiled = NDIM == 3 && tiled_adjoint(pl);
     {
       Tick tick(pl, "kspread");
@@ -1174,16 +1202,42 @@ static void kspread_t(isg_plan* pl, const KJob* jobs, int n) {
     }                                                                  \
   } while (0)
 
-// data of one state in sample order -> spread-visit order (into yv)
-static float2* to_visit_order(isg_plan* pl, const isg_traj* tr, const float2* y, float2* yv) {
+// data of one state in sample order -> spread-visit order (into yv); with
+// half-precision grids also the largest |re|, |im| into batch slot `slot`
+// (zeroed beforehand)
+static float2* to_visit_order(isg_plan* pl, const isg_traj* tr, const float2* y, float2* yv, int slot) {
   const int64_t n = tr->nvis * pl->C;
   if (n > 0) {
     Tick tick(pl, "visit_permute");
     hipLaunchKernelGGL(visit_permute_kernel, dim3(blocks_for(n, kGridThreads)), dim3(kGridThreads), 0, pl->stream, y,
-                       tr->order, tr->nvis, pl->C, yv);
+                       tr->order, tr->nvis, pl->C, yv, pl->ymax ? pl->ymax + (size_t)slot * kYmaxSlots : nullptr);
     LAUNCH_OK();
   }
   return yv;
+}
+
+// the scales the coil reduction of batch slot `slot` undoes (nothing for
+// FP32 grids): the input scale of a normal-operator call when
+// `input_scaled`, and the slot's spread-output scale
+static HalfUndo half_undo(const isg_plan* pl, int slot, const isg_traj* tr, bool input_scaled) {
+  HalfUndo u;
+  if (!pl->ymax) return u;
+  u.dsc = input_scaled ? pl->hsc + 1 : nullptr;
+  u.ymax = pl->ymax + (size_t)slot * kYmaxSlots;
+  u.dens = tr->dens;
+  return u;
+}
+
+// Half-precision grids: sc = [1/rms(v), rms(v)] on the device, taken by the
+// coil expansion (or the spread input) and undone by the coil reduction (or
+// the gather output).  No-op for FP32 grids.
+static void set_half_scale(isg_plan* pl, const float2* v, int64_t n) {
+  if (!pl->hsc) return;
+  const unsigned vb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, blocks_for(n, kVecThreads)));
+  Tick tick(pl, "half_scale");
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, v, v, n, pl->hs_part);
+  hipLaunchKernelGGL(half_scale_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->hs_part, (int)vb, n, pl->hsc);
+  LAUNCH_OK();
 }
 
 // scratch of the k-space stages for `nb` states processed together: their
@@ -1243,6 +1297,7 @@ static void op_sense_forward(isg_plan* pl, int P, const float2* x, const isg_mot
                              const isg_traj* const* k, float2* y) {
   const int B = phase_batch(pl, P);
   ensure_kspace(pl, B);
+  set_half_scale(pl, x, pl->N);
   upsample(pl, x, pl->ugrid);
   int64_t off = 0;
   std::vector<KJob> jobs(B);
@@ -1255,7 +1310,7 @@ static void op_sense_forward(isg_plan* pl, int P, const float2* x, const isg_mot
       jobs[i] = KJob{k[p], grid_of(pl, i), nullptr, y + off, nullptr};
       off += k[p]->M * pl->C;
     }
-    STORAGE_DISPATCH(pl, kgather_t, pl, jobs.data(), nb, false);
+    STORAGE_DISPATCH(pl, kgather_t, pl, jobs.data(), nb, false, pl->hsc ? pl->hsc + 1 : nullptr);
   }
 }
 
@@ -1272,9 +1327,10 @@ static void op_sense_adjoint(isg_plan* pl, int P, const float2* y, const isg_mot
   for (int p0 = 0; p0 < P; p0 += B) {
     const int nb = std::min(B, P - p0);
     float2* yv = (float2*)pl->ybuf.p;
+    if (pl->ymax) zero_ymax(pl, pl->ymax, nb);
     for (int i = 0; i < nb; ++i) {
       const int p = p0 + i;
-      to_visit_order(pl, k[p], y + off, yv);
+      to_visit_order(pl, k[p], y + off, yv, i);
       jobs[i] = KJob{k[p], grid_of(pl, i), yv, nullptr, sgrid_of(pl, i, tiles)};
       yv += k[p]->nvis * pl->C;
       off += k[p]->M * pl->C;
@@ -1282,7 +1338,8 @@ static void op_sense_adjoint(isg_plan* pl, int P, const float2* y, const isg_mot
     STORAGE_DISPATCH(pl, kspread_t, pl, jobs.data(), nb);
     for (int i = 0; i < nb; ++i) {
       const int p = p0 + i;
-      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, sgrid_of(pl, i, tiles), S, pl->wbuf + (int64_t)p * pl->N, k[p]);
+      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, sgrid_of(pl, i, tiles), S, pl->wbuf + (int64_t)p * pl->N, k[p],
+                       half_undo(pl, i, k[p], false));
       w[p] = pl->wbuf + (int64_t)p * pl->N;
     }
   }
@@ -1297,6 +1354,7 @@ static void op_normal(isg_plan* pl, int P, const float2* x, double lam, const is
   for (int p0 = 0; p0 < P; p0 += B) vmax = std::max(vmax, group_visits(k, p0, std::min(B, P - p0)));
   const int64_t tiles = max_touched(k, P);
   ensure_kspace(pl, B, vmax, tiled_adjoint(pl) ? tiles : 0);
+  set_half_scale(pl, x, pl->N);
   upsample(pl, x, pl->ugrid);
   std::vector<const float2*> w(P);
   std::vector<KJob> jobs(B);
@@ -1315,7 +1373,8 @@ static void op_normal(isg_plan* pl, int P, const float2* x, double lam, const is
     STORAGE_DISPATCH(pl, kspread_t, pl, jobs.data(), nb);
     for (int i = 0; i < nb; ++i) {
       const int p = p0 + i;
-      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, sgrid_of(pl, i, tiles), S, pl->wbuf + (int64_t)p * pl->N, k[p]);
+      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, sgrid_of(pl, i, tiles), S, pl->wbuf + (int64_t)p * pl->N, k[p],
+                       half_undo(pl, i, k[p], true));
       w[p] = pl->wbuf + (int64_t)p * pl->N;
     }
   }
@@ -1663,6 +1722,28 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
     }
     t.base = packed;
     taps[j] = t;
+  }
+  // dens: a bound on the samples whose kernel support reaches one grid cell,
+  // the largest number reaching one block of 8 cells per axis (scales the
+  // half-precision spread output; independent of the spread tile shape)
+  {
+    int nbk[3] = {1, 1, 1};
+    int64_t nblocks = 1;
+    for (int i = 0; i < nd; ++i) {
+      nbk[i] = (pl->G[i] + 7) / 8;
+      nblocks *= nbk[i];
+    }
+    std::vector<int> cnt((size_t)nblocks, 0);
+    int best = 0;
+    for (int64_t j = 0; j < M; ++j) {
+      int bs[3][2] = {{0, 0}, {0, 0}, {0, 0}}, nbs[3] = {1, 1, 1};
+      for (int i = 0; i < nd; ++i) nbs[i] = axis_tiles((int)((taps[j].base >> (10 * i)) & 1023), pl->G[i], 8, bs[i]);
+      for (int a = 0; a < nbs[0]; ++a)
+        for (int b = 0; b < nbs[1]; ++b)
+          for (int c = 0; c < nbs[2]; ++c)
+            best = std::max(best, ++cnt[((size_t)bs[0][a] * nbk[1] + bs[1][b]) * nbk[2] + bs[2][c]]);
+    }
+    tr->dens = (float)std::max(1, best);
   }
   tr->M = M;
   tr->taps = (KTap*)dmalloc(pl, sizeof(KTap) * taps.size());
@@ -2037,6 +2118,11 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
     pl->mbuf = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->N);
     pl->bufB = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->G[0] * n1 * n2);
     if (pl->ndim == 3) pl->bufC = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->G[0] * pl->G[1] * n2);
+    if (pl->storage != kFP32) {
+      pl->hsc = (float*)plan_alloc(pl, 2 * sizeof(float));
+      pl->hs_part = (double*)plan_alloc(pl, sizeof(double) * kDotBlocks);
+      pl->ymax = (unsigned*)plan_alloc(pl, sizeof(unsigned) * kMaxPhasesPerLaunch * kYmaxSlots);
+    }
     (void)n0;
     return ISG_OK;
   });
@@ -2367,11 +2453,12 @@ isg_status isg_sense_grad(isg_plan* pl, int P, const void* x, const isg_motion* 
     int64_t off = 0;
     for (int p = 0; p < P; ++p) {
       // v_p = sum_c conj(S_c) G_p^H r_{p,c}
-      float2* yv = to_visit_order(pl, k[p], (const float2*)r + off, (float2*)pl->ybuf.p);
+      if (pl->ymax) zero_ymax(pl, pl->ymax, 1);
+      float2* yv = to_visit_order(pl, k[p], (const float2*)r + off, (float2*)pl->ybuf.p, 0);
       const KJob job{k[p], grid_of(pl, 0), yv, nullptr, sgrid_of(pl, 0, tiles)};
       STORAGE_DISPATCH(pl, kspread_t, pl, &job, 1);
       float2* v = pl->wbuf + (int64_t)p * pl->N;
-      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, sgrid_of(pl, 0, tiles), Sm, v, k[p]);
+      STORAGE_DISPATCH(pl, coil_adjoint_t, pl, sgrid_of(pl, 0, tiles), Sm, v, k[p], half_undo(pl, 0, k[p], false));
       w[p] = v;
       if (grad_d) {
         Tick tick(pl, "warp_grad");

@@ -113,6 +113,7 @@ struct LdCoilExpand {
   const float2* S;      // coils [C][A][n]
   AxisTabs dx;          // 1/C(x/G) per axis over centred positions
   float scale;          // |N|^{-1/2}
+  const float* dsc;     // half-precision grids: per-call input scale dsc[0] (device), else null
   int64_t N;            // voxels per coil
   int n, L, C;
   int n1;               // extent of axis 1 (3D) for splitting a; 0 in 2D
@@ -133,7 +134,7 @@ struct LdCoilExpand {
       const int64_t a = a0 + al;
       float2 v = make_float2(0.f, 0.f);
       if (a < g.A) {
-        float f = scale * dx.t[n1 ? 2 : 1][j];
+        float f = (dsc ? scale * dsc[0] : scale) * dx.t[n1 ? 2 : 1][j];
         if (n1) {
           const int i0 = (int)(a / n1), i1 = (int)(a - (int64_t)i0 * n1);
           f *= dx.t[0][i0] * dx.t[1][i1];
@@ -158,18 +159,20 @@ struct StCoilReduce {
   const float2* S;      // coils [C][A][n]
   AxisTabs dx;
   float scale;
+  HalfUndo undo;         // half-precision grids: scales to undo (none for FP32)
   int64_t N;
   int n, L, C;
   int n1;
   FastDiv nd;
   __device__ void operator()(const float2* lines, const TileGeom& g, int64_t a0, int64_t) const {
     const int total = g.na * n;
+    const float hs = scale * undo.factor();
     for (int e = threadIdx.x; e < total; e += kFftThreads) {
       const int al = (int)nd.div((uint32_t)e);
       const int j = e - al * n;
       const int64_t a = a0 + al;
       if (a >= g.A) continue;
-      float f = scale * dx.t[n1 ? 2 : 1][j];
+      float f = hs * dx.t[n1 ? 2 : 1][j];
       if (n1) {
         const int i0 = (int)(a / n1), i1 = (int)(a - (int64_t)i0 * n1);
         f *= dx.t[0][i0] * dx.t[1][i1];

@@ -50,6 +50,29 @@ __device__ __forceinline__ double sum_partials(const double* partial, int np) {
   return block_sum(s);
 }
 
+// Input scale of a half-precision operator application: sc[0] = 2^-e and
+// sc[1] = 2^e with rms(v) = f 2^e, f in [0.5, 1) (1 and 1 for a zero or
+// non-finite rms), from sum(partial) = ||v||^2 over n complex values.  The
+// coil grids then hold the operator applied to an input of rms in
+// [0.5, 1), inside FP16 range whatever the caller's scale, and powers of two
+// scale exactly.
+__global__ __launch_bounds__(kVecThreads) void half_scale_kernel(const double* __restrict__ partial, int np,
+                                                                 int64_t n, float* __restrict__ sc) {
+  const double s = sum_partials(partial, np);
+  if (threadIdx.x == 0) {
+    const double rms = sqrt(s / (double)(n > 0 ? n : 1));
+    int e = 0;
+    if (rms > 1e-30 && rms < 1e30) (void)frexp(rms, &e);
+    sc[0] = ldexpf(1.f, -e);
+    sc[1] = ldexpf(1.f, e);
+  }
+}
+
+// p[0 .. n) = 0 (a kernel, not a memset node, so graph replays clear it too)
+__global__ void zero_u32_kernel(unsigned* __restrict__ p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
 // rho = sum(partial); hist[0] = sqrt(rho); iter = 0; breakdown = 0
 __global__ __launch_bounds__(kVecThreads) void cg_init_kernel(const double* __restrict__ partial, int np,
                                                               CgScalars* sc, double* hist) {
