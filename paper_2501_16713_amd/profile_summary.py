@@ -71,7 +71,7 @@ def stage_of(kernel: str) -> str:
             return "fft_coil_adj_last"
         if "St2Masked" in kernel:
             return "fft_coil_fwd_ax0"
-        if "Ld2Masked" in kernel:
+        if "Ld2Masked" in kernel or "Ld2Tiles" in kernel:
             return "fft_coil_adj_ax0"
         m = re.search(r"fft2_kernel<\d+, \d+, (-?\d+)", kernel)
         return "fft_coil_fwd_ax1" if m and m.group(1).startswith("-") else "fft_coil_adj_ax1"
