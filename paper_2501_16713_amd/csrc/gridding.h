@@ -255,7 +255,10 @@ __host__ __device__ inline size_t warp_spread_lds_bytes(const TileDims& td, int 
 // the tile of its own.  The lanes of one entry cover its 64 taps (distinct
 // points), so plain read-modify-write is race free; out-of-tile taps update
 // garbage slots instead of branching.  The copies are summed at the end in a
-// fixed order (deterministic).
+// fixed order (deterministic).  The global reads of the staging are
+// software-pipelined: a lane's voxel index is read two rounds ahead and its
+// displacement and value one round ahead, so they are in flight while the
+// wave accumulates the current round.
 template <int NDIM>
 __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPhases ph, float2* __restrict__ U,
                                                                    int accumulate, int ntiles, Dims dm,
@@ -266,6 +269,8 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
   __shared__ int4 st_off[kWarpWaves][64];
   __shared__ float4 st_w[kWarpWaves][64][3];
   __shared__ float2 st_v[kWarpWaves][64];
+  __shared__ int s_beg[kMaxPhasesPerLaunch];      // first entry of state p in its voxel list
+  __shared__ int s_pfx[kMaxPhasesPerLaunch + 1];  // entries of the tile over states < p
   const int tile = xcd_contiguous(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
   float2* dump = accw + (size_t)kWarpWaves * Q * td.P;
@@ -289,8 +294,18 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
     for (int e = threadIdx.x; e < n4; e += kGridThreads) a4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   // entries of this tile over all states, concatenated
-  int E = 0;
-  for (int p = 0; p < ph.P; ++p) E += ph.tile_off[p][tile + 1] - ph.tile_off[p][tile];
+  if ((int)threadIdx.x < ph.P) {
+    const int b = ph.tile_off[threadIdx.x][tile];
+    s_beg[threadIdx.x] = b;
+    s_pfx[threadIdx.x + 1] = ph.tile_off[threadIdx.x][tile + 1] - b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_pfx[0] = 0;
+    for (int p = 0; p < ph.P; ++p) s_pfx[p + 1] += s_pfx[p];
+  }
+  __syncthreads();
+  const int E = s_pfx[ph.P];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   // lane roles
@@ -310,24 +325,45 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
   float2* mydump = dump + lane;  // slot j at mydump[64 j]
   const int nbatch = (E + 63) / 64;
   const int rounds = (nbatch + kWarpWaves - 1) / kWarpWaves;
+  // the entry this lane stages in round rd: its state and voxel (-1: none)
+  auto voxel_of = [&](int rd, int& p) -> int {
+    const int e = (rd * kWarpWaves + wave) * 64 + lane;
+    p = 0;
+    if (rd >= rounds || e >= E) return -1;
+    while (e >= s_pfx[p + 1]) ++p;
+    return ph.vox[p][s_beg[p] + (e - s_pfx[p])];
+  };
+  float dn[NDIM];  // next round's displacement and value
+  float2 vn = make_float2(0.f, 0.f);
+  auto data_of = [&](int r, int p) {
+    if (r < 0) return;
+#pragma unroll
+    for (int i = 0; i < NDIM; ++i) dn[i] = ph.d[p][(int64_t)i * dm.N + r];
+    vn = ph.w[p][r];
+  };
+#pragma unroll
+  for (int i = 0; i < NDIM; ++i) dn[i] = 0.f;
+  int pn, p2;
+  int rn = voxel_of(0, pn);  // round 0
+  data_of(rn, pn);
+  int r2 = voxel_of(1, p2);  // round 1
   for (int rd = 0; rd < rounds; ++rd) {
     const int b = rd * kWarpWaves + wave;
     const int e0 = b * 64;
     const int ne = max(0, min(64, E - e0));
+    const int r = rn;
+    float dc[NDIM];
+#pragma unroll
+    for (int i = 0; i < NDIM; ++i) dc[i] = dn[i];
+    const float2 vc = vn;
     __syncthreads();  // accumulators zeroed / this wave's previous batch consumed
     if (lane < ne) {  // stage entry e0 + lane
-      int e = e0 + lane, p = 0;
-      while (e >= ph.tile_off[p][tile + 1] - ph.tile_off[p][tile]) {
-        e -= ph.tile_off[p][tile + 1] - ph.tile_off[p][tile];
-        ++p;
-      }
-      const int64_t r = ph.vox[p][ph.tile_off[p][tile] + e];
       int ri[3];
       voxel_coords<NDIM>(r, dm, ri);
       int off[3] = {0, 0, 0};
 #pragma unroll
       for (int i = 0; i < NDIM; ++i) {
-        const float yv = 2.0f * ph.d[p][(int64_t)i * dm.N + r];
+        const float yv = 2.0f * dc[i];
         const float fl = floorf(yv);
         float w[4];
         kb_weights(kb, yv - fl, w);
@@ -338,9 +374,14 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
         off[i] = o;
       }
       st_off[wave][lane] = make_int4(off[0], off[1], off[2], 0);
-      st_v[wave][lane] = ph.w[p][r];
+      st_v[wave][lane] = vc;
     }
     __syncthreads();
+    // reads for the next rounds, in flight during this round's accumulation
+    rn = r2;
+    pn = p2;
+    data_of(rn, pn);
+    r2 = voxel_of(rd + 2, p2);
     for (int s = 0; s < ne; s += Q) {
       const int sq = s + q;
       const bool has = sq < ne;
