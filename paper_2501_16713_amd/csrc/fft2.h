@@ -343,6 +343,17 @@ struct St2Rows {
   }
 };
 
+// Load of one element that reads as zero when `on` is false.  The load is
+// issued either way (from `dummy`, any valid address, when off) and the
+// result selected afterwards: a skipped load would sit in a branch of its
+// own, and the compiler then waits for every earlier load at each branch
+// join, so the loads of a line would be issued one at a time.
+template <int S>
+__device__ __forceinline__ float2 masked_load(const typename Elem<S>::T* addr, bool on, const float2* dummy) {
+  const float2 v = Elem<S>::load(on ? addr : reinterpret_cast<const typename Elem<S>::T*>(dummy));
+  return on ? v : make_float2(0.f, 0.f);
+}
+
 // Touched-tile masks of a trajectory.  The k-space grid [G0][...][C] is cut
 // into spread tiles; colmask[col] has bit t0 set when some sample's taps
 // touch tile (t0, col), col = (i1 / TS1) nt2 + i2 / TS2 (3D) or i1 / TS1 (2D).
@@ -381,8 +392,8 @@ struct Ld2Masked {
   }
   template <int L>
   __device__ float2 get(const Line& ln, int pos, bool valid) const {
-    if (!valid || !((ln.mask >> (pos >> tm.ts0_log2)) & 1ull)) return make_float2(0.f, 0.f);
-    return Elem<S>::load(ln.base + (int64_t)pos * blk.rs);
+    const bool on = valid && ((ln.mask >> (pos >> tm.ts0_log2)) & 1ull);
+    return masked_load<S>(ln.base + (int64_t)pos * blk.rs, on, tw);
   }
 };
 
@@ -439,9 +450,9 @@ struct Ld2Tiles {
   template <int L>
   __device__ float2 get(const Line& ln, int pos, bool valid) const {
     const int t0 = pos >> ts0_log2;
-    if (!valid || !((ln.mask >> t0) & 1ull)) return make_float2(0.f, 0.f);
+    const bool on = valid && ((ln.mask >> t0) & 1ull);
     const int k = __popcll(ln.mask & ((1ull << t0) - 1ull));
-    return Elem<S>::load(ln.base + (int64_t)k * volC + (int64_t)(pos & ((1 << ts0_log2) - 1)) * rowC);
+    return masked_load<S>(ln.base + (int64_t)k * volC + (int64_t)(pos & ((1 << ts0_log2) - 1)) * rowC, on, tw);
   }
 };
 
@@ -480,9 +491,11 @@ struct Ld2CoilExpand {
   template <int L>
   __device__ float2 get(const Line& ln, int pos, bool valid) const {
     const int j = pad_src<L>(kCentred, pos);
-    if (!valid || j < 0) return make_float2(0.f, 0.f);
+    const bool on = valid && j >= 0;
+    const int jj = on ? j : 0;  // every line's element 0 exists: unconditional loads, no branch
     const float* dl = dx.t[n1 ? 2 : 1];
-    return cscale(cmul(ln.srow[j], ln.mrow[j]), ln.f * dl[j]);
+    const float2 v = cscale(cmul(ln.srow[jj], ln.mrow[jj]), ln.f * dl[jj]);
+    return on ? v : make_float2(0.f, 0.f);
   }
 };
 
