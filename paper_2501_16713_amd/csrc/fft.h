@@ -260,16 +260,31 @@ struct LdStrided {
         lines[l * g.LS + lo + (e - l * gap)] = make_float2(0.f, 0.f);
       }
     }
+    // U elements per thread and round, all loads issued before the LDS
+    // stores (unconditional loads from p itself for out-of-range elements)
+    constexpr int U = 4;
     const int total = nl * n;
-    for (int e = threadIdx.x; e < total; e += kFftThreads) {
-      const int r = (int)nbd.div((uint32_t)e);
-      const int bl = e - r * g.nb;
-      const int al = (int)nd.div((uint32_t)r);
-      const int j = r - al * n;
-      const int64_t a = a0 + al, b = b0 + bl;
-      float2 v = make_float2(0.f, 0.f);
-      if (a < g.A && b < g.B) v = Elem<S>::load(p + a * sa + (int64_t)j * sj + b);
-      lines[(al * g.nb + bl) * g.LS + map_index(map, j, n, L)] = v;
+    for (int e0 = threadIdx.x; e0 < total; e0 += U * kFftThreads) {
+      float2 v[U];
+      int dst[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kFftThreads;
+        const bool in = e < total;
+        const int ee = in ? e : 0;
+        const int r = (int)nbd.div((uint32_t)ee);
+        const int bl = ee - r * g.nb;
+        const int al = (int)nd.div((uint32_t)r);
+        const int j = r - al * n;
+        const int64_t a = a0 + al, b = b0 + bl;
+        const bool ok = in && a < g.A && b < g.B;
+        const float2 x = Elem<S>::load(ok ? p + a * sa + (int64_t)j * sj + b : p);
+        v[u] = ok ? x : make_float2(0.f, 0.f);
+        dst[u] = in ? (al * g.nb + bl) * g.LS + map_index(map, j, n, L) : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (dst[u] >= 0) lines[dst[u]] = v[u];
     }
   }
 };

@@ -261,6 +261,17 @@ __device__ __forceinline__ int pad_src(int map, int p) {
   return p;
 }
 
+// Load of one element that reads as zero when `on` is false.  The load is
+// issued either way (from `dummy`, any valid address, when off) and the
+// result selected afterwards: a skipped load would sit in a branch of its
+// own, and the compiler then waits for every earlier load at each branch
+// join, so the loads of a line would be issued one at a time.
+template <int S>
+__device__ __forceinline__ float2 masked_load(const typename Elem<S>::T* addr, bool on, const float2* dummy) {
+  const float2 v = Elem<S>::load(on ? addr : reinterpret_cast<const typename Elem<S>::T*>(dummy));
+  return on ? v : make_float2(0.f, 0.f);
+}
+
 // strided load of element p of line (a, b): p[a*sa + j*sj + b]; map: dense,
 // or zero-pad of L/2 stored values (centred or spectral)
 template <int S>
@@ -278,8 +289,8 @@ struct Ld2Strided {
   template <int L>
   __device__ float2 get(const Line& ln, int pos, bool valid) const {
     const int j = pad_src<L>(map, pos);
-    if (!valid || j < 0) return make_float2(0.f, 0.f);
-    return Elem<S>::load(ln.base + (int64_t)(j >> tlog) * bs + (int64_t)(j & ((1 << tlog) - 1)) * sj);
+    return masked_load<S>(ln.base + (int64_t)(j >> tlog) * bs + (int64_t)(j & ((1 << tlog) - 1)) * sj,
+                          valid && j >= 0, tw);
   }
 };
 
@@ -297,8 +308,7 @@ struct Ld2Rows {
   template <int L>
   __device__ float2 get(const Line& ln, int pos, bool valid) const {
     const int j = pad_src<L>(map, pos);
-    if (!valid || j < 0) return make_float2(0.f, 0.f);
-    return Elem<S>::load(ln.base + (int64_t)j * blk.rs);
+    return masked_load<S>(ln.base + (int64_t)j * blk.rs, valid && j >= 0, tw);
   }
 };
 
@@ -342,17 +352,6 @@ struct St2Rows {
     if (valid && j >= 0) Elem<S>::store(ln.base + (int64_t)j * blk.rs, store_scaled<S>(v, scale));
   }
 };
-
-// Load of one element that reads as zero when `on` is false.  The load is
-// issued either way (from `dummy`, any valid address, when off) and the
-// result selected afterwards: a skipped load would sit in a branch of its
-// own, and the compiler then waits for every earlier load at each branch
-// join, so the loads of a line would be issued one at a time.
-template <int S>
-__device__ __forceinline__ float2 masked_load(const typename Elem<S>::T* addr, bool on, const float2* dummy) {
-  const float2 v = Elem<S>::load(on ? addr : reinterpret_cast<const typename Elem<S>::T*>(dummy));
-  return on ? v : make_float2(0.f, 0.f);
-}
 
 // Touched-tile masks of a trajectory.  The k-space grid [G0][...][C] is cut
 // into spread tiles; colmask[col] has bit t0 set when some sample's taps

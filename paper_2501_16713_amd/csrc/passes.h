@@ -38,9 +38,11 @@ struct UpMid {
                              int64_t a0, int64_t b0) const {
     constexpr int MAXE = kMaxPerThread;
     float2 v[MAXE];
+    // table reads are unconditional (index 0 for inactive threads) so the
+    // compiler can issue them together instead of one per branch
     float f = scale;
-    if (active) {
-      const int64_t b = b0 + li;  // na == 1 for axis-0 passes
+    {
+      const int64_t b = active ? b0 + li : 0;  // na == 1 for axis-0 passes
       if (three_d) {
         const int i1 = (int)(b / n_inner), i2 = (int)(b - (int64_t)i1 * n_inner);
         f *= tab.t[1][i1] * tab.t[2][i2];
@@ -51,7 +53,8 @@ struct UpMid {
 #pragma unroll
     for (int i = 0; i < MAXE; ++i) {
       const int j = tl + i * tpl;
-      if (active && j < n) v[i] = cscale(line[j], f * tab.t[0][j]);
+      const int jj = active && j < n ? j : 0;
+      v[i] = cscale(line[jj], f * tab.t[0][jj]);  // used only when active && j < n
     }
     __syncthreads();
     if (active) {
@@ -78,9 +81,11 @@ struct UpHMid {
                              int64_t a0, int64_t b0) const {
     constexpr int MAXE = kMaxPerThread;
     float2 v[MAXE];
+    // table reads are unconditional (index 0 for inactive threads) so the
+    // compiler can issue them together instead of one per branch
     float f = scale;
-    if (active) {
-      const int64_t b = b0 + li;
+    {
+      const int64_t b = active ? b0 + li : 0;
       if (three_d) {
         const int i1 = (int)(b / n_inner), i2 = (int)(b - (int64_t)i1 * n_inner);
         f *= tab.t[1][i1] * tab.t[2][i2];
@@ -91,7 +96,8 @@ struct UpHMid {
 #pragma unroll
     for (int i = 0; i < MAXE; ++i) {
       const int j = tl + i * tpl;
-      if (active && j < n) v[i] = cscale(line[j < n / 2 ? j : j + G - n], f * tab.t[0][j]);
+      const int jj = active && j < n ? j : 0;
+      v[i] = cscale(line[jj < n / 2 ? jj : jj + G - n], f * tab.t[0][jj]);  // used only when active && j < n
     }
     __syncthreads();
 #pragma unroll
