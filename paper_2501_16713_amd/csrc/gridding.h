@@ -702,7 +702,8 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
       float w[4];
       kb_weights(kb, tp.f[i], w);
       st_w[sidx][i] = make_float4(w[0], w[1], w[2], w[3]);
-      int o = (int)((tp.base >> (10 * i)) & 1023) - lo[i];  // periodic: the image next to the tile
+      const int loi = i == 0 ? lo[0] : (i == 1 ? lo[1] : lo[2]);  // no runtime index into a register array
+      int o = (int)((tp.base >> (10 * i)) & 1023) - loi;  // periodic: the image next to the tile
       if (o > dm.G[i] / 2) o -= dm.G[i];
       if (o < -dm.G[i] / 2) o += dm.G[i];
       ((int*)&st_off[sidx])[i] = o;
