@@ -473,6 +473,7 @@ struct KBatch {
   int first[kMaxPhasesPerLaunch + 1];
   const KTap* taps[kMaxPhasesPerLaunch];   // gather: taps per sample; spread: taps per visit
   int64_t count[kMaxPhasesPerLaunch];      // gather: samples of the state
+  const int* gorder[kMaxPhasesPerLaunch];  // gather: samples in processing order (null: index order)
   const KUnit* units[kMaxPhasesPerLaunch]; // spread: work units
   const KSplit* splits[kMaxPhasesPerLaunch];
   const int* vis_off[kMaxPhasesPerLaunch]; // gather into visit order: [M + 1] (null: sample order)
@@ -559,6 +560,10 @@ __device__ __forceinline__ float2 gather_one(const typename Elem<S>::T* __restri
 // With vis_off != null the result of sample j is written to every spread
 // visit of the sample (y_visit[v][c] for v in vis[vis_off[j] .. vis_off[j+1]))
 // instead of y[j][c], which lets the spread read its inputs contiguously.
+// Samples are taken in gorder (grouped by spread tile), so the waves working
+// at one time read the same few grid tiles and the grid is fetched from HBM
+// about once instead of once per spoke through it; each result is computed
+// exactly as in index order.
 template <int NDIM, int S>
 __global__ __launch_bounds__(kGridThreads) void kgather_kernel(KBatch<typename Elem<S>::T> bt, int C, Dims dm,
                                                                KbPoly kb) {
@@ -573,9 +578,11 @@ __global__ __launch_bounds__(kGridThreads) void kgather_kernel(KBatch<typename E
   const int sub = lane / C;
   const int c = lane - sub * C;
   const int64_t wave = (int64_t)(blockIdx.x - bt.first[p]) * (kGridThreads / 64) + (threadIdx.x >> 6);
-  const int64_t j = wave * spw + sub;
+  const int64_t jo = wave * spw + sub;
   if (wave * spw >= M) return;  // wavefront-uniform
-  const bool ok = sub < spw && j < M;
+  const bool ok = sub < spw && jo < M;
+  const int* __restrict__ gorder = bt.gorder[p];
+  const int64_t j = ok && gorder ? (int64_t)gorder[jo] : jo;
   float m = 0.f;
   if (ok) {
     const float2 acc = gather_one<NDIM, S>(grid, bt.taps[p][j], bt.blk, c, C, dm, kb, bt.oscale);

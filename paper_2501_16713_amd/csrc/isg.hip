@@ -263,6 +263,7 @@ struct isg_traj {
   int* vis = nullptr;           // ... are vis[vis_off[j] .. vis_off[j + 1])
   KTap* taps = nullptr;
   int* order = nullptr;
+  int* gorder = nullptr;          // [M]: gather processing order, samples grouped by their first spread tile
   KUnit* units = nullptr;
   int nunits = 0;
   KSplit* splits = nullptr;
@@ -1099,6 +1100,7 @@ static void kgather_t(isg_plan* pl, const KJob* jobs, int n, bool to_visits, con
       bt.first[i] = (int)blocks;
       bt.taps[i] = jb.tr->taps;
       bt.count[i] = jb.tr->M;
+      bt.gorder[i] = jb.tr->gorder;
       bt.vis_off[i] = to_visits ? jb.tr->vis_off : nullptr;
       bt.vis[i] = to_visits ? jb.tr->vis : nullptr;
       bt.yout[i] = jb.yout;
@@ -1616,8 +1618,8 @@ static void bin_traj(isg_plan* pl, isg_traj* tr) {
   const std::vector<KTap>& taps = tr->taps_h;
   HIP_OK(hipStreamSynchronize(pl->stream));
   pl->generation++;
-  for (void** q : {(void**)&tr->order, (void**)&tr->colmask, (void**)&tr->colbase, (void**)&tr->taps_v,
-                   (void**)&tr->vis_off, (void**)&tr->vis})
+  for (void** q : {(void**)&tr->order, (void**)&tr->gorder, (void**)&tr->colmask, (void**)&tr->colbase,
+                   (void**)&tr->taps_v, (void**)&tr->vis_off, (void**)&tr->vis})
     traj_free(pl, *q);
   tr->colmask_h.clear();
   tr->colbase_h.clear();
@@ -1670,6 +1672,22 @@ static void bin_traj(isg_plan* pl, isg_traj* tr) {
   }
   tr->order = (int*)dmalloc(pl, sizeof(int) * order.size());
   HIP_OK(hipMemcpy(tr->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
+  {  // gather order: samples by the first tile they visit, index order within a tile
+    std::vector<int> gcnt(ntiles + 1, 0), first(std::max<int64_t>(1, M));
+    for (int64_t j = 0; j < M; ++j) {
+      bool seen = false;
+      visit(j, [&](int t) {
+        if (!seen) first[j] = t;
+        seen = true;
+      });
+      gcnt[first[j] + 1]++;
+    }
+    for (int t = 0; t < ntiles; ++t) gcnt[t + 1] += gcnt[t];
+    std::vector<int> go(std::max<int64_t>(1, M));
+    for (int64_t j = 0; j < M; ++j) go[gcnt[first[j]]++] = (int)j;
+    tr->gorder = (int*)dmalloc(pl, sizeof(int) * go.size());
+    HIP_OK(hipMemcpy(tr->gorder, go.data(), sizeof(int) * go.size(), hipMemcpyHostToDevice));
+  }
   {  // visit-ordered taps and, per sample, the list of its visits
     const int64_t nvis = cnt[ntiles];
     std::vector<KTap> tv(std::max<int64_t>(1, nvis));
@@ -2253,8 +2271,8 @@ isg_status isg_traj_destroy(isg_traj* tr) {
     (void)hipStreamSynchronize(tr->plan->stream);
     tr->plan->generation++;
   }
-  for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->units, (void*)tr->splits, (void*)tr->colmask,
-                  (void*)tr->colbase, (void*)tr->taps_v, (void*)tr->vis_off, (void*)tr->vis})
+  for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->gorder, (void*)tr->units, (void*)tr->splits,
+                  (void*)tr->colmask, (void*)tr->colbase, (void*)tr->taps_v, (void*)tr->vis_off, (void*)tr->vis})
     if (p) (void)hipFree(p);
   delete tr;
   return ISG_OK;
