@@ -219,11 +219,14 @@ def main():
     if per_launch and dom[0] > 0:
         avg_ms = dom[1] / dom[0]
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        copy_gbps = device_copy_gbps(stream)
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": 8000.0,
                     "unit": "GB/s", "frac": round(achieved / 8000.0, 4),
                     "traffic": measured_traffic(dominant, w.name, args.storage),
                     "bytes_per_launch": per_launch, "avg_launch_ms": round(avg_ms, 4),
-                    "launches": dom[0]}
+                    "launches": dom[0],
+                    # the same bandwidth against a plain device copy measured here
+                    "copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4)}
 
     # ---- other forms, for the batched / mixed-precision speedups -------------
     if not args.no_tune:
@@ -279,6 +282,7 @@ def main():
         "config": {"workload": w.name, "shape": list(w.shape), "coils": w.ncoils, "phases": w.nphases,
                    "samples_per_phase": [int(k.shape[0]) for k in inp["k"]], "lambda": lam,
                    "storage": args.storage, "options": opts},
+        "per_state_applies_per_s": round(value * w.nphases, 3),
         "gridding_gpts_per_s": {
             "kspace_point_coil_interps": round(2 * total_samples * w.ncoils * value / 1e9, 4),
             "warp_voxels": round(2 * w.nphases * int(np.prod(w.shape)) * value / 1e9, 4),
@@ -291,6 +295,25 @@ def main():
         "stages_ms": {k: round(v[1], 4) for k, v in sorted(stages.items(), key=lambda kv: -kv[1][1])},
     }
     print(json.dumps(line), flush=True)
+
+
+def device_copy_gbps(stream, mib=1024, reps=5):
+    """HBM bandwidth of a plain device-to-device tensor copy (reads and
+    writes `mib` MiB each), GB/s, timed with events on `stream`"""
+    import torch
+    with torch.cuda.stream(stream):
+        src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        t1.record(stream)
+        t1.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+    del src, dst
+    return 2 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
 def measured_traffic(stage, workload, storage):
