@@ -2521,11 +2521,23 @@ isg_status isg_cg_solve(isg_plan* pl, int P, const void* y, const isg_motion* co
     double* hist = (double*)pl->cg_hist.p;
     float2* xv = (float2*)x;
     const unsigned vb = (unsigned)std::min<int64_t>(kDotBlocks, blocks_for(N, kVecThreads));
-    // r = b - N x0 with b = sum_p A_p^H y_p; p = r; rho = <r, r>
+    // r = b - N x0 with b = sum_p A_p^H y_p; p = r; rho = <r, r>.  For
+    // x0 = 0 (the usual start) N x0 is exactly zero, so r = b without an
+    // application of N: ||x0||^2, read back once, decides.
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, xv, xv, N, pl->cg_part);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb, hist);
+    LAUNCH_OK();
+    double x0_sq = -1.0;
+    HIP_OK(hipMemcpyAsync(&x0_sq, hist, sizeof(double), hipMemcpyDeviceToHost, pl->stream));
+    HIP_OK(hipStreamSynchronize(pl->stream));
     op_sense_adjoint(pl, P, (const float2*)y, d, (const float2*)S, k, pl->cg_p);
-    op_normal(pl, P, xv, lambda, d, (const float2*)S, k, pl->cg_q);
-    hipLaunchKernelGGL(sub_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_p, pl->cg_q, N);
-    hipLaunchKernelGGL(copy_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_r, N);
+    if (x0_sq == 0.0) {
+      hipLaunchKernelGGL(copy_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_p, N);
+    } else {
+      op_normal(pl, P, xv, lambda, d, (const float2*)S, k, pl->cg_q);
+      hipLaunchKernelGGL(sub_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_p, pl->cg_q, N);
+      hipLaunchKernelGGL(copy_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_r, N);
+    }
     hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_r, N,
                        pl->cg_part);
     hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb, pl->cg_sc,

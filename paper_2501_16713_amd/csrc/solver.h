@@ -68,6 +68,13 @@ __global__ __launch_bounds__(kVecThreads) void half_scale_kernel(const double* _
   }
 }
 
+// out[0] = sum(partial)
+__global__ __launch_bounds__(kVecThreads) void sum_partials_kernel(const double* __restrict__ partial, int np,
+                                                                   double* __restrict__ out) {
+  const double s = sum_partials(partial, np);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
 // p[0 .. n) = 0 (a kernel, not a memset node, so graph replays clear it too)
 __global__ void zero_u32_kernel(unsigned* __restrict__ p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;

@@ -216,6 +216,25 @@ def test_cg_solve(isg, lam):
     assert np.max(np.abs(np.array(hist) - ho)) < tol * ho[0]
 
 
+def test_cg_from_nonzero_start(isg):
+    """CG from x0 != 0 (r0 = b - N x0 needs an application of N; from x0 = 0
+    the solver skips it) against the oracle's CG from the same x0"""
+    lam, iters = 0.5, 5
+    tol = _cg_tol(lam, iters)
+    shape, inp, plan, S, mots, trs, y = _cg_problem(isg)
+    g = np.random.default_rng(11)
+    x0 = 0.1 * _rand_c(g, shape)
+    x, hist = plan.cg_solve(to_dev(y), mots, S, trs, lam, iters, x0=to_dev(x0))
+    yo = unpack(y.astype(np.complex128), inp["k"])
+    b = oracle.sense.sense_adjoint(yo, inp["d"], inp["S"], inp["k"], shape)
+    xo, ho = oracle.cg.cg(lambda v: oracle.sense.normal(v, lam, inp["d"], inp["S"], inp["k"]), b, iters,
+                          x0=x0.astype(np.complex128))
+    e = rel(x.cpu().numpy(), xo)
+    say(f"  x0 != 0: iterate rel err {e:.2e}, initial residual {hist[0]:.6e} vs {ho[0]:.6e}")
+    assert e < tol
+    assert abs(hist[0] - ho[0]) < 1e-5 * ho[0]
+
+
 def test_cg_graph_replay_matches_eager(isg, monkeypatch):
     """the HIP-graph replay of a CG iteration equals eager launches"""
     shape, inp, plan, S, mots, trs, y = _cg_problem(isg)
