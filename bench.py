@@ -77,7 +77,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
-              "(the path would shard over (state, coil) units; see DESIGN.md)", file=sys.stderr)
+              "(the path would shard over (state, coil) units of the states)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

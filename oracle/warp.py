@@ -10,7 +10,7 @@ grid, so T is computed like inverse k-space gridding but in image space
   forward (Eq. 9):  F -> 1/C*[k] -> Z -> F^H -> B_d
   adjoint (Eq. 8):  P_d -> F -> Z^H -> 1/C[k] -> F^H
 
-Readings of what the paper leaves open (also listed in the design doc):
+Readings of what the paper leaves open:
 * oversampling alpha = 2, so voxel r sits at grid coordinate alpha*r;
 * F is the unnormalised DFT; the inverse DFT onto the oversampled grid is
   scaled so that u[g] = (1/|N|) sum_k U[k] exp(+2 pi i k.g/G), which makes

@@ -344,9 +344,9 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
 #pragma unroll
   for (int i = 0; i < NDIM; ++i) dn[i] = 0.f;
   int pn, p2;
-  int rn = voxel_of(0, pn);  // round 0
+  int rn = voxel_of(0, pn);  // staging round 0
   data_of(rn, pn);
-  int r2 = voxel_of(1, p2);  // round 1
+  int r2 = voxel_of(1, p2);  // staging round 1
   for (int rd = 0; rd < rounds; ++rd) {
     const int b = rd * kWarpWaves + wave;
     const int e0 = b * 64;

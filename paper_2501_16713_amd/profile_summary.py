@@ -10,8 +10,8 @@ The bench is run with --calib-copy-mb, so each process also launches one
 plain elementwise kernel (a negation) that reads and writes a known number
 of bytes; both counters are scaled by what they read for it.
 
-    python3 -m paper_2501_16713_amd.profile_summary --out gpurun_out/profiles/normal_op_batched_160_fp32 \\
-        --raw gpurun_out/prof_raw -- --steps 3 --warmup 1 --cg-iters 0 --no-cpu-baseline --forms "" \\
+    python3 -m paper_2501_16713_amd.profile_summary --out out/normal_op_batched_160_fp32 \\
+        --raw out/prof_raw -- --steps 3 --warmup 1 --cg-iters 0 --no-cpu-baseline --forms "" \\
         --no-tune --ktile 4 --chunk 1024 --batch 6 --graph 0
 
 writes OUT.md (the table, with the commands) and OUT.json (read by bench.py,
