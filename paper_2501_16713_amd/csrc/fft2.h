@@ -167,9 +167,17 @@ __device__ __forceinline__ int slot(int k1, int n2) {
 // L-point line (zeros outside the stored range); St: per-thread line setup +
 // element stores (positions outside a crop are skipped).  St may also request
 // an LDS epilogue (coil reduction) through St::kEpilogue.
-template <int L1, int L2, int S, int MAP1, int MAP2, class Ld, class St>
+// GAP bit 0: the loads zero-pad L/2 stored values, so positions [L/4, 3L/4)
+// are zero; bit 1: the stores crop to L/2 values, so those positions are not
+// stored.  With L1 (L2) a multiple of 4 the gap is the same step-1 inputs
+// n1 in [L1/4, 3L1/4) (step-2 outputs k2 in [L2/4, 3L2/4)) for every thread:
+// those loads are not issued, and the outputs that are never stored are not
+// computed (dead code).
+template <int L1, int L2, int S, int MAP1, int MAP2, class Ld, class St, int GAP = 0>
 __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
   constexpr int L = L1 * L2;
+  constexpr bool kGapIn = (GAP & 1) && L1 % 4 == 0;
+  constexpr bool kGapOut = (GAP & 2) && L2 % 4 == 0;
   extern __shared__ float2 smem[];
   float2* tw = smem;           // exp(-2 pi i q / L)
   float2* lines = smem + L;
@@ -202,7 +210,9 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
     const bool valid = a < g.A && b < g.B;
     auto line = ld.setup(a, b, valid);
 #pragma unroll
-    for (int n1 = 0; n1 < L1; ++n1) v[n1] = ld.template get<L>(line, L2 * n1 + n2, valid);
+    for (int n1 = 0; n1 < L1; ++n1)
+      v[n1] = (kGapIn && n1 >= L1 / 4 && n1 < 3 * L1 / 4) ? make_float2(0.f, 0.f)
+                                                          : ld.template get<L>(line, L2 * n1 + n2, valid);
     reg_dft<L1, S>(v);
   }
   __syncthreads();  // twiddle table in LDS
@@ -234,7 +244,8 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
     if (act2) {
       float2* dstl = lines + (al2 * g.nb + bl2) * g.LS;
 #pragma unroll
-      for (int k2 = 0; k2 < L2; ++k2) dstl[k1 + L1 * k2] = u[k2];
+      for (int k2 = 0; k2 < L2; ++k2)
+        if (!(kGapOut && k2 >= L2 / 4 && k2 < 3 * L2 / 4)) dstl[k1 + L1 * k2] = u[k2];
     }
     __syncthreads();
     st.epilogue(lines, g, a0, b0);
@@ -244,7 +255,8 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
       const bool valid = a < g.A && b < g.B;
       auto line = st.setup(a, b, valid);
 #pragma unroll
-      for (int k2 = 0; k2 < L2; ++k2) st.template put<L>(line, k1 + L1 * k2, u[k2], valid);
+      for (int k2 = 0; k2 < L2; ++k2)
+        if (!(kGapOut && k2 >= L2 / 4 && k2 < 3 * L2 / 4)) st.template put<L>(line, k1 + L1 * k2, u[k2], valid);
     }
   }
 }
@@ -352,6 +364,20 @@ struct St2Rows {
     if (valid && j >= 0) Elem<S>::store(ln.base + (int64_t)j * blk.rs, store_scaled<S>(v, scale));
   }
 };
+
+// Whether a loader zero-pads (a store crops) L/2 stored values of every line,
+// i.e. positions [L/4, 3L/4) are zero (not stored): checked on the host
+// before a kernel is launched with the corresponding GAP bit.
+template <class T>
+inline bool half_gap(const T&, int) { return false; }
+template <int S>
+inline bool half_gap(const Ld2Strided<S>& x, int) { return x.map == kCentred || x.map == kSpectral; }
+template <int S>
+inline bool half_gap(const Ld2Rows<S>& x, int) { return x.map == kCentred || x.map == kSpectral; }
+template <int S>
+inline bool half_gap(const St2Strided<S>& x, int) { return x.map == kCentred || x.map == kSpectral; }
+template <int S>
+inline bool half_gap(const St2Rows<S>& x, int) { return x.map == kCentred || x.map == kSpectral; }
 
 // Touched-tile masks of a trajectory.  The k-space grid [G0][...][C] is cut
 // into spread tiles; colmask[col] has bit t0 set when some sample's taps
@@ -535,5 +561,9 @@ struct St2CoilReduce {
     }
   }
 };
+
+// the coil expansion always zero-pads (centred), the coil reduction crops
+inline bool half_gap(const Ld2CoilExpand& x, int L) { return 2 * x.n == L; }
+inline bool half_gap(const St2CoilReduce& x, int L) { return 2 * x.n == L; }
 
 }  // namespace isg

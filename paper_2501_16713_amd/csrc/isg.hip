@@ -458,7 +458,7 @@ static Tile2 make_tile2(int64_t A, int64_t B, int L, int nb_fixed) {
   return g;
 }
 
-template <int L1, int L2, int SG, int M1, int M2, class Ld, class St>
+template <int L1, int L2, int SG, int M1, int M2, int GAP, class Ld, class St>
 static void launch_fft2(isg_plan* pl, const char* tag, const Ld& ld, const St& st, const Tile2& g) {
   constexpr int L = L1 * L2;
   const int nl = g.na * g.nb;
@@ -466,7 +466,9 @@ static void launch_fft2(isg_plan* pl, const char* tag, const Ld& ld, const St& s
   if (threads > 512 || nl * L1 > threads)
     throw HipError{hipErrorInvalidConfiguration, "fft2 tile does not fit one workgroup"};
   const size_t lds = sizeof(float2) * ((size_t)L + (size_t)nl * g.LS);
-  auto kern = fft2_kernel<L1, L2, SG, M1, M2, Ld, St>;
+  if (((GAP & 1) && !half_gap(ld, L)) || ((GAP & 2) && !half_gap(st, L)))
+    throw HipError{hipErrorInvalidConfiguration, "fft2 gap flags do not match the line maps"};
+  auto kern = fft2_kernel<L1, L2, SG, M1, M2, Ld, St, GAP>;
   allow_lds(kern, lds);
   const int64_t tiles = ((g.A + g.na - 1) / g.na) * g.tiles_b;
   Tile2 gl = g;
@@ -485,21 +487,21 @@ static void launch_fft2(isg_plan* pl, const char* tag, const Ld& ld, const St& s
   LAUNCH_OK();
 }
 
-template <int SG, int M1, int M2, class Ld, class St>
+template <int SG, int M1, int M2, int GAP = 0, class Ld, class St>
 static void run_fft2(isg_plan* pl, const char* tag, int L, const Ld& ld, const St& st, const Tile2& g) {
   switch (L) {
-    case 32: launch_fft2<4, 8, SG, M1, M2>(pl, tag, ld, st, g); break;
-    case 40: launch_fft2<5, 8, SG, M1, M2>(pl, tag, ld, st, g); break;
-    case 48: launch_fft2<6, 8, SG, M1, M2>(pl, tag, ld, st, g); break;
-    case 64: launch_fft2<8, 8, SG, M1, M2>(pl, tag, ld, st, g); break;
-    case 80: launch_fft2<8, 10, SG, M1, M2>(pl, tag, ld, st, g); break;
-    case 96: launch_fft2<8, 12, SG, M1, M2>(pl, tag, ld, st, g); break;
-    case 128: launch_fft2<8, 16, SG, M1, M2>(pl, tag, ld, st, g); break;
-    case 160: launch_fft2<10, 16, SG, M1, M2>(pl, tag, ld, st, g); break;
-    case 192: launch_fft2<12, 16, SG, M1, M2>(pl, tag, ld, st, g); break;
-    case 256: launch_fft2<16, 16, SG, M1, M2>(pl, tag, ld, st, g); break;
-    case 320: launch_fft2<16, 20, SG, M1, M2>(pl, tag, ld, st, g); break;
-    case 512: launch_fft2<16, 32, SG, M1, M2>(pl, tag, ld, st, g); break;
+    case 32: launch_fft2<4, 8, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 40: launch_fft2<5, 8, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 48: launch_fft2<6, 8, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 64: launch_fft2<8, 8, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 80: launch_fft2<8, 10, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 96: launch_fft2<8, 12, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 128: launch_fft2<8, 16, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 160: launch_fft2<10, 16, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 192: launch_fft2<12, 16, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 256: launch_fft2<16, 16, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 320: launch_fft2<16, 20, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 512: launch_fft2<16, 32, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
     default: throw HipError{hipErrorInvalidValue, "fft2: unsupported length"};
   }
 }
@@ -896,22 +898,22 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
   const float scale = image_end_scale(pl);
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
     // S_c m / c(x/G) |N|^{-1/2}, centred pad, F along axis 2
-    run_fft2<-1, kJFast, kBFast>(pl, "fft_coil_fwd_last", G2, ld2_expand(pl, m, Sm, n2, n1, G2),
+    run_fft2<-1, kJFast, kBFast, 1>(pl, "fft_coil_fwd_last", G2, ld2_expand(pl, m, Sm, n2, n1, G2),
                                  st2<S>(pl->k1buf, (int64_t)G2 * C, C, kDense),
                                  make_tile2((int64_t)n0 * n1, C, G2, C));
     // centred pad, F along axis 1 (into the row-blocked k2buf)
-    run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax1", G1,
+    run_fft2<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax1", G1,
                                  ld2<S>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
                                  st2_axis1<S>(pl->k2buf, pl->blk_k2, kDense, axis_store_scale(pl, 1)),
                                  xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
     // centred pad, F along axis 0
-    run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0, ld2_rows<S>(pl, pl->k2buf, pl->blk_k2, kCentred, G0),
+    run_fft2<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2_rows<S>(pl, pl->k2buf, pl->blk_k2, kCentred, G0),
                                  st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), axis_store_scale(pl, 0)),
                                  make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
-    run_fft2<-1, kJFast, kBFast>(pl, "fft_coil_fwd_last", G1, ld2_expand(pl, m, Sm, n1, 0, G1),
+    run_fft2<-1, kJFast, kBFast, 1>(pl, "fft_coil_fwd_last", G1, ld2_expand(pl, m, Sm, n1, 0, G1),
                                  st2<S>(pl->k1buf, (int64_t)G1 * C, C, kDense), make_tile2(n0, C, G1, C));
-    run_fft2<-1, kBFast, kBFast>(pl, "fft_coil_fwd_ax0", G0, ld2<S>(pl, pl->k1buf, 0, (int64_t)G1 * C, kCentred, G0),
+    run_fft2<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2<S>(pl, pl->k1buf, 0, (int64_t)G1 * C, kCentred, G0),
                                  st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), axis_store_scale(pl, 0)),
                                  make_tile2(1, (int64_t)G1 * C, G0, 0));
   } else if (pl->ndim == 3) {
@@ -985,26 +987,26 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
   const float scale = image_end_scale(pl);
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
     if (tr && tiled_adjoint(pl))  // spread output tile-major (touched tiles only)
-      run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2_tiles<S>(pl, grid, tr, G0),
+      run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0, ld2_tiles<S>(pl, grid, tr, G0),
                                    st2_rows<S>(pl->k2buf, pl->blk_k2, kCentred, axis_store_scale(pl, 0)),
                                    make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
     else
-      run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0,
-                                   ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
+      run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0,
+                                      ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
                                    st2_rows<S>(pl->k2buf, pl->blk_k2, kCentred, axis_store_scale(pl, 0)),
                                    make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
-    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax1", G1,
+    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax1", G1,
                                  ld2_axis1<S>(pl, pl->k2buf, pl->blk_k2, kDense, G1),
                                  st2<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred,
                                         axis_store_scale(pl, 1)),
                                  xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
-    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G2, ld2<S>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
+    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_last", G2, ld2<S>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
                                  st2_reduce(pl, w, Sm, n2, n1, G2, undo), make_tile2((int64_t)n0 * n1, C, G2, C));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
-    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_ax0", G0, ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
+    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0, ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
                                  st2<S>(pl->k1buf, 0, (int64_t)G1 * C, kCentred, axis_store_scale(pl, 0)),
                                  make_tile2(1, (int64_t)G1 * C, G0, 0));
-    run_fft2<+1, kBFast, kBFast>(pl, "fft_coil_adj_last", G1, ld2<S>(pl, pl->k1buf, (int64_t)G1 * C, C, kDense, G1),
+    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_last", G1, ld2<S>(pl, pl->k1buf, (int64_t)G1 * C, C, kDense, G1),
                                  st2_reduce(pl, w, Sm, n1, 0, G1, undo), make_tile2(n0, C, G1, C));
   } else if (pl->ndim == 3) {
     {  // F^H along axis 0, centred crop
