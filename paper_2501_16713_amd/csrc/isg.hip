@@ -1400,7 +1400,8 @@ static int iwrap(int64_t g, int G) {
   return (int)(r < 0 ? r + G : r);
 }
 
-// tiles (along one axis) touched by taps b..b+3 (mod G) with tile size TS
+// tiles (along one axis) touched by taps b..b+3 (mod G) with tile size TS;
+// TS >= kWidth (or TS = G), so the taps reach at most two tiles
 static int axis_tiles(int b, int G, int TS, int out[2]) {
   const int t0 = b / TS;
   const int e = b + kWidth - 1;
@@ -1482,6 +1483,9 @@ static void set_ktile(isg_plan* pl, int t1) {
     const int ts[2] = {16, t1};
     for (int i = 0; i < 2; ++i) pl->ktile.TS[i] = std::min(ts[i], pl->G[i]);
   }
+  for (int i = 0; i < pl->ndim; ++i)  // tap runs reach at most two tiles per axis (axis_tiles)
+    if (pl->ktile.TS[i] < kWidth && pl->ktile.TS[i] < pl->G[i])
+      throw HipError{hipErrorInvalidConfiguration, "k-space tiles narrower than the kernel"};
   pl->ktile.vol = 1;
   for (int i = 0; i < pl->ndim; ++i) {
     pl->ktile.nt[i] = (pl->G[i] + pl->ktile.TS[i] - 1) / pl->ktile.TS[i];
@@ -2109,9 +2113,9 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
     while (P % 16 != 4) ++P;
     pl->wtile.P = P;
   }
-  set_ktile(pl, pl->ndim == 3 ? 8 : 16);
-  set_layouts(pl);
   isg_status st = guarded(pl, [&]() -> isg_status {
+    set_ktile(pl, pl->ndim == 3 ? 8 : 16);
+    set_layouts(pl);
     HIP_OK(hipGetDevice(&pl->device));
     HIP_OK(hipDeviceGetAttribute(&pl->ncu, hipDeviceAttributeMultiprocessorCount, pl->device));
     // deapodization tables
