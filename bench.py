@@ -337,41 +337,60 @@ def measured_traffic(stage, workload, storage):
 def cpu_baseline(inp, w, log):
     """The FP64 oracle timed on this host on a bounded sample of the same
     workload, scaled to applies/s.  One apply is P x (T + T^H) plus
-    P x C coil units (G_p then G_p^H); the sample times one coil unit of
-    state 0 and the warp pair of state 0 on 1/32 of the voxels, whose FFT
-    part (the upsampling of the whole image) is timed separately."""
+    P x C coil units (G_p then G_p^H).  The sample, all of state 0:
+    * one coil unit, whole;
+    * the upsampling FFTs of T, whole; the FFTs of T^H are the same
+      transforms in reverse order and are taken to cost the same;
+    * the warp gather on 1/32 of the voxels, scaled by 32;
+    * the warp spread on the same 1/32 of the voxels, scaled by 32 after
+      subtracting its fixed part (the per-tap sums over the whole grid),
+      which is timed on its own with no points."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     import oracle
 
-    cores = 1  # the sampled oracle steps (pocketfft, bincount, elementwise numpy) run on one thread
+    # scipy.fft with workers=-1 (the oracle's FFTs) starts os.cpu_count()
+    # threads; everything else in the sampled steps runs on one thread
+    cores = os.cpu_count() or 1
     x = inp["x"].astype(np.complex128)
     d, k, S = inp["d"][0], inp["k"][0], inp["S"]
     shape = w.shape
+    gshape = oracle.warp.oversampled_shape(shape)
     nvox = int(np.prod(shape))
     sub = np.arange(0, nvox, 32)
     with threadpool_limits(limits=1):
         t = time.time()
         u = oracle.warp.upsample(x)
         t_up = time.time() - t
+        coords = oracle.warp.warp_coords(d)
         t = time.time()
-        oracle.grid.gather(u, oracle.warp.warp_coords(d)[sub])
+        v = oracle.grid.gather(u, coords[sub])
         t_gather_sub = time.time() - t
+        t = time.time()
+        oracle.grid.spread(v[:0], coords[:0], gshape)
+        t_spread_fixed = time.time() - t
+        t = time.time()
+        oracle.grid.spread(v, coords[sub], gshape)
+        t_spread_sub = time.time() - t
         t = time.time()
         yk = oracle.kspace.nufft_forward(S[0].astype(np.complex128) * x, k)
         oracle.kspace.nufft_adjoint(yk, k, shape)
         t_coil = time.time() - t
-    # T ~ upsample + gather; T^H ~ spread + same FFT work: taken equal to T
     t_warp = t_up + 32 * t_gather_sub
-    per_apply = w.nphases * 2 * t_warp + w.nphases * w.ncoils * t_coil
-    log(f"oracle sample: upsample {t_up:.1f}s, gather 1/32 {t_gather_sub:.1f}s, coil unit {t_coil:.1f}s "
+    t_spread = t_spread_fixed + 32 * max(0.0, t_spread_sub - t_spread_fixed)
+    t_warp_adj = t_up + t_spread
+    per_apply = w.nphases * (t_warp + t_warp_adj) + w.nphases * w.ncoils * t_coil
+    sampled = t_up + t_gather_sub + t_spread_fixed + t_spread_sub + t_coil
+    log(f"oracle sample ({sampled:.1f}s): upsample {t_up:.1f}s, gather 1/32 {t_gather_sub:.1f}s, "
+        f"spread fixed {t_spread_fixed:.1f}s, spread 1/32 {t_spread_sub:.1f}s, coil unit {t_coil:.1f}s "
         f"-> {per_apply:.0f}s per apply")
-    return {"value": round(1.0 / per_apply, 6), "unit": "applies/s", "cores": cores, "kind": "oracle",
-            "sample": (f"FP64 oracle, state 0: one coil's G then G^H ({t_coil:.1f}s), the upsampling FFTs "
-                       f"({t_up:.1f}s) and the warp gather on 1/32 of the voxels ({t_gather_sub:.1f}s); "
-                       f"scaled to {w.nphases} states x {w.ncoils} coils with T^H taken equal to T "
-                       f"-> {per_apply:.0f}s per apply")}
-
+    return {"value": float(f"{1.0 / per_apply:.4g}"), "unit": "applies/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle, state 0, {sampled:.0f}s timed: one coil's G then G^H ({t_coil:.1f}s), "
+                       f"the upsampling FFTs ({t_up:.1f}s, also taken for the FFTs of T^H), the warp gather "
+                       f"on 1/32 of the voxels ({t_gather_sub:.1f}s) and the warp spread on the same voxels "
+                       f"({t_spread_sub:.1f}s, of which a fixed {t_spread_fixed:.1f}s measured with no points); "
+                       f"scaled to {w.nphases} states x {w.ncoils} coils -> {per_apply:.0f}s per apply; "
+                       f"FFTs on {cores} threads (scipy workers=-1), the rest on one")}
 
 if __name__ == "__main__":
     main()
