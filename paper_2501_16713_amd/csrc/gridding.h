@@ -267,10 +267,20 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
   constexpr int Q = WL::kCopies;
   extern __shared__ float2 accw[];  // [kWarpWaves][Q][P], then [kWarpDump] garbage
   __shared__ int4 st_off[kWarpWaves][64];
-  __shared__ float4 st_w[kWarpWaves][64][3];
+  __shared__ float st_w[kWarpWaves][64 * 12];  // entry s: weights of axis i at 12 s + 4 i + t
   __shared__ float2 st_v[kWarpWaves][64];
   __shared__ int s_beg[kMaxPhasesPerLaunch];      // first entry of state p in its voxel list
   __shared__ int s_pfx[kMaxPhasesPerLaunch + 1];  // entries of the tile over states < p
+  // per-state pointers in LDS: indexing the kernel arguments by a runtime
+  // state would read them from memory in line with the staging loads, and
+  // waiting for such a read waits for every load issued before it
+  // (held as global-address-space pointers, so the loads through them are
+  // global loads and not flat ones, which the LDS waits would also wait for)
+  typedef const __attribute__((address_space(1))) int* GInt;
+  typedef const __attribute__((address_space(1))) float* GFloat;
+  __shared__ GInt s_vox[kMaxPhasesPerLaunch];
+  __shared__ GFloat s_d[kMaxPhasesPerLaunch];
+  __shared__ GFloat s_w[kMaxPhasesPerLaunch];  // complex values as (re, im) pairs
   const int tile = xcd_contiguous(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
   float2* dump = accw + (size_t)kWarpWaves * Q * td.P;
@@ -298,6 +308,9 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
     const int b = ph.tile_off[threadIdx.x][tile];
     s_beg[threadIdx.x] = b;
     s_pfx[threadIdx.x + 1] = ph.tile_off[threadIdx.x][tile + 1] - b;
+    s_vox[threadIdx.x] = (GInt)ph.vox[threadIdx.x];
+    s_d[threadIdx.x] = (GFloat)ph.d[threadIdx.x];
+    s_w[threadIdx.x] = (GFloat)ph.w[threadIdx.x];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -331,15 +344,17 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
     p = 0;
     if (rd >= rounds || e >= E) return -1;
     while (e >= s_pfx[p + 1]) ++p;
-    return ph.vox[p][s_beg[p] + (e - s_pfx[p])];
+    return s_vox[p][s_beg[p] + (e - s_pfx[p])];
   };
   float dn[NDIM];  // next round's displacement and value
   float2 vn = make_float2(0.f, 0.f);
   auto data_of = [&](int r, int p) {
     if (r < 0) return;
+    const GFloat dp = s_d[p];
 #pragma unroll
-    for (int i = 0; i < NDIM; ++i) dn[i] = ph.d[p][(int64_t)i * dm.N + r];
-    vn = ph.w[p][r];
+    for (int i = 0; i < NDIM; ++i) dn[i] = dp[(int64_t)i * dm.N + r];
+    const GFloat wp = s_w[p] + 2 * (int64_t)r;
+    vn = make_float2(wp[0], wp[1]);
   };
 #pragma unroll
   for (int i = 0; i < NDIM; ++i) dn[i] = 0.f;
@@ -367,7 +382,8 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
         const float fl = floorf(yv);
         float w[4];
         kb_weights(kb, yv - fl, w);
-        st_w[wave][lane][i] = make_float4(w[0], w[1], w[2], w[3]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) st_w[wave][12 * lane + 4 * i + t] = w[t];
         int o = wrap(2 * ri[i] + (int)fl - 1, dm.G[i], dm.invG[i]) - lo[i];  // nearest periodic image
         if (o > dm.G[i] / 2) o -= dm.G[i];
         if (o < -dm.G[i] / 2) o += dm.G[i];
@@ -391,9 +407,11 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
       if constexpr (NDIM == 3) {
         const int l1 = of.y + tb, l2 = of.z + ta;
         const bool ok12 = has && (unsigned)l1 < (unsigned)ext[1] && (unsigned)l2 < (unsigned)ext[2];
-        const float w12 = ((const float*)&st_w[wave][sc][1])[tb] * ((const float*)&st_w[wave][sc][2])[ta];
-        const float* w0 = (const float*)&st_w[wave][sc][0];
-        const int base = l1 * td.S1 + l2;
+        // 24-bit products keep the LDS address arithmetic in 32-bit ALU ops
+        // (out-of-tile offsets give unused addresses; the garbage slot is taken)
+        const int wi = __mul24(sc, 12);
+        const float w12 = st_w[wave][wi + 4 + tb] * st_w[wave][wi + 8 + ta];
+        const int base = __mul24(l1, td.S1) + l2;
         float2* ptr[2];
         float2 a[2];
         float wt[2];
@@ -401,8 +419,8 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
         for (int j = 0; j < 2; ++j) {
           const int l0 = of.x + t0a + j;
           const bool ok = ok12 && (unsigned)l0 < (unsigned)ext[0];
-          ptr[j] = ok ? copy + (l0 * td.S0 + base) : mydump + 64 * j;
-          wt[j] = w12 * w0[t0a + j];
+          ptr[j] = ok ? copy + (__mul24(l0, td.S0) + base) : mydump + 64 * j;
+          wt[j] = w12 * st_w[wave][wi + t0a + j];
           a[j] = *ptr[j];
         }
 #pragma unroll
@@ -410,8 +428,9 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
       } else {
         const int l0 = of.x + t0a, l1 = of.y + ta;
         const bool ok = has && (unsigned)l0 < (unsigned)ext[0] && (unsigned)l1 < (unsigned)ext[1];
-        const float ww = ((const float*)&st_w[wave][sc][0])[t0a] * ((const float*)&st_w[wave][sc][1])[ta];
-        float2* pt = ok ? copy + (l0 * td.S0 + l1) : mydump;
+        const int wi = __mul24(sc, 12);
+        const float ww = st_w[wave][wi + t0a] * st_w[wave][wi + 4 + ta];
+        float2* pt = ok ? copy + (__mul24(l0, td.S0) + l1) : mydump;
         const float2 a = *pt;
         *pt = make_float2(fmaf(ww, v.x, a.x), fmaf(ww, v.y, a.y));
       }
@@ -462,6 +481,18 @@ struct KTap {
   float f[3];
   uint32_t base;  // b0 | b1 << 10 | b2 << 20
 };
+// a tap record in one 16-byte load (field by field, the loads of later
+// fields can be sunk past the branches of the weight evaluation and are then
+// waited for one at a time)
+__device__ __forceinline__ KTap ktap_load(const KTap* p) {
+  const uint4 q = *reinterpret_cast<const uint4*>(p);
+  KTap t;
+  t.f[0] = __uint_as_float(q.x);
+  t.f[1] = __uint_as_float(q.y);
+  t.f[2] = __uint_as_float(q.z);
+  t.base = q.w;
+  return t;
+}
 
 // k-space interpolation work of up to kMaxPhasesPerLaunch states in one
 // launch (each state has its own trajectory and its own grid): blocks
@@ -585,7 +616,7 @@ __global__ __launch_bounds__(kGridThreads) void kgather_kernel(KBatch<typename E
   const int64_t j = ok && gorder ? (int64_t)gorder[jo] : jo;
   float m = 0.f;
   if (ok) {
-    const float2 acc = gather_one<NDIM, S>(grid, bt.taps[p][j], bt.blk, c, C, dm, kb, bt.oscale);
+    const float2 acc = gather_one<NDIM, S>(grid, ktap_load(bt.taps[p] + j), bt.blk, c, C, dm, kb, bt.oscale);
     m = fmaxf(fabsf(acc.x), fabsf(acc.y));
     if (vis_off) {
       const int v1 = vis_off[j + 1];
@@ -653,8 +684,9 @@ __host__ __device__ inline size_t kspread_lds_bytes(const KTile& kt, int C) {
 
 // k-space spread of one work unit, without atomics.  The unit's samples are
 // staged in LDS in batches of kSpreadBatch (tap offsets relative to the tile,
-// tap weights, the C coil values); staging work is spread over every thread,
-// one (sample, axis) pair each.  Wave w owns coils 4w .. 4w+3 (their planes
+// tap weights, the C coil values); thread s stages sample s, and the loads
+// of the next batch are in flight while the current one is accumulated.
+// Wave w owns coils 4w .. 4w+3 (their planes
 // are its alone); in 3D its 64 lanes are (coil, t2, t1) and each lane
 // applies the sample's four t0 taps, in 2D the lanes are (coil, t1, t0).
 // Within a wave every lane updates distinct points, so plain LDS
@@ -696,26 +728,48 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
   float2* plane = acc + (size_t)cr * kt.P;
   float2* mydump = dump + lane;  // slot t at mydump[64 t]
 
+  // The staging is software-pipelined: the coil values and tap records of
+  // the next batch are loaded into registers while the current one is
+  // accumulated.  nthr = 64 ceil(C/4) >= 16 C, so a batch holds at most
+  // kSpreadBatch C / nthr <= 4 coil values per thread.  Addresses are clamped
+  // into the batch (always valid), so the loads need no branch.
+  constexpr int kYRegs = kSpreadBatch / 16;
+  float2 yr[kYRegs];
+  KTap tr;
+  auto fetch = [&](int b0) {
+    const int nb = min(kSpreadBatch, un.count - b0);
+    const float2* src = yv + (int64_t)(un.start + b0) * C;
+    const int ny = nb * C;
+#pragma unroll
+    for (int k = 0; k < kYRegs; ++k) yr[k] = src[min((int)threadIdx.x + k * nthr, ny - 1)];
+    tr = ktap_load(taps_v + un.start + b0 + min((int)threadIdx.x, nb - 1));
+  };
+  fetch(0);
   for (int b0 = 0; b0 < un.count; b0 += kSpreadBatch) {
     const int nb = min(kSpreadBatch, un.count - b0);
     __syncthreads();  // previous batch consumed (and the accumulator zeroed)
-    {
-      const float2* src = yv + (int64_t)(un.start + b0) * C;
-      for (int e = threadIdx.x; e < nb * C; e += nthr) st_y[e] = src[e];
+#pragma unroll
+    for (int k = 0; k < kYRegs; ++k) {
+      const int e = (int)threadIdx.x + k * nthr;
+      if (e < nb * C) st_y[e] = yr[k];
     }
-    for (int e = threadIdx.x; e < nb * NDIM; e += nthr) {
-      const int sidx = e / NDIM, i = e - sidx * NDIM;
-      const KTap tp = taps_v[un.start + b0 + sidx];
-      float w[4];
-      kb_weights(kb, tp.f[i], w);
-      st_w[sidx][i] = make_float4(w[0], w[1], w[2], w[3]);
-      const int loi = i == 0 ? lo[0] : (i == 1 ? lo[1] : lo[2]);  // no runtime index into a register array
-      int o = (int)((tp.base >> (10 * i)) & 1023) - loi;  // periodic: the image next to the tile
-      if (o > dm.G[i] / 2) o -= dm.G[i];
-      if (o < -dm.G[i] / 2) o += dm.G[i];
-      ((int*)&st_off[sidx])[i] = o;
+    if ((int)threadIdx.x < nb) {  // thread s stages sample s: per-axis weights and tap-0 offsets
+      int off[3] = {0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < NDIM; ++i) {
+        float w[4];
+        kb_weights(kb, tr.f[i], w);
+        st_w[threadIdx.x][i] = make_float4(w[0], w[1], w[2], w[3]);
+        int o = (int)((tr.base >> (10 * i)) & 1023) - lo[i];  // periodic: the image next to the tile
+        if (o > dm.G[i] / 2) o -= dm.G[i];
+        if (o < -dm.G[i] / 2) o += dm.G[i];
+        off[i] = o;
+      }
+      st_off[threadIdx.x] = make_int4(off[0], off[1], off[2], 0);
     }
     __syncthreads();
+    // the next batch (the last one again at the end: valid addresses, unused)
+    fetch(b0 + kSpreadBatch < un.count ? b0 + kSpreadBatch : b0);
     // the parameters of sample s + 1 are read before the accumulator update
     // of sample s, so each sample costs one LDS round trip
     int4 of = st_off[0];
