@@ -233,14 +233,19 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n) {
   return (b & 7) * per + (b >> 3);
 }
 
-constexpr int kWarpWaves = kGridThreads / 64;
+// Wavefronts per workgroup and entries a wavefront stages per round.  LDS
+// per wavefront (two tile copies and the staging area) limits a CU to 12 of
+// them; 2 wavefronts staging 32 or 16 entries fit 14 or 16 but were slower
+// (more staging rounds per entry).
+constexpr int kWarpWaves = 4;
+constexpr int kWarpStage = 64;
 // entries a wave applies per step: 3D lanes (entry, t0 half, t1, t2) apply
 // two taps each; 2D lanes (entry, t0, t1) one
 template <int NDIM> struct WarpLanes {
   static constexpr int kCopies = NDIM == 3 ? 2 : 4;
   static constexpr int kTapsPerLane = NDIM == 3 ? 2 : 1;
 };
-constexpr int kWarpDump = 2 * 64;  // garbage slots for out-of-tile taps
+constexpr int kWarpDump = 64;  // garbage slots for out-of-tile taps
 
 __host__ __device__ inline size_t warp_spread_lds_bytes(const TileDims& td, int ndim) {
   const int copies = ndim == 3 ? WarpLanes<3>::kCopies : WarpLanes<2>::kCopies;
@@ -248,9 +253,10 @@ __host__ __device__ inline size_t warp_spread_lds_bytes(const TileDims& td, int 
 }
 
 // Image-space spread of one tile, without atomics.  Entries (state, voxel)
-// of the tile, over all states, are cut into batches of 64; wave w takes
-// batches w, w + 4, ...: the 64 lanes stage one entry each (tap offsets
-// relative to the tile, weights, value) in the wave's LDS staging area, then
+// of the tile, over all states, are cut into batches of kWarpStage; wave w
+// takes batches w, w + kWarpWaves, ...: its first kWarpStage lanes stage one
+// entry each (tap offsets relative to the tile, weights, value) in the
+// wave's LDS staging area, then
 // walk the staged entries several at a time, each entry in an LDS copy of
 // the tile of its own.  The lanes of one entry cover its 64 taps (distinct
 // points), so plain read-modify-write is race free; out-of-tile taps update
@@ -260,15 +266,15 @@ __host__ __device__ inline size_t warp_spread_lds_bytes(const TileDims& td, int 
 // displacement and value one round ahead, so they are in flight while the
 // wave accumulates the current round.
 template <int NDIM>
-__global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPhases ph, float2* __restrict__ U,
+__global__ __launch_bounds__(64 * kWarpWaves) void warp_spread_kernel(WarpSpreadPhases ph, float2* __restrict__ U,
                                                                    int accumulate, int ntiles, Dims dm,
                                                                    TileDims td, KbPoly kb) {
   using WL = WarpLanes<NDIM>;
   constexpr int Q = WL::kCopies;
   extern __shared__ float2 accw[];  // [kWarpWaves][Q][P], then [kWarpDump] garbage
-  __shared__ int4 st_off[kWarpWaves][64];
-  __shared__ float st_w[kWarpWaves][64 * 12];  // entry s: weights of axis i at 12 s + 4 i + t
-  __shared__ float2 st_v[kWarpWaves][64];
+  __shared__ int4 st_off[kWarpWaves][kWarpStage];
+  __shared__ float st_w[kWarpWaves][kWarpStage * 12];  // entry s: weights of axis i at 12 s + 4 i + t
+  __shared__ float2 st_v[kWarpWaves][kWarpStage];
   __shared__ int s_beg[kMaxPhasesPerLaunch];      // first entry of state p in its voxel list
   __shared__ int s_pfx[kMaxPhasesPerLaunch + 1];  // entries of the tile over states < p
   // per-state pointers in LDS: indexing the kernel arguments by a runtime
@@ -301,7 +307,7 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
   {
     float4* a4 = (float4*)accw;
     const int n4 = (kWarpWaves * Q * td.P) >> 1;  // P is even
-    for (int e = threadIdx.x; e < n4; e += kGridThreads) a4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int e = threadIdx.x; e < n4; e += 64 * kWarpWaves) a4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   // entries of this tile over all states, concatenated
   if ((int)threadIdx.x < ph.P) {
@@ -335,14 +341,18 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
     ta = lane & 3;  // t1
   }
   float2* copy = accw + (size_t)(wave * Q + q) * td.P;
-  float2* mydump = dump + lane;  // slot j at mydump[64 j]
-  const int nbatch = (E + 63) / 64;
+  // an out-of-tile tap updates the garbage slot congruent to its would-be
+  // address mod 64 (the same LDS bank), so a step whose taps lie partly
+  // outside the tile keeps the bank pattern of one wholly inside (the slots
+  // hold garbage, so lanes may share one)
+  const int mbase = (wave * Q + q - kWarpWaves * Q) * td.P;
+  const int nbatch = (E + kWarpStage - 1) / kWarpStage;
   const int rounds = (nbatch + kWarpWaves - 1) / kWarpWaves;
   // the entry this lane stages in round rd: its state and voxel (-1: none)
   auto voxel_of = [&](int rd, int& p) -> int {
-    const int e = (rd * kWarpWaves + wave) * 64 + lane;
+    const int e = (rd * kWarpWaves + wave) * kWarpStage + lane;
     p = 0;
-    if (rd >= rounds || e >= E) return -1;
+    if (rd >= rounds || lane >= kWarpStage || e >= E) return -1;
     while (e >= s_pfx[p + 1]) ++p;
     return s_vox[p][s_beg[p] + (e - s_pfx[p])];
   };
@@ -364,8 +374,8 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
   int r2 = voxel_of(1, p2);  // staging round 1
   for (int rd = 0; rd < rounds; ++rd) {
     const int b = rd * kWarpWaves + wave;
-    const int e0 = b * 64;
-    const int ne = max(0, min(64, E - e0));
+    const int e0 = b * kWarpStage;
+    const int ne = max(0, min(kWarpStage, E - e0));
     const int r = rn;
     float dc[NDIM];
 #pragma unroll
@@ -419,7 +429,8 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
         for (int j = 0; j < 2; ++j) {
           const int l0 = of.x + t0a + j;
           const bool ok = ok12 && (unsigned)l0 < (unsigned)ext[0];
-          ptr[j] = ok ? copy + (__mul24(l0, td.S0) + base) : mydump + 64 * j;
+          const int off = __mul24(l0, td.S0) + base;
+          ptr[j] = ok ? copy + off : dump + ((mbase + off) & 63);
           wt[j] = w12 * st_w[wave][wi + t0a + j];
           a[j] = *ptr[j];
         }
@@ -430,7 +441,8 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
         const bool ok = has && (unsigned)l0 < (unsigned)ext[0] && (unsigned)l1 < (unsigned)ext[1];
         const int wi = __mul24(sc, 12);
         const float ww = st_w[wave][wi + t0a] * st_w[wave][wi + 4 + ta];
-        float2* pt = ok ? copy + (__mul24(l0, td.S0) + l1) : mydump;
+        const int off = __mul24(l0, td.S0) + l1;
+        float2* pt = ok ? copy + off : dump + ((mbase + off) & 63);
         const float2 a = *pt;
         *pt = make_float2(fmaf(ww, v.x, a.x), fmaf(ww, v.y, a.y));
       }
@@ -438,7 +450,7 @@ __global__ __launch_bounds__(kGridThreads) void warp_spread_kernel(WarpSpreadPha
   }
   __syncthreads();
   // sum the copies and write the tile: rows along the last axis are contiguous in U
-  for (int e = threadIdx.x; e < vol; e += kGridThreads) {
+  for (int e = threadIdx.x; e < vol; e += 64 * kWarpWaves) {
     int l[3] = {0, 0, 0};
     int t = e;
     for (int i = NDIM - 1; i >= 0; --i) {

@@ -777,11 +777,11 @@ static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const 
       allow_lds(warp_spread_kernel<2>, lds);
     Tick tick(pl, "warp_spread");
     if (pl->ndim == 3)
-      hipLaunchKernelGGL(warp_spread_kernel<3>, dim3(nblk), dim3(kGridThreads), lds, pl->stream, ph, U, acc, nt,
-                         pl->dims, pl->wtile, pl->kb);
+      hipLaunchKernelGGL(warp_spread_kernel<3>, dim3(nblk), dim3(64 * kWarpWaves), lds, pl->stream, ph, U, acc,
+                         nt, pl->dims, pl->wtile, pl->kb);
     else
-      hipLaunchKernelGGL(warp_spread_kernel<2>, dim3(nblk), dim3(kGridThreads), lds, pl->stream, ph, U, acc, nt,
-                         pl->dims, pl->wtile, pl->kb);
+      hipLaunchKernelGGL(warp_spread_kernel<2>, dim3(nblk), dim3(64 * kWarpWaves), lds, pl->stream, ph, U, acc,
+                         nt, pl->dims, pl->wtile, pl->kb);
     LAUNCH_OK();
   }
 }
