@@ -621,12 +621,21 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
   if (pl->ndim == 3) {
     mid.n_inner = n2;
     mid.three_d = 1;
-    {  // F along axis 2
+    // the passes along axes 1 and 2 take the register FFT where the length
+    // allows it (an in-place pass is safe there: a workgroup loads all its
+    // lines before any store, and no line is shared between workgroups)
+    if (fft2_supported(n2)) {  // F along axis 2
+      run_fft2<-1, kJFast, kJFast>(pl, "fft_up_ax2", n2, ld2<kFP32>(pl, x, n2, 1, kDense, n2),
+                                   st2<kFP32>(pl->bufA, n2, 1, kDense), make_tile2((int64_t)n0 * n1, 1, n2, 1));
+    } else {
       TileGeom g = make_geom((int64_t)n0 * n1, 1, n2, 0);
       run_pass(pl, "fft_up_ax2", ld_strided<kFP32>(x, n2, 1, n2, n2, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufA, n2, 1, n2, n2, kDense, g), g, line_plan(pl, n2), -1.f, nullptr, 0.f);
     }
-    {  // F along axis 1, in place
+    if (fft2_supported(n1)) {  // F along axis 1, in place
+      run_fft2<-1, kBFast, kBFast>(pl, "fft_up_ax1", n1, ld2<kFP32>(pl, pl->bufA, (int64_t)n1 * n2, n2, kDense, n1),
+                                   st2<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, kDense), make_tile2(n0, n2, n1, 0));
+    } else {
       TileGeom g = make_geom(n0, n2, n1, 0);
       run_pass(pl, "fft_up_ax1", ld_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), g, line_plan(pl, n1), -1.f,
@@ -638,13 +647,20 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
                st_strided<kFP32>(pl->bufB, 0, (int64_t)n1 * n2, G0, G0, kDense, g), g, line_plan(pl, n0), -1.f,
                &line_plan(pl, G0), +1.f);
     }
-    {  // F^H along axis 1 with the spectral pad
+    if (fft2_supported(G1)) {  // F^H along axis 1 with the spectral pad
+      run_fft2<+1, kBFast, kBFast, 1>(pl, "fft_up_G1", G1,
+                                      ld2<kFP32>(pl, pl->bufB, (int64_t)n1 * n2, n2, kSpectral, G1),
+                                      st2<kFP32>(pl->bufC, (int64_t)G1 * n2, n2, kDense), make_tile2(G0, n2, G1, 0));
+    } else {
       TileGeom g = make_geom(G0, n2, G1, 0);
       run_pass(pl, "fft_up_G1", ld_strided<kFP32>(pl->bufB, (int64_t)n1 * n2, n2, n1, G1, kSpectral, g), NoMid(),
                st_strided<kFP32>(pl->bufC, (int64_t)G1 * n2, n2, G1, G1, kDense, g), g, line_plan(pl, G1), +1.f,
                nullptr, 0.f);
     }
-    {  // F^H along axis 2 with the spectral pad
+    if (fft2_supported(G2)) {  // F^H along axis 2 with the spectral pad
+      run_fft2<+1, kJFast, kJFast, 1>(pl, "fft_up_G2", G2, ld2<kFP32>(pl, pl->bufC, n2, 1, kSpectral, G2),
+                                      st2<kFP32>(u, G2, 1, kDense), make_tile2((int64_t)G0 * G1, 1, G2, 1));
+    } else {
       TileGeom g = make_geom((int64_t)G0 * G1, 1, G2, 0);
       run_pass(pl, "fft_up_G2", ld_strided<kFP32>(pl->bufC, n2, 1, n2, G2, kSpectral, g), NoMid(),
                st_strided<kFP32>(u, G2, 1, G2, G2, kDense, g), g, line_plan(pl, G2), +1.f, nullptr, 0.f);
@@ -683,12 +699,20 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
   if (pl->ndim == 3) {
     mid.n_inner = n2;
     mid.three_d = 1;
-    {  // F along axis 2, crop
+    // register FFTs along axes 2 and 1 where the length allows (as in upsample)
+    if (fft2_supported(G2)) {  // F along axis 2, crop
+      run_fft2<-1, kJFast, kJFast, 2>(pl, "fft_uph_G2", G2, ld2<kFP32>(pl, U, G2, 1, kDense, G2),
+                                      st2<kFP32>(pl->bufC, n2, 1, kSpectral), make_tile2((int64_t)G0 * G1, 1, G2, 1));
+    } else {
       TileGeom g = make_geom((int64_t)G0 * G1, 1, G2, 0);
       run_pass(pl, "fft_uph_G2", ld_strided<kFP32>(U, G2, 1, G2, G2, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufC, n2, 1, n2, G2, kSpectral, g), g, line_plan(pl, G2), -1.f, nullptr, 0.f);
     }
-    {  // F along axis 1, crop
+    if (fft2_supported(G1)) {  // F along axis 1, crop
+      run_fft2<-1, kBFast, kBFast, 2>(pl, "fft_uph_G1", G1,
+                                      ld2<kFP32>(pl, pl->bufC, (int64_t)G1 * n2, n2, kDense, G1),
+                                      st2<kFP32>(pl->bufB, (int64_t)n1 * n2, n2, kSpectral), make_tile2(G0, n2, G1, 0));
+    } else {
       TileGeom g = make_geom(G0, n2, G1, 0);
       run_pass(pl, "fft_uph_G1", ld_strided<kFP32>(pl->bufC, (int64_t)G1 * n2, n2, G1, G1, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufB, (int64_t)n1 * n2, n2, n1, G1, kSpectral, g), g, line_plan(pl, G1), -1.f,
@@ -700,13 +724,19 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
                st_strided<kFP32>(pl->bufA, 0, (int64_t)n1 * n2, n0, n0, kDense, g), g, line_plan(pl, G0), -1.f,
                &line_plan(pl, n0), +1.f);
     }
-    {  // F^H along axis 1, in place
+    if (fft2_supported(n1)) {  // F^H along axis 1, in place
+      run_fft2<+1, kBFast, kBFast>(pl, "fft_uph_ax1", n1, ld2<kFP32>(pl, pl->bufA, (int64_t)n1 * n2, n2, kDense, n1),
+                                   st2<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, kDense), make_tile2(n0, n2, n1, 0));
+    } else {
       TileGeom g = make_geom(n0, n2, n1, 0);
       run_pass(pl, "fft_uph_ax1", ld_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), g, line_plan(pl, n1), +1.f,
                nullptr, 0.f);
     }
-    {  // F^H along axis 2
+    if (fft2_supported(n2)) {  // F^H along axis 2
+      run_fft2<+1, kJFast, kJFast>(pl, "fft_uph_ax2", n2, ld2<kFP32>(pl, pl->bufA, n2, 1, kDense, n2),
+                                   st2<kFP32>(out, n2, 1, kDense), make_tile2((int64_t)n0 * n1, 1, n2, 1));
+    } else {
       TileGeom g = make_geom((int64_t)n0 * n1, 1, n2, 0);
       run_pass(pl, "fft_uph_ax2", ld_strided<kFP32>(pl->bufA, n2, 1, n2, n2, kDense, g), NoMid(),
                st_strided<kFP32>(out, n2, 1, n2, n2, kDense, g), g, line_plan(pl, n2), +1.f, nullptr, 0.f);
