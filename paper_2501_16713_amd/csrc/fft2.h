@@ -379,6 +379,18 @@ inline bool half_gap(const St2Strided<S>& x, int) { return x.map == kCentred || 
 template <int S>
 inline bool half_gap(const St2Rows<S>& x, int) { return x.map == kCentred || x.map == kSpectral; }
 
+// The strided load and store of the single-image upsampling passes: the same
+// code as Ld2Strided / St2Strided under types of their own, so that kernel
+// names (and profiles) tell those passes from the coil passes of equal length.
+template <int S>
+struct Ld2Image : Ld2Strided<S> {};
+template <int S>
+struct St2Image : St2Strided<S> {};
+template <int S>
+inline bool half_gap(const Ld2Image<S>& x, int L) { return half_gap(static_cast<const Ld2Strided<S>&>(x), L); }
+template <int S>
+inline bool half_gap(const St2Image<S>& x, int L) { return half_gap(static_cast<const St2Strided<S>&>(x), L); }
+
 // Touched-tile masks of a trajectory.  The k-space grid [G0][...][C] is cut
 // into spread tiles; colmask[col] has bit t0 set when some sample's taps
 // touch tile (t0, col), col = (i1 / TS1) nt2 + i2 / TS2 (3D) or i1 / TS1 (2D).

@@ -532,6 +532,18 @@ static St2Strided<S> st2(void* p, int64_t sa, int64_t sj, int map, float scale =
   return s;
 }
 
+// the same for the single-image upsampling passes (types of their own)
+static Ld2Image<kFP32> ld2_img(const isg_plan* pl, const float2* p, int64_t sa, int64_t sj, int map, int L) {
+  Ld2Image<kFP32> l;
+  static_cast<Ld2Strided<kFP32>&>(l) = ld2<kFP32>(pl, p, sa, sj, map, L);
+  return l;
+}
+static St2Image<kFP32> st2_img(float2* p, int64_t sa, int64_t sj, int map) {
+  St2Image<kFP32> s;
+  static_cast<St2Strided<kFP32>&>(s) = st2<kFP32>(p, sa, sj, map);
+  return s;
+}
+
 // lines along axis 1 of a row-blocked array: a = i0, b = i2 C + c, j = i1
 template <int S>
 static Ld2Strided<S> ld2_axis1(const isg_plan* pl, const void* p, const Blk& blk, int map, int L) {
@@ -625,16 +637,16 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
     // allows it (an in-place pass is safe there: a workgroup loads all its
     // lines before any store, and no line is shared between workgroups)
     if (fft2_supported(n2)) {  // F along axis 2
-      run_fft2<-1, kJFast, kJFast>(pl, "fft_up_ax2", n2, ld2<kFP32>(pl, x, n2, 1, kDense, n2),
-                                   st2<kFP32>(pl->bufA, n2, 1, kDense), make_tile2((int64_t)n0 * n1, 1, n2, 1));
+      run_fft2<-1, kJFast, kJFast>(pl, "fft_up_ax2", n2, ld2_img(pl, x, n2, 1, kDense, n2),
+                                   st2_img(pl->bufA, n2, 1, kDense), make_tile2((int64_t)n0 * n1, 1, n2, 1));
     } else {
       TileGeom g = make_geom((int64_t)n0 * n1, 1, n2, 0);
       run_pass(pl, "fft_up_ax2", ld_strided<kFP32>(x, n2, 1, n2, n2, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufA, n2, 1, n2, n2, kDense, g), g, line_plan(pl, n2), -1.f, nullptr, 0.f);
     }
     if (fft2_supported(n1)) {  // F along axis 1, in place
-      run_fft2<-1, kBFast, kBFast>(pl, "fft_up_ax1", n1, ld2<kFP32>(pl, pl->bufA, (int64_t)n1 * n2, n2, kDense, n1),
-                                   st2<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, kDense), make_tile2(n0, n2, n1, 0));
+      run_fft2<-1, kBFast, kBFast>(pl, "fft_up_ax1", n1, ld2_img(pl, pl->bufA, (int64_t)n1 * n2, n2, kDense, n1),
+                                   st2_img(pl->bufA, (int64_t)n1 * n2, n2, kDense), make_tile2(n0, n2, n1, 0));
     } else {
       TileGeom g = make_geom(n0, n2, n1, 0);
       run_pass(pl, "fft_up_ax1", ld_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
@@ -649,8 +661,8 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
     }
     if (fft2_supported(G1)) {  // F^H along axis 1 with the spectral pad
       run_fft2<+1, kBFast, kBFast, 1>(pl, "fft_up_G1", G1,
-                                      ld2<kFP32>(pl, pl->bufB, (int64_t)n1 * n2, n2, kSpectral, G1),
-                                      st2<kFP32>(pl->bufC, (int64_t)G1 * n2, n2, kDense), make_tile2(G0, n2, G1, 0));
+                                      ld2_img(pl, pl->bufB, (int64_t)n1 * n2, n2, kSpectral, G1),
+                                      st2_img(pl->bufC, (int64_t)G1 * n2, n2, kDense), make_tile2(G0, n2, G1, 0));
     } else {
       TileGeom g = make_geom(G0, n2, G1, 0);
       run_pass(pl, "fft_up_G1", ld_strided<kFP32>(pl->bufB, (int64_t)n1 * n2, n2, n1, G1, kSpectral, g), NoMid(),
@@ -658,8 +670,8 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
                nullptr, 0.f);
     }
     if (fft2_supported(G2)) {  // F^H along axis 2 with the spectral pad
-      run_fft2<+1, kJFast, kJFast, 1>(pl, "fft_up_G2", G2, ld2<kFP32>(pl, pl->bufC, n2, 1, kSpectral, G2),
-                                      st2<kFP32>(u, G2, 1, kDense), make_tile2((int64_t)G0 * G1, 1, G2, 1));
+      run_fft2<+1, kJFast, kJFast, 1>(pl, "fft_up_G2", G2, ld2_img(pl, pl->bufC, n2, 1, kSpectral, G2),
+                                      st2_img(u, G2, 1, kDense), make_tile2((int64_t)G0 * G1, 1, G2, 1));
     } else {
       TileGeom g = make_geom((int64_t)G0 * G1, 1, G2, 0);
       run_pass(pl, "fft_up_G2", ld_strided<kFP32>(pl->bufC, n2, 1, n2, G2, kSpectral, g), NoMid(),
@@ -701,8 +713,8 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
     mid.three_d = 1;
     // register FFTs along axes 2 and 1 where the length allows (as in upsample)
     if (fft2_supported(G2)) {  // F along axis 2, crop
-      run_fft2<-1, kJFast, kJFast, 2>(pl, "fft_uph_G2", G2, ld2<kFP32>(pl, U, G2, 1, kDense, G2),
-                                      st2<kFP32>(pl->bufC, n2, 1, kSpectral), make_tile2((int64_t)G0 * G1, 1, G2, 1));
+      run_fft2<-1, kJFast, kJFast, 2>(pl, "fft_uph_G2", G2, ld2_img(pl, U, G2, 1, kDense, G2),
+                                      st2_img(pl->bufC, n2, 1, kSpectral), make_tile2((int64_t)G0 * G1, 1, G2, 1));
     } else {
       TileGeom g = make_geom((int64_t)G0 * G1, 1, G2, 0);
       run_pass(pl, "fft_uph_G2", ld_strided<kFP32>(U, G2, 1, G2, G2, kDense, g), NoMid(),
@@ -710,8 +722,8 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
     }
     if (fft2_supported(G1)) {  // F along axis 1, crop
       run_fft2<-1, kBFast, kBFast, 2>(pl, "fft_uph_G1", G1,
-                                      ld2<kFP32>(pl, pl->bufC, (int64_t)G1 * n2, n2, kDense, G1),
-                                      st2<kFP32>(pl->bufB, (int64_t)n1 * n2, n2, kSpectral), make_tile2(G0, n2, G1, 0));
+                                      ld2_img(pl, pl->bufC, (int64_t)G1 * n2, n2, kDense, G1),
+                                      st2_img(pl->bufB, (int64_t)n1 * n2, n2, kSpectral), make_tile2(G0, n2, G1, 0));
     } else {
       TileGeom g = make_geom(G0, n2, G1, 0);
       run_pass(pl, "fft_uph_G1", ld_strided<kFP32>(pl->bufC, (int64_t)G1 * n2, n2, G1, G1, kDense, g), NoMid(),
@@ -725,8 +737,8 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
                &line_plan(pl, n0), +1.f);
     }
     if (fft2_supported(n1)) {  // F^H along axis 1, in place
-      run_fft2<+1, kBFast, kBFast>(pl, "fft_uph_ax1", n1, ld2<kFP32>(pl, pl->bufA, (int64_t)n1 * n2, n2, kDense, n1),
-                                   st2<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, kDense), make_tile2(n0, n2, n1, 0));
+      run_fft2<+1, kBFast, kBFast>(pl, "fft_uph_ax1", n1, ld2_img(pl, pl->bufA, (int64_t)n1 * n2, n2, kDense, n1),
+                                   st2_img(pl->bufA, (int64_t)n1 * n2, n2, kDense), make_tile2(n0, n2, n1, 0));
     } else {
       TileGeom g = make_geom(n0, n2, n1, 0);
       run_pass(pl, "fft_uph_ax1", ld_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
@@ -734,8 +746,8 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
                nullptr, 0.f);
     }
     if (fft2_supported(n2)) {  // F^H along axis 2
-      run_fft2<+1, kJFast, kJFast>(pl, "fft_uph_ax2", n2, ld2<kFP32>(pl, pl->bufA, n2, 1, kDense, n2),
-                                   st2<kFP32>(out, n2, 1, kDense), make_tile2((int64_t)n0 * n1, 1, n2, 1));
+      run_fft2<+1, kJFast, kJFast>(pl, "fft_uph_ax2", n2, ld2_img(pl, pl->bufA, n2, 1, kDense, n2),
+                                   st2_img(out, n2, 1, kDense), make_tile2((int64_t)n0 * n1, 1, n2, 1));
     } else {
       TileGeom g = make_geom((int64_t)n0 * n1, 1, n2, 0);
       run_pass(pl, "fft_uph_ax2", ld_strided<kFP32>(pl->bufA, n2, 1, n2, n2, kDense, g), NoMid(),

@@ -65,6 +65,8 @@ def stage_of(kernel: str) -> str:
         if tag + "_kernel" in kernel:
             return tag
     if "fft2_kernel" in kernel:
+        if "Ld2Image" in kernel:
+            return "fft_upsample_passes"
         if "Ld2CoilExpand" in kernel:
             return "fft_coil_fwd_last"
         if "St2CoilReduce" in kernel:
