@@ -680,7 +680,10 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
   } else {
     mid.n_inner = 1;
     mid.three_d = 0;
-    {
+    if (fft2_supported(n1)) {
+      run_fft2<-1, kJFast, kJFast>(pl, "fft_up_ax1", n1, ld2_img(pl, x, n1, 1, kDense, n1),
+                                   st2_img(pl->bufA, n1, 1, kDense), make_tile2(n0, 1, n1, 1));
+    } else {
       TileGeom g = make_geom(n0, 1, n1, 0);
       run_pass(pl, "fft_up_ax1", ld_strided<kFP32>(x, n1, 1, n1, n1, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufA, n1, 1, n1, n1, kDense, g), g, line_plan(pl, n1), -1.f, nullptr, 0.f);
@@ -691,7 +694,10 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
                st_strided<kFP32>(pl->bufB, 0, n1, G0, G0, kDense, g), g, line_plan(pl, n0), -1.f, &line_plan(pl, G0),
                +1.f);
     }
-    {
+    if (fft2_supported(G1)) {
+      run_fft2<+1, kJFast, kJFast, 1>(pl, "fft_up_G1", G1, ld2_img(pl, pl->bufB, n1, 1, kSpectral, G1),
+                                      st2_img(u, G1, 1, kDense), make_tile2(G0, 1, G1, 1));
+    } else {
       TileGeom g = make_geom(G0, 1, G1, 0);
       run_pass(pl, "fft_up_G1", ld_strided<kFP32>(pl->bufB, n1, 1, n1, G1, kSpectral, g), NoMid(),
                st_strided<kFP32>(u, G1, 1, G1, G1, kDense, g), g, line_plan(pl, G1), +1.f, nullptr, 0.f);
@@ -756,7 +762,10 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
   } else {
     mid.n_inner = 1;
     mid.three_d = 0;
-    {
+    if (fft2_supported(G1)) {
+      run_fft2<-1, kJFast, kJFast, 2>(pl, "fft_uph_G1", G1, ld2_img(pl, U, G1, 1, kDense, G1),
+                                      st2_img(pl->bufB, n1, 1, kSpectral), make_tile2(G0, 1, G1, 1));
+    } else {
       TileGeom g = make_geom(G0, 1, G1, 0);
       run_pass(pl, "fft_uph_G1", ld_strided<kFP32>(U, G1, 1, G1, G1, kDense, g), NoMid(),
                st_strided<kFP32>(pl->bufB, n1, 1, n1, G1, kSpectral, g), g, line_plan(pl, G1), -1.f, nullptr, 0.f);
@@ -767,7 +776,10 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
                st_strided<kFP32>(pl->bufA, 0, n1, n0, n0, kDense, g), g, line_plan(pl, G0), -1.f, &line_plan(pl, n0),
                +1.f);
     }
-    {
+    if (fft2_supported(n1)) {
+      run_fft2<+1, kJFast, kJFast>(pl, "fft_uph_ax1", n1, ld2_img(pl, pl->bufA, n1, 1, kDense, n1),
+                                   st2_img(out, n1, 1, kDense), make_tile2(n0, 1, n1, 1));
+    } else {
       TileGeom g = make_geom(n0, 1, n1, 0);
       run_pass(pl, "fft_uph_ax1", ld_strided<kFP32>(pl->bufA, n1, 1, n1, n1, kDense, g), NoMid(),
                st_strided<kFP32>(out, n1, 1, n1, n1, kDense, g), g, line_plan(pl, n1), +1.f, nullptr, 0.f);
