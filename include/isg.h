@@ -45,7 +45,13 @@
  *                 component i is along array axis i; image voxel index j
  *                 sits at the centred position j - n/2
  *   data   y      complex64, states packed one after another; state p holds
- *                 [M_p][C] (sample-major, coils contiguous).
+ *                 [M_p][C] (sample-major, coils contiguous).  Sample-major
+ *                 rather than coil-major ([C][M_p]): one set of 4^ndim
+ *                 kernel weights per sample serves its C contiguous coil
+ *                 values in one coalesced access, in the gather and the
+ *                 spread alike.  Every apply call takes the number of
+ *                 states P it is given (at most the plan's nphases) and P
+ *                 motion and trajectory handles.
  *
  * Numerics: Kaiser-Bessel kernel of width 4 on a 2x oversampled periodic
  * grid, beta = pi*sqrt(4*(1.5)^2 - 0.8); FP32 arithmetic (FP64 for the
@@ -66,7 +72,9 @@ extern "C" {
 typedef enum {
   ISG_OK = 0,
   ISG_ERR_INVALID_ARG = 1,       /* null pointer, bad count, bad enum, size mismatch */
-  ISG_ERR_UNSUPPORTED_SHAPE = 2, /* n_i not even, < 8, > 512, or with a prime factor > 5 */
+  ISG_ERR_UNSUPPORTED_SHAPE = 2, /* n_i not even, < 8, > 512, or with a prime factor > 7;
+                                    alpha != 2, width != 4, beta > 0 and not the default;
+                                    ncoils * 2 * n_last > 8192 */
   ISG_ERR_OUT_OF_MEMORY = 3,     /* a device or host allocation failed */
   ISG_ERR_DEVICE = 4,            /* no usable GPU, or a HIP runtime error */
   ISG_ERR_NOT_FINITE = 5,        /* NaN/Inf in a displacement field or trajectory */
@@ -97,9 +105,22 @@ typedef struct isg_plan isg_plan;     /* shape, tables, scratch; library-owned *
 typedef struct isg_motion isg_motion; /* prepared displacement field d_p       */
 typedef struct isg_traj isg_traj;     /* prepared trajectory k_p               */
 
+/* Plan description.  Shapes: each n_i even, 8 <= n_i <= 512, prime factors
+ * in {2, 3, 5, 7} (lengths whose factors are 2, 3 and 5 only, and whose
+ * oversampled length is one of 32, 40, 48, 64, 80, 96, 128, 160, 192, 256,
+ * 320, 512, run the faster two-step register FFT; the others the general
+ * LDS Stockham passes).  The coil passes hold all C coils of a line in one
+ * workgroup, so ncoils * 2 * n_last <= 8192.  The interpolation kernel is
+ * fixed to Kaiser-Bessel of width 4 on a 2x oversampled grid (the operators'
+ * tables and tap loops are built for it): alpha and width must be given as
+ * 2 and 4, and beta as <= 0 (meaning pi sqrt((W/alpha)^2 (alpha - 1/2)^2 -
+ * 0.8) = 8.99615...) or that value itself. */
 typedef struct {
   int ndim;            /* 2 or 3 */
   int64_t n[3];        /* image shape; n[2] ignored when ndim == 2 */
+  int alpha;           /* oversampling factor G_i / n_i: must be 2 */
+  int width;           /* kernel width W in oversampled cells (taps per axis): must be 4 */
+  double beta;         /* Kaiser-Bessel shape parameter; <= 0: the default */
   int ncoils;          /* C >= 1 (1..32) */
   int nphases;         /* P >= 1: most states one call may pass */
   isg_storage storage; /* storage of the coil-expanded k-space grids */
@@ -119,6 +140,10 @@ isg_status isg_device_count(int* count);
  * tables and allocates the scratch the operators need.  Errors:
  * INVALID_ARG, UNSUPPORTED_SHAPE, DEVICE (no GPU), OUT_OF_MEMORY. */
 isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** plan);
+/* Destroy a plan (synchronizes its stream).  Motions and trajectories
+ * prepared on it may be destroyed before or after it: those still alive are
+ * detached, keep their own device memory until their own destroy call, and
+ * fail every apply call (INVALID_ARG: no plan). */
 isg_status isg_plan_destroy(isg_plan* plan);
 /* Change the stream later calls enqueue on. */
 isg_status isg_plan_set_stream(isg_plan* plan, void* stream);

@@ -55,6 +55,9 @@ class isg_plan_desc(C.Structure):
     _fields_ = [
         ("ndim", C.c_int),
         ("n", C.c_int64 * 3),
+        ("alpha", C.c_int),
+        ("width", C.c_int),
+        ("beta", C.c_double),
         ("ncoils", C.c_int),
         ("nphases", C.c_int),
         ("storage", C.c_int),

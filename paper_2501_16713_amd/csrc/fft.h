@@ -98,6 +98,37 @@ template <> __device__ __forceinline__ void dft<5>(float2* v, float s) {
   v[3] = csub(m2, n2);
 }
 
+// 7 points: pairs t_m = v_m + v_{7-m}, d_m = v_m - v_{7-m} (m = 1..3), so
+// X_k = v_0 + sum_m cos(2 pi mk/7) t_m + s i sum_m sin(2 pi mk/7) d_m and
+// X_{7-k} the same with the sine sum negated.
+template <> __device__ __forceinline__ void dft<7>(float2* v, float s) {
+  const float c1 = 0.62348980185873353f;   // cos(2 pi / 7)
+  const float c2 = -0.22252093395631440f;  // cos(4 pi / 7)
+  const float c3 = -0.90096886790241913f;  // cos(6 pi / 7)
+  const float s1 = 0.78183148246802981f;   // sin(2 pi / 7)
+  const float s2 = 0.97492791218182361f;   // sin(4 pi / 7)
+  const float s3 = 0.43388373911755812f;   // sin(6 pi / 7)
+  const float2 a0 = v[0];
+  const float2 t1 = cadd(v[1], v[6]), t2 = cadd(v[2], v[5]), t3 = cadd(v[3], v[4]);
+  const float2 d1 = csub(v[1], v[6]), d2 = csub(v[2], v[5]), d3 = csub(v[3], v[4]);
+  auto re = [&](float a, float b, float c) {
+    return make_float2(a0.x + a * t1.x + b * t2.x + c * t3.x, a0.y + a * t1.y + b * t2.y + c * t3.y);
+  };
+  auto im = [&](float a, float b, float c) {
+    return cmul_si(make_float2(a * d1.x + b * d2.x + c * d3.x, a * d1.y + b * d2.y + c * d3.y), s);
+  };
+  const float2 m1 = re(c1, c2, c3), n1 = im(s1, s2, s3);
+  const float2 m2 = re(c2, c3, c1), n2 = im(s2, -s3, -s1);
+  const float2 m3 = re(c3, c1, c2), n3 = im(s3, -s1, s2);
+  v[0] = cadd(a0, cadd(t1, cadd(t2, t3)));
+  v[1] = cadd(m1, n1);
+  v[6] = csub(m1, n1);
+  v[2] = cadd(m2, n2);
+  v[5] = csub(m2, n2);
+  v[3] = cadd(m3, n3);
+  v[4] = csub(m3, n3);
+}
+
 template <> __device__ __forceinline__ void dft<8>(float2* v, float s) {
   // radix-2 split into even/odd radix-4 DFTs, then twiddles exp(s 2 pi i m / 8)
   const float r = 0.70710678118654752440f;
@@ -176,6 +207,7 @@ __device__ __forceinline__ void fft_line(float2* line, const LinePlan& lp, int t
       case 3: fft_stage<3>(line, lp, st, tl, tpl, s, tw, active); break;
       case 4: fft_stage<4>(line, lp, st, tl, tpl, s, tw, active); break;
       case 5: fft_stage<5>(line, lp, st, tl, tpl, s, tw, active); break;
+      case 7: fft_stage<7>(line, lp, st, tl, tpl, s, tw, active); break;
       default: fft_stage<8>(line, lp, st, tl, tpl, s, tw, active); break;
     }
   }

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <set>
 #include <new>
 #include <string>
 #include <vector>
@@ -59,7 +60,8 @@ static FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
-static bool factor_235(int L, std::vector<int>& R) {
+// radices of the Stockham stages of a line of length L (factors 2, 3, 5, 7)
+static bool factor_radices(int L, std::vector<int>& R) {
   R.clear();
   int m = L;
   while (m % 8 == 0 && m > 4) { R.push_back(8); m /= 8; }
@@ -67,6 +69,7 @@ static bool factor_235(int L, std::vector<int>& R) {
   while (m % 2 == 0) { R.push_back(2); m /= 2; }
   while (m % 5 == 0) { R.push_back(5); m /= 5; }
   while (m % 3 == 0) { R.push_back(3); m /= 3; }
+  while (m % 7 == 0) { R.push_back(7); m /= 7; }
   return m == 1 && (int)R.size() <= kMaxStages;
 }
 
@@ -151,6 +154,11 @@ struct isg_plan {
   float* dx[3] = {nullptr, nullptr, nullptr};  // c(0)/c(x/G), centred positions
   std::map<int, LinePlan> lines;
   std::vector<void*> owned;
+  std::map<void*, size_t> sizes;  // bytes of every device allocation the plan counts
+  // live prepared handles; destroying the plan detaches them (their later
+  // destroy then frees only their own memory)
+  std::set<isg_motion*> motions;
+  std::set<isg_traj*> trajs;
   // scratch
   float2* ugrid = nullptr;  // [NG]
   float2* bufA = nullptr;   // [N]
@@ -287,7 +295,22 @@ static void* dmalloc(isg_plan* pl, size_t bytes) {
     throw std::bad_alloc();
   }
   pl->bytes += (int64_t)bytes;
+  pl->sizes[p] = bytes;
   return p;
+}
+
+// free memory from dmalloc (it leaves the plan's count); pl may be null for
+// a handle whose plan was destroyed first
+static hipError_t dfree(isg_plan* pl, void* p) {
+  if (!p) return hipSuccess;
+  if (pl) {
+    auto it = pl->sizes.find(p);
+    if (it != pl->sizes.end()) {
+      pl->bytes -= (int64_t)it->second;
+      pl->sizes.erase(it);
+    }
+  }
+  return hipFree(p);
 }
 
 static void* plan_alloc(isg_plan* pl, size_t bytes) {
@@ -301,8 +324,7 @@ static void grow(isg_plan* pl, DevBuf& b, size_t bytes) {
   pl->generation++;
   if (b.p) {
     HIP_OK(hipStreamSynchronize(pl->stream));
-    HIP_OK(hipFree(b.p));
-    pl->bytes -= (int64_t)b.bytes;
+    HIP_OK(dfree(pl, b.p));
     b.p = nullptr;
     b.bytes = 0;
   }
@@ -314,7 +336,7 @@ static const LinePlan& line_plan(isg_plan* pl, int L) {
   auto it = pl->lines.find(L);
   if (it != pl->lines.end()) return it->second;
   std::vector<int> R;
-  factor_235(L, R);
+  factor_radices(L, R);
   LinePlan lp;
   memset(&lp, 0, sizeof(lp));
   lp.L = L;
@@ -1468,6 +1490,19 @@ static int axis_tiles(int b, int G, int TS, int out[2]) {
   return 1;
 }
 
+// Extent of a spread tile along an axis of G cells: the requested extent,
+// capped at the largest power of two not above G/2.  Both spreads place a
+// tap run relative to the tile origin at its nearest periodic image, the
+// offset folded into (-G/2, G/2]; a run of W = 4 taps meets a tile of
+// extent at most G/2 in one periodic image only, so the fold finds every
+// in-tile tap.  A wider tile (e.g. 16 on an axis of 16, 20 or 24 cells)
+// would lose the taps of runs that start past G/2 from its origin.
+static int spread_extent(int want, int G) {
+  int cap = 1;
+  while (2 * cap <= G / 2) cap *= 2;
+  return std::min(want, cap);
+}
+
 static isg_status prepare_motion(isg_plan* pl, const float* d_dev, isg_motion* mo) {
   const int nd = pl->ndim;
   const int64_t N = pl->N;
@@ -1532,10 +1567,10 @@ static void set_ktile(isg_plan* pl, int t1) {
   }
   if (pl->ndim == 3) {
     const int ts[3] = {pl->C > 16 ? 4 : 8, t1, 8};
-    for (int i = 0; i < 3; ++i) pl->ktile.TS[i] = std::min(ts[i], pl->G[i]);
+    for (int i = 0; i < 3; ++i) pl->ktile.TS[i] = spread_extent(ts[i], pl->G[i]);
   } else {
     const int ts[2] = {16, t1};
-    for (int i = 0; i < 2; ++i) pl->ktile.TS[i] = std::min(ts[i], pl->G[i]);
+    for (int i = 0; i < 2; ++i) pl->ktile.TS[i] = spread_extent(ts[i], pl->G[i]);
   }
   for (int i = 0; i < pl->ndim; ++i)  // tap runs reach at most two tiles per axis (axis_tiles)
     if (pl->ktile.TS[i] < kWidth && pl->ktile.TS[i] < pl->G[i])
@@ -1646,8 +1681,8 @@ static void build_units(isg_plan* pl, isg_traj* tr) {
   if (units.empty()) units.push_back(KUnit{0, 0, 0, -1, -1});  // keep the launch non-empty
   HIP_OK(hipStreamSynchronize(pl->stream));
   pl->generation++;
-  if (tr->units) HIP_OK(hipFree(tr->units));
-  if (tr->splits) HIP_OK(hipFree(tr->splits));
+  HIP_OK(dfree(pl, tr->units));
+  HIP_OK(dfree(pl, tr->splits));
   tr->units = nullptr;
   tr->splits = nullptr;
   tr->units = (KUnit*)dmalloc(pl, sizeof(KUnit) * units.size());
@@ -1664,7 +1699,7 @@ static void build_units(isg_plan* pl, isg_traj* tr) {
 // free a device array of a trajectory (its memory leaves the plan's count)
 static void traj_free(isg_plan* pl, void*& p) {
   if (p) {
-    HIP_OK(hipFree(p));
+    HIP_OK(dfree(pl, p));
     p = nullptr;
   }
 }
@@ -1836,7 +1871,7 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
 static bool good_length(int64_t n) {
   if (n < 8 || n > 512 || (n & 1)) return false;
   std::vector<int> R;
-  return factor_235((int)n, R) && factor_235((int)(2 * n), R);
+  return factor_radices((int)n, R) && factor_radices((int)(2 * n), R);
 }
 
 static isg_status check_plan(const isg_plan* pl) {
@@ -2099,10 +2134,14 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
   if (desc->nphases < 1 || desc->nphases > 1024) return fail(ISG_ERR_INVALID_ARG, "nphases must be in 1..1024");
   if (desc->storage < ISG_STORE_FP32 || desc->storage > ISG_STORE_FP16)
     return fail(ISG_ERR_INVALID_ARG, "unknown storage type");
+  if (desc->alpha != kAlpha) return fail(ISG_ERR_UNSUPPORTED_SHAPE, "alpha (oversampling) must be 2");
+  if (desc->width != kWidth) return fail(ISG_ERR_UNSUPPORTED_SHAPE, "width (kernel taps per axis) must be 4");
+  if (!(desc->beta <= 0.0) && !(std::fabs(desc->beta - kb_beta()) <= 1e-9 * kb_beta()))
+    return fail(ISG_ERR_UNSUPPORTED_SHAPE, "beta must be <= 0 (the default Kaiser-Bessel shape) or equal to it");
   for (int i = 0; i < desc->ndim; ++i)
     if (!good_length(desc->n[i]))
       return fail(ISG_ERR_UNSUPPORTED_SHAPE,
-                  "each n_i must be even, in 8..512, with prime factors 2, 3, 5 only (got " +
+                  "each n_i must be even, in 8..512, with prime factors 2, 3, 5, 7 only (got " +
                       std::to_string((long long)desc->n[i]) + ")");
   {  // the coil passes hold all C coils of a line: C * 2 n_last <= 8192
     const int64_t Gl = 2 * desc->n[desc->ndim - 1];
@@ -2150,7 +2189,7 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
   }
   const int wts = pl->ndim == 3 ? 8 : 16;
   for (int i = 0; i < pl->ndim; ++i) {
-    pl->wtile.TS[i] = std::min(wts, pl->G[i]);
+    pl->wtile.TS[i] = spread_extent(wts, pl->G[i]);
     pl->wtile.nt[i] = (pl->G[i] + pl->wtile.TS[i] - 1) / pl->wtile.TS[i];
   }
   // dense planes of complex values; plane size = 4 (mod 16) staggers the
@@ -2214,7 +2253,11 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
 
 isg_status isg_plan_destroy(isg_plan* pl) {
   if (!pl) return ISG_OK;
-  if (pl->stream || true) (void)hipStreamSynchronize(pl->stream);
+  (void)hipStreamSynchronize(pl->stream);
+  // motions and trajectories that outlive the plan keep their own device
+  // memory until their destroy call, which then touches no plan state
+  for (isg_motion* mo : pl->motions) mo->plan = nullptr;
+  for (isg_traj* tr : pl->trajs) tr->plan = nullptr;
   for (void* p : pl->owned) (void)hipFree(p);
   if (pl->ngraph.exec) (void)hipGraphExecDestroy(pl->ngraph.exec);
   if (pl->ngraph.graph) (void)hipGraphDestroy(pl->ngraph.graph);
@@ -2286,6 +2329,7 @@ isg_status isg_motion_create(isg_plan* pl, const float* d, isg_motion** out) {
   isg_motion* mo = new (std::nothrow) isg_motion();
   if (!mo) return fail(ISG_ERR_OUT_OF_MEMORY, "host allocation failed");
   mo->plan = pl;
+  pl->motions.insert(mo);
   st = guarded(pl, [&]() { return prepare_motion(pl, d, mo); });
   if (st != ISG_OK) {
     isg_motion_destroy(mo);
@@ -2297,12 +2341,13 @@ isg_status isg_motion_create(isg_plan* pl, const float* d, isg_motion** out) {
 
 isg_status isg_motion_destroy(isg_motion* mo) {
   if (!mo) return ISG_OK;
-  if (mo->plan) {
-    (void)hipStreamSynchronize(mo->plan->stream);
-    mo->plan->generation++;
+  isg_plan* pl = mo->plan;
+  if (pl) {
+    (void)hipStreamSynchronize(pl->stream);
+    pl->generation++;
+    pl->motions.erase(mo);
   }
-  for (void* p : {(void*)mo->d, (void*)mo->tile_off, (void*)mo->vox})
-    if (p) (void)hipFree(p);
+  for (void* p : {(void*)mo->d, (void*)mo->tile_off, (void*)mo->vox}) (void)dfree(pl, p);
   delete mo;
   return ISG_OK;
 }
@@ -2316,6 +2361,7 @@ isg_status isg_traj_create(isg_plan* pl, const float* k, int64_t M, isg_traj** o
   isg_traj* tr = new (std::nothrow) isg_traj();
   if (!tr) return fail(ISG_ERR_OUT_OF_MEMORY, "host allocation failed");
   tr->plan = pl;
+  pl->trajs.insert(tr);
   st = guarded(pl, [&]() { return prepare_traj(pl, k, M, tr); });
   if (st != ISG_OK) {
     isg_traj_destroy(tr);
@@ -2327,13 +2373,15 @@ isg_status isg_traj_create(isg_plan* pl, const float* k, int64_t M, isg_traj** o
 
 isg_status isg_traj_destroy(isg_traj* tr) {
   if (!tr) return ISG_OK;
-  if (tr->plan) {
-    (void)hipStreamSynchronize(tr->plan->stream);
-    tr->plan->generation++;
+  isg_plan* pl = tr->plan;
+  if (pl) {
+    (void)hipStreamSynchronize(pl->stream);
+    pl->generation++;
+    pl->trajs.erase(tr);
   }
   for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->gorder, (void*)tr->units, (void*)tr->splits,
                   (void*)tr->colmask, (void*)tr->colbase, (void*)tr->taps_v, (void*)tr->vis_off, (void*)tr->vis})
-    if (p) (void)hipFree(p);
+    (void)dfree(pl, p);
   delete tr;
   return ISG_OK;
 }
@@ -2342,7 +2390,7 @@ isg_status isg_traj_info(const isg_traj* tr, int64_t* nvisits, int64_t* ntiles, 
   if (!tr || !nvisits || !ntiles || !tile_points) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
   *nvisits = tr->nvis;
   *ntiles = tr->ntouched;
-  *tile_points = tr->plan->ktile.vol;
+  *tile_points = (int64_t)tr->ts[0] * tr->ts[1] * tr->ts[2];  // no plan access: the plan may be gone
   return ISG_OK;
 }
 

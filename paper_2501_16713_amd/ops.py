@@ -10,6 +10,7 @@ p holding [M_p][C].
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 
 import torch
 
@@ -53,6 +54,7 @@ class Motion:
         check(plan.lib.isg_motion_create(plan.handle, _ptr(d), C.byref(h)))
         self.handle = h
         self.d = d
+        plan._dependents.add(self)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -78,6 +80,7 @@ class Traj:
         h = C.c_void_p()
         check(plan.lib.isg_traj_create(plan.handle, _ptr(k), self.M, C.byref(h)))
         self.handle = h
+        plan._dependents.add(self)
 
     def info(self) -> dict:
         """{"visits": (sample, tile) spread visits, "tiles": touched spread
@@ -101,14 +104,17 @@ class Traj:
 class Plan:
     """Shape, tables and scratch for one image geometry.
 
-    shape: image shape (2D or 3D, even lengths 8..512 with factors 2, 3, 5);
+    shape: image shape (2D or 3D, even lengths 8..512 with factors 2, 3, 5, 7);
     ncoils / nphases: coil count and most states per call; storage: element
-    type of the coil-expanded k-space grids ("fp32", "bf16", "fp16").
+    type of the coil-expanded k-space grids ("fp32", "bf16", "fp16");
+    alpha / width / beta: oversampling, kernel width and Kaiser-Bessel shape
+    (only 2, 4 and the default beta, given as <= 0, are supported).
     """
 
     def __init__(self, shape, ncoils: int = 1, nphases: int = 1, storage: str = "fp32",
-                 device=None):
+                 device=None, alpha: int = 2, width: int = 4, beta: float = 0.0):
         self.lib = _lib.load()
+        self._dependents = weakref.WeakSet()  # live Motion / Traj objects
         self.shape = tuple(int(s) for s in shape)
         self.ndim = len(self.shape)
         self.ncoils = int(ncoils)
@@ -119,6 +125,9 @@ class Plan:
         desc.ndim = self.ndim
         for i, s in enumerate(self.shape):
             desc.n[i] = s
+        desc.alpha = int(alpha)
+        desc.width = int(width)
+        desc.beta = float(beta)
         desc.ncoils = self.ncoils
         desc.nphases = self.nphases
         desc.storage = _lib.STORAGE[storage]
@@ -130,7 +139,10 @@ class Plan:
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
+        """Destroy the plan, after the motions and trajectories still open on it."""
         if getattr(self, "handle", None):
+            for dep in list(getattr(self, "_dependents", ())):
+                dep.close()
             self.lib.isg_plan_destroy(self.handle)
             self.handle = None
 

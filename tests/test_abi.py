@@ -2,8 +2,10 @@
 every function include/isg.h declares, and rejects bad arguments before any
 device work.  No compute call is made here."""
 import ctypes as C
+import math
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -39,11 +41,14 @@ def test_version_and_empty_error():
     assert isinstance(lib.isg_last_error().decode(), str)
 
 
-def _desc(ndim=3, n=(16, 16, 16), C_=2, P=1, storage=0):
+def _desc(ndim=3, n=(16, 16, 16), C_=2, P=1, storage=0, alpha=2, width=4, beta=0.0):
     d = _lib.isg_plan_desc()
     d.ndim = ndim
     for i, v in enumerate(n):
         d.n[i] = v
+    d.alpha = alpha
+    d.width = width
+    d.beta = beta
     d.ncoils = C_
     d.nphases = P
     d.storage = storage
@@ -58,8 +63,11 @@ def _desc(ndim=3, n=(16, 16, 16), C_=2, P=1, storage=0):
     (dict(C_=33), 1),
     (dict(P=0), 1),
     (dict(storage=7), 1),
-    (dict(n=(16, 14, 16)), 2),   # prime factor 7
+    (dict(n=(16, 22, 16)), 2),   # prime factor 11
     (dict(n=(16, 15, 16)), 2),   # odd
+    (dict(alpha=3), 2),          # oversampling other than 2
+    (dict(width=6), 2),          # kernel width other than 4
+    (dict(beta=5.0), 2),         # a Kaiser-Bessel shape other than the default
     (dict(n=(6, 16, 16)), 2),    # too small
     (dict(n=(1024, 16, 16)), 2), # too large
     (dict(n=(16, 16, 512), C_=16), 2),  # coils x 2 n_last > 8192
@@ -104,3 +112,37 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         _lib.load(str(tmp_path / "nope.so"))
+
+
+@needs_lib
+@pytest.mark.parametrize("kw", [dict(n=(14, 28, 16)), dict(beta=-1.0),
+                                dict(beta=math.pi * math.sqrt(4 * 1.5 ** 2 - 0.8))])
+def test_plan_create_accepts(kw):
+    """radix-7 lengths, beta <= 0 and the default beta itself pass validation
+    (on a host without a GPU the call then stops at the device check)"""
+    lib = _lib.load()
+    cnt = C.c_int(0)
+    lib.isg_device_count(C.byref(cnt))
+    h = C.c_void_p()
+    d = _desc(**kw)
+    st = lib.isg_plan_create(C.byref(d), C.byref(h))
+    assert st == (0 if cnt.value > 0 else 4), lib.isg_last_error().decode()
+    if h.value:
+        assert lib.isg_plan_destroy(h) == 0
+
+
+def test_plan_desc_layout_matches_header(tmp_path):
+    """the ctypes mirror of isg_plan_desc has the C struct's size and field
+    offsets (compiled from include/isg.h with the host C compiler)"""
+    fields = [f[0] for f in _lib.isg_plan_desc._fields_]
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("%s %zu\\n", "{f}", offsetof(isg_plan_desc, {f}));\n' for f in fields)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "isg.h"\nint main(void) {\n'
+                   '  printf("size %zu\\n", sizeof(isg_plan_desc));\n' + body + '  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                      check=True).stdout.splitlines())
+    assert int(out["size"]) == C.sizeof(_lib.isg_plan_desc)
+    for f in fields:
+        assert int(out[f]) == getattr(_lib.isg_plan_desc, f).offset, f

@@ -188,13 +188,20 @@ def _cg_problem(isg):
     return shape, inp, plan, S, mots, trs, y
 
 
-# lambda_max of this problem's normal operator is about 52 (power iteration
-# on the oracle), so kappa = (52 + lambda)/lambda.  The FP32 normal operator
-# differs from the FP64 one by delta ~ 1e-6 relative (its parity test); CG
-# amplifies a perturbation of the operator by at most ~ k * kappa * delta
-# after k iterations, which bounds how far the FP32 iterate may drift.
-def _cg_tol(lam, iters=8, delta=1e-6):
-    return iters * (52.0 + lam) / lam * delta
+# Bounds on the FP32 CG iterate's relative distance from the FP64 oracle's
+# after 8 iterations.  lambda_max of this problem's normal operator is about
+# 52 (power iteration on the oracle), so kappa = (52 + lambda)/lambda is 11.4,
+# 105 and 5200; CG amplifies the FP32 operator's ~1e-6 relative error by up
+# to about k kappa.  The measured errors on MI355X are 9.8e-6, 6.0e-5 and
+# 5.3e-4 (x0 = 0) and 1.3e-6 (x0 != 0, lambda 0.5, 5 iterations); each bound
+# is about 5x its measured value, so a defect of a few 1e-4 relative in one
+# iteration fails.
+_CG_TOL = {5.0: 5e-5, 0.5: 3e-4, 1e-2: 3e-3}
+_CG_TOL_X0 = 1e-5
+
+
+def _cg_tol(lam):
+    return _CG_TOL[lam]
 
 
 @pytest.mark.parametrize("lam", [5.0, 0.5, 1e-2])
@@ -208,19 +215,20 @@ def test_cg_solve(isg, lam):
     b = oracle.sense.sense_adjoint(yo, inp["d"], inp["S"], inp["k"], shape)
     xo, ho = oracle.cg.cg(lambda v: oracle.sense.normal(v, lam, inp["d"], inp["S"], inp["k"]), b, iters)
     e = rel(x.cpu().numpy(), xo)
+    eh = float(np.max(np.abs(np.array(hist) - ho)) / ho[0])
     say(f"  iterate rel err {e:.2e}; residual history rel err "
-        f"{np.max(np.abs(np.array(hist) - ho) / np.array(ho)):.2e}")
+        f"{np.max(np.abs(np.array(hist) - ho) / np.array(ho)):.2e}, against ||r_0|| {eh:.2e}")
     assert e < tol
-    # the recursively updated residual carries the same absolute error,
-    # measured against the initial residual
-    assert np.max(np.abs(np.array(hist) - ho)) < tol * ho[0]
+    # the recursively updated residual norms, against the initial residual
+    # (FP64 inner products of FP32 vectors: about 1e-6 per iteration)
+    assert eh < max(tol, 1e-4)
 
 
 def test_cg_from_nonzero_start(isg):
     """CG from x0 != 0 (r0 = b - N x0 needs an application of N; from x0 = 0
     the solver skips it) against the oracle's CG from the same x0"""
     lam, iters = 0.5, 5
-    tol = _cg_tol(lam, iters)
+    tol = _CG_TOL_X0
     shape, inp, plan, S, mots, trs, y = _cg_problem(isg)
     g = np.random.default_rng(11)
     x0 = 0.1 * _rand_c(g, shape)
@@ -237,13 +245,15 @@ def test_cg_from_nonzero_start(isg):
 
 def test_cg_graph_replay_matches_eager(isg, monkeypatch):
     """the HIP-graph replay of a CG iteration equals eager launches"""
+    import torch
     shape, inp, plan, S, mots, trs, y = _cg_problem(isg)
     xg, hg = plan.cg_solve(to_dev(y), mots, S, trs, 0.1, 6)
     monkeypatch.setenv("ISG_NO_GRAPH", "1")
     xe, he = plan.cg_solve(to_dev(y), mots, S, trs, 0.1, 6)
-    # only the LDS-atomic summation order of the spreads differs
-    assert rel(xg.cpu().numpy(), xe.cpu().numpy()) < 1e-5
-    assert np.allclose(hg, he, rtol=1e-5)
+    # the same kernels in the same order with fixed-order reductions (the
+    # spreads use no atomics): replay and eager launches agree bit for bit
+    assert torch.equal(xg, xe)
+    assert hg == he
 
 
 def test_cg_breakdown_is_reported(isg):

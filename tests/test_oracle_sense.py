@@ -97,6 +97,31 @@ def test_cg_iterates_are_krylov_galerkin_solutions():
         assert np.linalg.norm(x - want) <= 1e-8 * np.linalg.norm(want)
 
 
+def test_cg_from_nonzero_start_is_shifted_galerkin_solution():
+    """from x0 != 0 the iterates are x0 plus the Galerkin solution of
+    N e = r0 = b - N x0 over the Krylov space of r0 (a dropped or sign-flipped
+    N x0 term in r0 fails this), and they still converge to the direct solve"""
+    shape = (4, 4, 4)
+    g, ds, S, ks = _problem(shape, C=2, P=2, M=(20, 30), seed=5)
+    lam = 0.05
+    Nd = _dense_normal(shape, lam, ds, S, ks)
+    b = _rand_c(g, shape).reshape(-1)
+    x0 = 0.7 * _rand_c(g, shape).reshape(-1)
+    r0 = b - Nd @ x0
+    for iters in (1, 3, 6):
+        x, hist = cg.cg(lambda v: Nd @ v, b, iters, x0=x0)
+        K = [r0]
+        for _ in range(iters - 1):
+            K.append(Nd @ K[-1])
+        V, _ = np.linalg.qr(np.stack(K, axis=1))
+        want = x0 + V @ np.linalg.solve(V.conj().T @ Nd @ V, V.conj().T @ r0)
+        assert np.linalg.norm(x - want) <= 1e-8 * np.linalg.norm(want)
+        assert abs(hist[0] - np.linalg.norm(r0)) <= 1e-12 * np.linalg.norm(r0)
+    x, _ = cg.cg(lambda v: Nd @ v, b, 200, x0=x0)
+    want = np.linalg.solve(Nd, b)
+    assert np.linalg.norm(x - want) <= 1e-8 * np.linalg.norm(want)
+
+
 def test_cg_converges_to_direct_solve():
     shape = (4, 4, 2)
     g, ds, S, ks = _problem(shape, C=2, P=2, M=(20, 30), seed=4)
