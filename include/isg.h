@@ -244,6 +244,20 @@ isg_status isg_warp(isg_plan* plan, const isg_motion* d, const void* x, void* y)
 /* x = T_d^H y, adjoint image-space gridding (Eq. 7-8); out-of-place. */
 isg_status isg_warp_adjoint(isg_plan* plan, const isg_motion* d, const void* y, void* x);
 
+/* x = T_d^H y exactly as isg_warp_adjoint computes it (same kernels, same
+ * result bit for bit), for callers that cannot allocate device memory while
+ * they run: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The call allocates nothing: the oversampled grid
+ * and the FFT intermediates live in one fixed 64 MiB device array of the
+ * library (held on every GPU the library runs on until the process ends),
+ * which fits 8 (|G| + G0 G1 n2 + G0 n1 n2 + |N|) bytes plus alignment:
+ * every 2D shape, 3D up to about 80^3 voxels.  Larger shapes fail with
+ * INVALID_ARG (use isg_warp_adjoint).  The plan's device must be current.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams or threads, without ordering between them) race
+ * and give wrong results.  Asynchronous on the plan's stream. */
+isg_status isg_warp_adjoint_noalloc(isg_plan* plan, const isg_motion* d, const void* y, void* x);
+
 /* grad[i][r] = Re(conj(v[r]) * d(T_d x)[r] / d d_i[r]): the gradient of
  * Re<v, T_d x> with respect to the displacement field, which is what a
  * registration or motion-refinement loss needs by the chain rule.

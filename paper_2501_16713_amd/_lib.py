@@ -41,6 +41,7 @@ SIGNATURES = {
     "isg_traj_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)]),
     "isg_warp": (C.c_int, [_p, _p, _p, _p]),
     "isg_warp_adjoint": (C.c_int, [_p, _p, _p, _p]),
+    "isg_warp_adjoint_noalloc": (C.c_int, [_p, _p, _p, _p]),
     "isg_warp_grad_d": (C.c_int, [_p, _p, _p, _p, _p]),
     "isg_sense_forward": (C.c_int, [_p, C.c_int, _p, _p, _p, _p, _p]),
     "isg_sense_adjoint": (C.c_int, [_p, C.c_int, _p, _p, _p, _p, _p]),

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <new>
 #include <string>
@@ -728,7 +729,15 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
 }
 
 // adjoint of upsample (Eq. 8 after the spread): x = F^H_N (1/C) Z^H F_G U / |N|
-static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
+// Intermediate images of the adjoint upsampling passes: A [n0][n1][n2],
+// B [G0][n1][n2], C [G0][G1][n2] (C unused in 2D).
+struct UpBufs {
+  float2 *A, *B, *C;
+};
+
+static UpBufs plan_up_bufs(const isg_plan* pl);
+
+static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out, const UpBufs& ub) {
   const int n0 = pl->n[0], n1 = pl->n[1], n2 = pl->n[2];
   const int G0 = pl->G[0], G1 = pl->G[1], G2 = pl->G[2];
   UpHMid mid;
@@ -742,43 +751,43 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
     // register FFTs along axes 2 and 1 where the length allows (as in upsample)
     if (fft2_supported(G2)) {  // F along axis 2, crop
       run_fft2<-1, kJFast, kJFast, 2>(pl, "fft_uph_G2", G2, ld2_img(pl, U, G2, 1, kDense, G2),
-                                      st2_img(pl->bufC, n2, 1, kSpectral), make_tile2((int64_t)G0 * G1, 1, G2, 1));
+                                      st2_img(ub.C, n2, 1, kSpectral), make_tile2((int64_t)G0 * G1, 1, G2, 1));
     } else {
       TileGeom g = make_geom((int64_t)G0 * G1, 1, G2, 0);
       run_pass(pl, "fft_uph_G2", ld_strided<kFP32>(U, G2, 1, G2, G2, kDense, g), NoMid(),
-               st_strided<kFP32>(pl->bufC, n2, 1, n2, G2, kSpectral, g), g, line_plan(pl, G2), -1.f, nullptr, 0.f);
+               st_strided<kFP32>(ub.C, n2, 1, n2, G2, kSpectral, g), g, line_plan(pl, G2), -1.f, nullptr, 0.f);
     }
     if (fft2_supported(G1)) {  // F along axis 1, crop
       run_fft2<-1, kBFast, kBFast, 2>(pl, "fft_uph_G1", G1,
-                                      ld2_img(pl, pl->bufC, (int64_t)G1 * n2, n2, kDense, G1),
-                                      st2_img(pl->bufB, (int64_t)n1 * n2, n2, kSpectral), make_tile2(G0, n2, G1, 0));
+                                      ld2_img(pl, ub.C, (int64_t)G1 * n2, n2, kDense, G1),
+                                      st2_img(ub.B, (int64_t)n1 * n2, n2, kSpectral), make_tile2(G0, n2, G1, 0));
     } else {
       TileGeom g = make_geom(G0, n2, G1, 0);
-      run_pass(pl, "fft_uph_G1", ld_strided<kFP32>(pl->bufC, (int64_t)G1 * n2, n2, G1, G1, kDense, g), NoMid(),
-               st_strided<kFP32>(pl->bufB, (int64_t)n1 * n2, n2, n1, G1, kSpectral, g), g, line_plan(pl, G1), -1.f,
+      run_pass(pl, "fft_uph_G1", ld_strided<kFP32>(ub.C, (int64_t)G1 * n2, n2, G1, G1, kDense, g), NoMid(),
+               st_strided<kFP32>(ub.B, (int64_t)n1 * n2, n2, n1, G1, kSpectral, g), g, line_plan(pl, G1), -1.f,
                nullptr, 0.f);
     }
     {  // F along axis 0, crop, deapodize, F^H of length n0
       TileGeom g = make_geom(1, (int64_t)n1 * n2, G0, 0);
-      run_pass(pl, "fft_uph_ax0", ld_strided<kFP32>(pl->bufB, 0, (int64_t)n1 * n2, G0, G0, kDense, g), mid,
-               st_strided<kFP32>(pl->bufA, 0, (int64_t)n1 * n2, n0, n0, kDense, g), g, line_plan(pl, G0), -1.f,
+      run_pass(pl, "fft_uph_ax0", ld_strided<kFP32>(ub.B, 0, (int64_t)n1 * n2, G0, G0, kDense, g), mid,
+               st_strided<kFP32>(ub.A, 0, (int64_t)n1 * n2, n0, n0, kDense, g), g, line_plan(pl, G0), -1.f,
                &line_plan(pl, n0), +1.f);
     }
     if (fft2_supported(n1)) {  // F^H along axis 1, in place
-      run_fft2<+1, kBFast, kBFast>(pl, "fft_uph_ax1", n1, ld2_img(pl, pl->bufA, (int64_t)n1 * n2, n2, kDense, n1),
-                                   st2_img(pl->bufA, (int64_t)n1 * n2, n2, kDense), make_tile2(n0, n2, n1, 0));
+      run_fft2<+1, kBFast, kBFast>(pl, "fft_uph_ax1", n1, ld2_img(pl, ub.A, (int64_t)n1 * n2, n2, kDense, n1),
+                                   st2_img(ub.A, (int64_t)n1 * n2, n2, kDense), make_tile2(n0, n2, n1, 0));
     } else {
       TileGeom g = make_geom(n0, n2, n1, 0);
-      run_pass(pl, "fft_uph_ax1", ld_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
-               st_strided<kFP32>(pl->bufA, (int64_t)n1 * n2, n2, n1, n1, kDense, g), g, line_plan(pl, n1), +1.f,
+      run_pass(pl, "fft_uph_ax1", ld_strided<kFP32>(ub.A, (int64_t)n1 * n2, n2, n1, n1, kDense, g), NoMid(),
+               st_strided<kFP32>(ub.A, (int64_t)n1 * n2, n2, n1, n1, kDense, g), g, line_plan(pl, n1), +1.f,
                nullptr, 0.f);
     }
     if (fft2_supported(n2)) {  // F^H along axis 2
-      run_fft2<+1, kJFast, kJFast>(pl, "fft_uph_ax2", n2, ld2_img(pl, pl->bufA, n2, 1, kDense, n2),
+      run_fft2<+1, kJFast, kJFast>(pl, "fft_uph_ax2", n2, ld2_img(pl, ub.A, n2, 1, kDense, n2),
                                    st2_img(out, n2, 1, kDense), make_tile2((int64_t)n0 * n1, 1, n2, 1));
     } else {
       TileGeom g = make_geom((int64_t)n0 * n1, 1, n2, 0);
-      run_pass(pl, "fft_uph_ax2", ld_strided<kFP32>(pl->bufA, n2, 1, n2, n2, kDense, g), NoMid(),
+      run_pass(pl, "fft_uph_ax2", ld_strided<kFP32>(ub.A, n2, 1, n2, n2, kDense, g), NoMid(),
                st_strided<kFP32>(out, n2, 1, n2, n2, kDense, g), g, line_plan(pl, n2), +1.f, nullptr, 0.f);
     }
   } else {
@@ -786,27 +795,33 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
     mid.three_d = 0;
     if (fft2_supported(G1)) {
       run_fft2<-1, kJFast, kJFast, 2>(pl, "fft_uph_G1", G1, ld2_img(pl, U, G1, 1, kDense, G1),
-                                      st2_img(pl->bufB, n1, 1, kSpectral), make_tile2(G0, 1, G1, 1));
+                                      st2_img(ub.B, n1, 1, kSpectral), make_tile2(G0, 1, G1, 1));
     } else {
       TileGeom g = make_geom(G0, 1, G1, 0);
       run_pass(pl, "fft_uph_G1", ld_strided<kFP32>(U, G1, 1, G1, G1, kDense, g), NoMid(),
-               st_strided<kFP32>(pl->bufB, n1, 1, n1, G1, kSpectral, g), g, line_plan(pl, G1), -1.f, nullptr, 0.f);
+               st_strided<kFP32>(ub.B, n1, 1, n1, G1, kSpectral, g), g, line_plan(pl, G1), -1.f, nullptr, 0.f);
     }
     {
       TileGeom g = make_geom(1, n1, G0, 0);
-      run_pass(pl, "fft_uph_ax0", ld_strided<kFP32>(pl->bufB, 0, n1, G0, G0, kDense, g), mid,
-               st_strided<kFP32>(pl->bufA, 0, n1, n0, n0, kDense, g), g, line_plan(pl, G0), -1.f, &line_plan(pl, n0),
+      run_pass(pl, "fft_uph_ax0", ld_strided<kFP32>(ub.B, 0, n1, G0, G0, kDense, g), mid,
+               st_strided<kFP32>(ub.A, 0, n1, n0, n0, kDense, g), g, line_plan(pl, G0), -1.f, &line_plan(pl, n0),
                +1.f);
     }
     if (fft2_supported(n1)) {
-      run_fft2<+1, kJFast, kJFast>(pl, "fft_uph_ax1", n1, ld2_img(pl, pl->bufA, n1, 1, kDense, n1),
+      run_fft2<+1, kJFast, kJFast>(pl, "fft_uph_ax1", n1, ld2_img(pl, ub.A, n1, 1, kDense, n1),
                                    st2_img(out, n1, 1, kDense), make_tile2(n0, 1, n1, 1));
     } else {
       TileGeom g = make_geom(n0, 1, n1, 0);
-      run_pass(pl, "fft_uph_ax1", ld_strided<kFP32>(pl->bufA, n1, 1, n1, n1, kDense, g), NoMid(),
+      run_pass(pl, "fft_uph_ax1", ld_strided<kFP32>(ub.A, n1, 1, n1, n1, kDense, g), NoMid(),
                st_strided<kFP32>(out, n1, 1, n1, n1, kDense, g), g, line_plan(pl, n1), +1.f, nullptr, 0.f);
     }
   }
+}
+
+static UpBufs plan_up_bufs(const isg_plan* pl) { return UpBufs{pl->bufA, pl->bufB, pl->bufC}; }
+
+static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out) {
+  upsample_adjoint(pl, U, out, plan_up_bufs(pl));
 }
 
 // ---------------------------------------------------------------------------
@@ -2107,6 +2122,51 @@ static isg_status tune(isg_plan* pl, int P, const float2* x, const isg_motion* c
 }
 
 // ---------------------------------------------------------------------------
+// allocation-free variant of the warp adjoint: its oversampled grid and FFT
+// intermediates live in a fixed device array instead of plan memory
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+// Never pass `scratch` itself to a kernel or a copy: in host code the name is
+// a host-side stand-in.  static_scratch() returns the device address.
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;  // device ordinal -> address of that device's copy
+
+// device address of the current device's copy of `scratch`, looked up once
+// per device (each GPU holds its own copy at its own address)
+static void* static_scratch() {
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) throw HipError{hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch) returned NULL"};
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+
+// byte offsets of the warp-adjoint buffers inside the static scratch: U
+// [G...], then C, B, A of the adjoint upsampling passes, each 256-aligned
+struct StaticLayout {
+  size_t u, a, b, c, total;
+};
+static StaticLayout static_layout(const isg_plan* pl) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t e = sizeof(float2);
+  StaticLayout L;
+  L.u = 0;
+  L.c = up(L.u + e * (size_t)pl->NG);
+  const size_t cb = pl->ndim == 3 ? e * (size_t)pl->G[0] * pl->G[1] * pl->n[2] : 0;
+  L.b = up(L.c + cb);
+  L.a = up(L.b + e * (size_t)pl->G[0] * pl->n[1] * pl->n[2]);
+  L.total = up(L.a + e * (size_t)pl->N);
+  return L;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -2423,6 +2483,31 @@ isg_status isg_warp_adjoint(isg_plan* pl, const isg_motion* d, const void* y, vo
     const float2* w = (const float2*)y;
     warp_spread(pl, 1, &d, &w, pl->ugrid);
     upsample_adjoint(pl, pl->ugrid, (float2*)x);
+    return ISG_OK;
+  });
+}
+
+isg_status isg_warp_adjoint_noalloc(isg_plan* pl, const isg_motion* d, const void* y, void* x) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!d || !x || !y) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (d->plan != pl) return fail(ISG_ERR_INVALID_ARG, "motion belongs to another plan");
+  if (x == y) return fail(ISG_ERR_INVALID_ARG, "warp_adjoint is out-of-place: x must differ from y");
+  const StaticLayout L = static_layout(pl);
+  if (L.total > kStaticScratchBytes)
+    return fail(ISG_ERR_INVALID_ARG, "isg_warp_adjoint_noalloc: the shape needs " + std::to_string(L.total >> 20) +
+                                         " MiB of scratch, more than the fixed 64 MiB (use isg_warp_adjoint)");
+  return guarded(pl, [&]() -> isg_status {
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != pl->device) return fail(ISG_ERR_INVALID_ARG, "the plan's device must be current");
+    char* base = (char*)static_scratch();
+    float2* U = (float2*)(base + L.u);
+    const UpBufs ub{(float2*)(base + L.a), (float2*)(base + L.b), pl->ndim == 3 ? (float2*)(base + L.c) : nullptr};
+    const float2* w = (const float2*)y;
+    // the spread writes every cell of U (no accumulation into old contents)
+    warp_spread(pl, 1, &d, &w, U);
+    upsample_adjoint(pl, U, (float2*)x, ub);
     return ISG_OK;
   });
 }

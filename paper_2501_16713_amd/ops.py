@@ -245,6 +245,16 @@ class Plan:
         check(self.lib.isg_warp_adjoint(self.handle, motion.handle, _ptr(y), _ptr(out)))
         return out
 
+    def warp_adjoint_noalloc(self, y: torch.Tensor, motion: Motion, out: torch.Tensor) -> torch.Tensor:
+        """T_d^H y into a caller-supplied `out`, with the library's fixed
+        device scratch instead of plan memory (allocates nothing; shapes up to
+        the scratch's 64 MiB, see include/isg.h)."""
+        y = self._image(y, "y")
+        out = self._image(out, "out")
+        self._sync_stream()
+        check(self.lib.isg_warp_adjoint_noalloc(self.handle, motion.handle, _ptr(y), _ptr(out)))
+        return out
+
     def warp_grad_d(self, x: torch.Tensor, v: torch.Tensor, motion: Motion,
                     out: torch.Tensor | None = None) -> torch.Tensor:
         """Re(conj(v) * d(T_d x)/dd), float32 [ndim][*shape]."""
