@@ -236,6 +236,11 @@ isg_status isg_traj_count(const isg_traj* traj, int64_t* M);
  * visits, of k-space spread tiles any sample touches, and of grid points per
  * tile (for traffic accounting). */
 isg_status isg_traj_info(const isg_traj* traj, int64_t* nvisits, int64_t* ntiles, int64_t* tile_points);
+/* Grid cells (per coil) the axis-0 passes store in the forward direction
+ * and read in the adjoint one: the runs of cells along axis 0 (of the k-space
+ * tile extent along axis 0) that some sample's taps reach, per grid column;
+ * 0 when the path keeps no such masks (every cell is then touched). */
+isg_status isg_traj_touched_cells(const isg_traj* traj, int64_t* cells);
 
 /* y = T_d x, forward image-space gridding (Eq. 9).  x, y: device complex64
  * images; out-of-place (x != y). */
@@ -248,11 +253,11 @@ isg_status isg_warp_adjoint(isg_plan* plan, const isg_motion* d, const void* y, 
  * result bit for bit), for callers that cannot allocate device memory while
  * they run: code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc.  The call allocates nothing: the oversampled grid
- * and the FFT intermediates live in one fixed 64 MiB device array of the
- * library (held on every GPU the library runs on until the process ends),
- * which fits 8 (|G| + G0 G1 n2 + G0 n1 n2 + |N|) bytes plus alignment:
- * every 2D shape, 3D up to about 80^3 voxels.  Larger shapes fail with
- * INVALID_ARG (use isg_warp_adjoint).  The plan's device must be current.
+ * the spread's tile regions and the FFT intermediates live in one fixed
+ * 64 MiB device array of the library (held on every GPU the library runs on
+ * until the process ends), which fits about 290 |N| bytes in 3D and 100 |N|
+ * in 2D: every 2D shape, 3D up to about 60^3 voxels.  Larger shapes fail
+ * with INVALID_ARG (use isg_warp_adjoint).  The plan's device must be current.
  * Every call on one GPU shares that GPU's array: calls that overlap on one
  * GPU (different streams or threads, without ordering between them) race
  * and give wrong results.  Asynchronous on the plan's stream. */

@@ -391,25 +391,21 @@ inline bool half_gap(const Ld2Image<S>& x, int L) { return half_gap(static_cast<
 template <int S>
 inline bool half_gap(const St2Image<S>& x, int L) { return half_gap(static_cast<const St2Strided<S>&>(x), L); }
 
-// Touched-tile masks of a trajectory.  The k-space grid [G0][...][C] is cut
-// into spread tiles; colmask[col] has bit t0 set when some sample's taps
-// touch tile (t0, col), col = (i1 / TS1) nt2 + i2 / TS2 (3D) or i1 / TS1 (2D).
-// Untouched tiles are never read by the gather and are zero after the
-// spread, so the axis-0 passes skip them.
+// Touched-cell masks of a trajectory, read by the axis-0 passes.  Along
+// axis 0 the grid is cut into runs of 2^ts0_log2 cells (the k-space spread
+// tile extent along axis 0).  fmask[(i1, i2)] (i1 alone in 2D) has bit t set
+// when some sample's taps reach a cell of run t of that column: the gather
+// reads no other cell and the spread leaves every other cell zero, so the
+// forward axis-0 pass stores only the marked runs and the adjoint one reads
+// only those.  (A coarser per-tile-column mask, colmask, locates the tiles
+// of the tile-major spread output.)
 struct TileMask {
-  const uint64_t* colmask;  // null: every tile is touched
-  int C, G2, TS1, TS2, nt2, ts0_log2, three_d;
+  const uint64_t* fmask;  // null: every run is touched
+  int C, G2, three_d, ts0_log2;
   __device__ __forceinline__ uint64_t column(int64_t b) const {
-    if (!colmask) return ~0ull;
-    const uint32_t q = (uint32_t)b / (uint32_t)C;  // (i1, i2) flat, or i1 in 2D (< 2^31)
-    uint32_t col;
-    if (three_d) {
-      const uint32_t i1 = q / (uint32_t)G2, i2 = q - i1 * (uint32_t)G2;
-      col = (i1 / (uint32_t)TS1) * (uint32_t)nt2 + i2 / (uint32_t)TS2;
-    } else {
-      col = q / (uint32_t)TS1;
-    }
-    return colmask[col];
+    if (!fmask) return ~0ull;
+    const uint32_t q = (uint32_t)b / (uint32_t)C;  // i1 G2 + i2 in 3D, i1 in 2D (< 2^31)
+    return fmask[q];
   }
 };
 
@@ -463,7 +459,8 @@ struct St2Masked {
 template <int S>
 struct Ld2Tiles {
   const typename Elem<S>::T* p;
-  const uint64_t* colmask;
+  const uint64_t* colmask;  // per tile column: touched tiles (their slots)
+  const uint64_t* fmask;    // per grid column (i1, i2): touched runs along axis 0
   const int* colbase;
   int C, G2, ts0_log2, ts1, ts2, nt2;
   int64_t volC;   // elements per tile
@@ -472,22 +469,23 @@ struct Ld2Tiles {
   const float2* tw;
   struct Line {
     const typename Elem<S>::T* base;
-    uint64_t mask;
+    uint64_t mask;  // touched tiles of the tile column
+    uint64_t fine;  // touched runs of the grid column
   };
   __device__ Line setup(int64_t, int64_t b, bool valid) const {
-    if (!valid) return Line{p, 0ull};
+    if (!valid) return Line{p, 0ull, 0ull};
     const uint32_t q = cdiv.div((uint32_t)b);
     const int c = (int)(b - (int64_t)q * C);
     const uint32_t i1 = g2div.div(q);
     const int i2 = (int)(q - i1 * (uint32_t)G2);
     const int col = (int)(i1 / (uint32_t)ts1) * nt2 + i2 / ts2;
     const int l1 = (int)(i1 % (uint32_t)ts1), l2 = i2 % ts2;
-    return Line{p + (int64_t)colbase[col] * volC + (int64_t)(l1 * ts2 + l2) * C + c, colmask[col]};
+    return Line{p + (int64_t)colbase[col] * volC + (int64_t)(l1 * ts2 + l2) * C + c, colmask[col], fmask[q]};
   }
   template <int L>
   __device__ float2 get(const Line& ln, int pos, bool valid) const {
     const int t0 = pos >> ts0_log2;
-    const bool on = valid && ((ln.mask >> t0) & 1ull);
+    const bool on = valid && ((ln.fine >> t0) & 1ull);
     const int k = __popcll(ln.mask & ((1ull << t0) - 1ull));
     return masked_load<S>(ln.base + (int64_t)k * volC + (int64_t)(pos & ((1 << ts0_log2) - 1)) * rowC, on, tw);
   }

@@ -215,14 +215,41 @@ struct WarpSpreadPhases {
   const float2* w[kMaxPhasesPerLaunch];      // values to spread, [N]
 };
 
-// Image-space spread tile; LDS holds planes of P complex values, point
-// (l0, l1, l2) at l0 * S0 + l1 * S1 + l2.
+// Image-space spread tiles and their regions.  Every (state, voxel) entry
+// belongs to the one tile that holds its first tap along every axis (the tap
+// run b .. b+3 starts in [lo, lo + ext)), so all 4^NDIM of its taps fall in
+// that tile's region: the tile extended by a halo of three cells past its
+// upper faces (wrapping periodically), ext + 3 cells per axis.  The regions
+// of neighbouring tiles overlap in the halos; a second pass sums them.
+// Tile extents are powers of two (at most G/2), and every G is a multiple
+// of 4, so a ragged last tile is at least 4 wide and a cell gets
+// contributions from its own tile and, within three cells above a tile
+// boundary, from the tile below it: at most two tiles per axis.
 struct TileDims {
-  int TS[3];      // tile extent per axis
-  int nt[3];      // tiles per axis
-  int S0, S1;     // plane strides (complex values)
-  int P;          // plane size (complex values), = 4 (mod 16)
+  int TS[3];   // tile extent per axis (power of two)
+  int lg[3];   // log2 TS
+  int nt[3];   // tiles per axis
+  int E[3];    // region extent per axis, TS + 3 (1 on a missing axis)
+  int R0, R1;  // LDS strides of a region copy along axes 0 and 1 (last axis contiguous, rows padded to an
+               // even length so that the 16 taps of one step hit 32 distinct banks)
+  int P;       // LDS region copy size (float2, even)
+  int RV;      // region cells in global memory (E0 E1 E2, compact)
 };
+
+// Wavefronts per workgroup and entries a wavefront stages per round.  Each
+// wavefront accumulates into a region copy of its own.
+constexpr int kWarpWaves = 4;
+constexpr int kWarpStage = 64;
+// entries a wavefront applies per step: in 3D its 64 lanes are the 64 taps
+// of one entry, in 2D four entries of 16 taps (one region copy each)
+template <int NDIM> struct WarpLanes {
+  static constexpr int kEntries = NDIM == 3 ? 1 : 4;
+};
+
+__host__ __device__ inline size_t warp_spread_lds_bytes(const TileDims& td, int ndim) {
+  const int q = ndim == 3 ? WarpLanes<3>::kEntries : WarpLanes<2>::kEntries;
+  return sizeof(float2) * (size_t)kWarpWaves * q * td.P;
+}
 
 // Workgroup index -> tile such that the workgroups of one XCD (consecutive
 // indices go to the 8 XCDs in turn) take one contiguous range of tiles, whose
@@ -233,46 +260,23 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Wavefronts per workgroup and entries a wavefront stages per round.  LDS
-// per wavefront (two tile copies and the staging area) limits a CU to 12 of
-// them; 2 wavefronts staging 32 or 16 entries fit 14 or 16 but were slower
-// (more staging rounds per entry).
-constexpr int kWarpWaves = 4;
-constexpr int kWarpStage = 64;
-// entries a wave applies per step: 3D lanes (entry, t0 half, t1, t2) apply
-// two taps each; 2D lanes (entry, t0, t1) one
-template <int NDIM> struct WarpLanes {
-  static constexpr int kCopies = NDIM == 3 ? 2 : 4;
-  static constexpr int kTapsPerLane = NDIM == 3 ? 2 : 1;
-};
-constexpr int kWarpDump = 64;  // garbage slots for out-of-tile taps
-
-__host__ __device__ inline size_t warp_spread_lds_bytes(const TileDims& td, int ndim) {
-  const int copies = ndim == 3 ? WarpLanes<3>::kCopies : WarpLanes<2>::kCopies;
-  return sizeof(float2) * ((size_t)kWarpWaves * copies * td.P + kWarpDump);
-}
-
-// Image-space spread of one tile, without atomics.  Entries (state, voxel)
-// of the tile, over all states, are cut into batches of kWarpStage; wave w
-// takes batches w, w + kWarpWaves, ...: its first kWarpStage lanes stage one
-// entry each (tap offsets relative to the tile, weights, value) in the
-// wave's LDS staging area, then
-// walk the staged entries several at a time, each entry in an LDS copy of
-// the tile of its own.  The lanes of one entry cover its 64 taps (distinct
-// points), so plain read-modify-write is race free; out-of-tile taps update
-// garbage slots instead of branching.  The copies are summed at the end in a
-// fixed order (deterministic).  The global reads of the staging are
-// software-pipelined: a lane's voxel index is read two rounds ahead and its
-// displacement and value one round ahead, so they are in flight while the
-// wave accumulates the current round.
+// Pass 1 of the image-space spread, without atomics: the entries of one
+// tile over all states (voxel lists from the plan-time binning) are
+// accumulated in LDS copies of the tile's region and the region is written
+// to reg[tile][E0][E1][E2].  Entries are cut into batches of kWarpStage;
+// wave w takes batches w, w + kWarpWaves, ...: its lanes stage one entry
+// each (region offset of the first tap, the per-axis weights, the value),
+// then the wave walks the staged entries, its lanes covering the taps of an
+// entry (distinct cells, so plain read-modify-write is race free).  The
+// copies are summed in a fixed order (deterministic).  The global reads of
+// the staging are software-pipelined: a lane's voxel index is read two
+// rounds ahead and its displacement and value one round ahead.
 template <int NDIM>
-__global__ __launch_bounds__(64 * kWarpWaves) void warp_spread_kernel(WarpSpreadPhases ph, float2* __restrict__ U,
-                                                                   int accumulate, int ntiles, Dims dm,
-                                                                   TileDims td, KbPoly kb) {
-  using WL = WarpLanes<NDIM>;
-  constexpr int Q = WL::kCopies;
-  extern __shared__ float2 accw[];  // [kWarpWaves][Q][P], then [kWarpDump] garbage
-  __shared__ int4 st_off[kWarpWaves][kWarpStage];
+__global__ __launch_bounds__(64 * kWarpWaves) void warp_spread_kernel(WarpSpreadPhases ph, float2* __restrict__ reg,
+                                                                   int ntiles, Dims dm, TileDims td, KbPoly kb) {
+  constexpr int Q = WarpLanes<NDIM>::kEntries;
+  extern __shared__ float2 accw[];  // [kWarpWaves][Q][P]
+  __shared__ int st_off[kWarpWaves][kWarpStage];
   __shared__ float st_w[kWarpWaves][kWarpStage * 12];  // entry s: weights of axis i at 12 s + 4 i + t
   __shared__ float2 st_v[kWarpWaves][kWarpStage];
   __shared__ int s_beg[kMaxPhasesPerLaunch];      // first entry of state p in its voxel list
@@ -289,19 +293,12 @@ __global__ __launch_bounds__(64 * kWarpWaves) void warp_spread_kernel(WarpSpread
   __shared__ GFloat s_w[kMaxPhasesPerLaunch];  // complex values as (re, im) pairs
   const int tile = xcd_contiguous(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
-  float2* dump = accw + (size_t)kWarpWaves * Q * td.P;
-  int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
-  int vol = 1;
+  int lo[3] = {0, 0, 0};
   {
     int t = tile;
     for (int i = NDIM - 1; i >= 0; --i) {
       lo[i] = (t % td.nt[i]) * td.TS[i];
       t /= td.nt[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NDIM; ++i) {
-      ext[i] = min(td.TS[i], dm.G[i] - lo[i]);
-      vol *= td.TS[i];
     }
   }
   {
@@ -327,25 +324,21 @@ __global__ __launch_bounds__(64 * kWarpWaves) void warp_spread_kernel(WarpSpread
   const int E = s_pfx[ph.P];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  // lane roles
-  int q, t0a, ta, tb;  // entry slot, first t0, and the taps of the two faster axes
+  // lane roles: the entry slot of a step and the tap along each axis
+  int q, ta0, ta1, ta2;
   if constexpr (NDIM == 3) {
-    q = lane >> 5;
-    t0a = 2 * ((lane >> 4) & 1);
-    tb = (lane >> 2) & 3;  // t1
-    ta = lane & 3;         // t2
+    q = 0;
+    ta0 = lane >> 4;
+    ta1 = (lane >> 2) & 3;
+    ta2 = lane & 3;
   } else {
     q = lane >> 4;
-    t0a = (lane >> 2) & 3;  // t0
-    tb = 0;
-    ta = lane & 3;  // t1
+    ta0 = (lane >> 2) & 3;
+    ta1 = lane & 3;
+    ta2 = 0;
   }
   float2* copy = accw + (size_t)(wave * Q + q) * td.P;
-  // an out-of-tile tap updates the garbage slot congruent to its would-be
-  // address mod 64 (the same LDS bank), so a step whose taps lie partly
-  // outside the tile keeps the bank pattern of one wholly inside (the slots
-  // hold garbage, so lanes may share one)
-  const int mbase = (wave * Q + q - kWarpWaves * Q) * td.P;
+  const int tapoff = NDIM == 3 ? __mul24(ta0, td.R0) + __mul24(ta1, td.R1) + ta2 : __mul24(ta0, td.R0) + ta1;
   const int nbatch = (E + kWarpStage - 1) / kWarpStage;
   const int rounds = (nbatch + kWarpWaves - 1) / kWarpWaves;
   // the entry this lane stages in round rd: its state and voxel (-1: none)
@@ -385,7 +378,7 @@ __global__ __launch_bounds__(64 * kWarpWaves) void warp_spread_kernel(WarpSpread
     if (lane < ne) {  // stage entry e0 + lane
       int ri[3];
       voxel_coords<NDIM>(r, dm, ri);
-      int off[3] = {0, 0, 0};
+      int off = 0;
 #pragma unroll
       for (int i = 0; i < NDIM; ++i) {
         const float yv = 2.0f * dc[i];
@@ -394,12 +387,11 @@ __global__ __launch_bounds__(64 * kWarpWaves) void warp_spread_kernel(WarpSpread
         kb_weights(kb, yv - fl, w);
 #pragma unroll
         for (int t = 0; t < 4; ++t) st_w[wave][12 * lane + 4 * i + t] = w[t];
-        int o = wrap(2 * ri[i] + (int)fl - 1, dm.G[i], dm.invG[i]) - lo[i];  // nearest periodic image
-        if (o > dm.G[i] / 2) o -= dm.G[i];
-        if (o < -dm.G[i] / 2) o += dm.G[i];
-        off[i] = o;
+        // the binning put the first tap in this tile: 0 <= o < ext
+        const int o = wrap(2 * ri[i] + (int)fl - 1, dm.G[i], dm.invG[i]) - lo[i];
+        off += __mul24(o, i == 0 ? td.R0 : (i == NDIM - 1 ? 1 : td.R1));
       }
-      st_off[wave][lane] = make_int4(off[0], off[1], off[2], 0);
+      st_off[wave][lane] = off;
       st_v[wave][lane] = vc;
     }
     __syncthreads();
@@ -410,65 +402,85 @@ __global__ __launch_bounds__(64 * kWarpWaves) void warp_spread_kernel(WarpSpread
     r2 = voxel_of(rd + 2, p2);
     for (int s = 0; s < ne; s += Q) {
       const int sq = s + q;
-      const bool has = sq < ne;
+      const bool has = sq < ne;  // 2D: a slot past the last entry adds zero
       const int sc = has ? sq : s;
-      const int4 of = st_off[wave][sc];
-      const float2 v = st_v[wave][sc];
-      if constexpr (NDIM == 3) {
-        const int l1 = of.y + tb, l2 = of.z + ta;
-        const bool ok12 = has && (unsigned)l1 < (unsigned)ext[1] && (unsigned)l2 < (unsigned)ext[2];
-        // 24-bit products keep the LDS address arithmetic in 32-bit ALU ops
-        // (out-of-tile offsets give unused addresses; the garbage slot is taken)
-        const int wi = __mul24(sc, 12);
-        const float w12 = st_w[wave][wi + 4 + tb] * st_w[wave][wi + 8 + ta];
-        const int base = __mul24(l1, td.S1) + l2;
-        float2* ptr[2];
-        float2 a[2];
-        float wt[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int l0 = of.x + t0a + j;
-          const bool ok = ok12 && (unsigned)l0 < (unsigned)ext[0];
-          const int off = __mul24(l0, td.S0) + base;
-          ptr[j] = ok ? copy + off : dump + ((mbase + off) & 63);
-          wt[j] = w12 * st_w[wave][wi + t0a + j];
-          a[j] = *ptr[j];
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) *ptr[j] = make_float2(fmaf(wt[j], v.x, a[j].x), fmaf(wt[j], v.y, a[j].y));
-      } else {
-        const int l0 = of.x + t0a, l1 = of.y + ta;
-        const bool ok = has && (unsigned)l0 < (unsigned)ext[0] && (unsigned)l1 < (unsigned)ext[1];
-        const int wi = __mul24(sc, 12);
-        const float ww = st_w[wave][wi + t0a] * st_w[wave][wi + 4 + ta];
-        const int off = __mul24(l0, td.S0) + l1;
-        float2* pt = ok ? copy + off : dump + ((mbase + off) & 63);
-        const float2 a = *pt;
-        *pt = make_float2(fmaf(ww, v.x, a.x), fmaf(ww, v.y, a.y));
-      }
+      const int wi = __mul24(sc, 12);
+      float wt = st_w[wave][wi + ta0] * st_w[wave][wi + 4 + ta1];
+      if constexpr (NDIM == 3) wt *= st_w[wave][wi + 8 + ta2];
+      const float2 v = has ? st_v[wave][sc] : make_float2(0.f, 0.f);
+      float2* pt = copy + st_off[wave][sc] + tapoff;
+      const float2 a = *pt;
+      *pt = make_float2(fmaf(wt, v.x, a.x), fmaf(wt, v.y, a.y));
     }
   }
   __syncthreads();
-  // sum the copies and write the tile: rows along the last axis are contiguous in U
-  for (int e = threadIdx.x; e < vol; e += 64 * kWarpWaves) {
-    int l[3] = {0, 0, 0};
-    int t = e;
-    for (int i = NDIM - 1; i >= 0; --i) {
-      l[i] = t % td.TS[i];
-      t /= td.TS[i];
-    }
-    bool ok = true;
-    for (int i = 0; i < NDIM; ++i) ok = ok && l[i] < ext[i];
-    if (!ok) continue;
-    int64_t gi = 0;
-    for (int i = 0; i < NDIM; ++i) gi = gi * dm.G[i] + lo[i] + l[i];
-    const int pi = NDIM == 3 ? l[0] * td.S0 + l[1] * td.S1 + l[2] : l[0] * td.S0 + l[1];
+  // sum the copies and write the region, [E0][E1][E2] compact
+  const int e12 = td.E[1] * td.E[2];
+  for (int e = threadIdx.x; e < td.RV; e += 64 * kWarpWaves) {
+    const int l0 = e / e12;
+    const int rem = e - l0 * e12;
+    const int l1 = rem / td.E[2];
+    const int l2 = rem - l1 * td.E[2];
+    const int pi = NDIM == 3 ? l0 * td.R0 + l1 * td.R1 + l2 : l0 * td.R0 + l1;
     float2 v = make_float2(0.f, 0.f);
 #pragma unroll
     for (int w = 0; w < kWarpWaves * Q; ++w) v = cadd(v, accw[(size_t)w * td.P + pi]);
-    if (accumulate) v = cadd(v, U[gi]);
-    U[gi] = v;
+    reg[(int64_t)tile * td.RV + e] = v;
   }
+}
+
+// Pass 2 of the image-space spread: U[g] (+)= the sum of every region that
+// covers g, in a fixed order.  Along axis i, g lies at l = g - lo in its own
+// tile t, and, when l < 3, also at l + ext(t') in the region of the tile
+// below, t' = t - 1 (periodically: the last tile below tile 0).  One
+// workgroup per row of U along the last axis (G_last <= 1024 threads).
+template <int NDIM>
+__global__ __launch_bounds__(1024) void warp_spread_sum_kernel(const float2* __restrict__ reg, float2* __restrict__ U,
+                                                               int accumulate, Dims dm, TileDims td) {
+  const int gl = threadIdx.x;  // along the last axis
+  if (gl >= dm.G[NDIM - 1]) return;
+  int g[3] = {0, 0, 0};
+  if constexpr (NDIM == 3) {
+    g[0] = blockIdx.x / dm.G[1];
+    g[1] = blockIdx.x - g[0] * dm.G[1];
+    g[2] = gl;
+  } else {
+    g[0] = blockIdx.x;
+    g[1] = gl;
+  }
+  int tt[3][2], ll[3][2], nc[3] = {1, 1, 1};
+#pragma unroll
+  for (int i = 0; i < NDIM; ++i) {
+    const int t = g[i] >> td.lg[i];
+    const int l = g[i] - (t << td.lg[i]);
+    tt[i][0] = t;
+    ll[i][0] = l;
+    if (l < 3) {
+      const int tp = t == 0 ? td.nt[i] - 1 : t - 1;
+      const int ext = tp == td.nt[i] - 1 ? dm.G[i] - (tp << td.lg[i]) : td.TS[i];
+      tt[i][1] = tp;
+      ll[i][1] = l + ext;
+      nc[i] = 2;
+    }
+  }
+  float2 v = make_float2(0.f, 0.f);
+  if constexpr (NDIM == 3) {
+    for (int a = 0; a < nc[0]; ++a)
+      for (int b = 0; b < nc[1]; ++b)
+        for (int c = 0; c < nc[2]; ++c) {
+          const int tile = (tt[0][a] * td.nt[1] + tt[1][b]) * td.nt[2] + tt[2][c];
+          v = cadd(v, reg[(int64_t)tile * td.RV + (ll[0][a] * td.E[1] + ll[1][b]) * td.E[2] + ll[2][c]]);
+        }
+  } else {
+    for (int a = 0; a < nc[0]; ++a)
+      for (int b = 0; b < nc[1]; ++b) {
+        const int tile = tt[0][a] * td.nt[1] + tt[1][b];
+        v = cadd(v, reg[(int64_t)tile * td.RV + ll[0][a] * td.E[1] + ll[1][b]]);
+      }
+  }
+  const int64_t gi = (int64_t)blockIdx.x * dm.G[NDIM - 1] + gl;
+  if (accumulate) v = cadd(U[gi], v);
+  U[gi] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -533,8 +545,11 @@ struct KBatch {
   unsigned* ymax;
   float dens[kMaxPhasesPerLaunch];
   // spread output tile-major instead: the touched tiles one after another,
-  // each [TS0][TS1][TS2][C] contiguous at gslot * vol * C (spread and reduce)
+  // each [TS0][TS1][TS2][C] contiguous at gslot * vol * C (spread and reduce);
+  // the spread then stores only the runs fmask marks (the adjoint axis-0
+  // pass reads no others)
   int tiled;
+  const uint64_t* fmask[kMaxPhasesPerLaunch];  // touched runs per grid column (i1, i2)
 };
 
 // the state a block belongs to
@@ -694,6 +709,91 @@ __host__ __device__ inline size_t kspread_lds_bytes(const KTile& kt, int C) {
   return sizeof(float2) * ((size_t)C * kt.P + kSpreadDump + (size_t)kSpreadBatch * C);
 }
 
+// Touched columns of a tile for the tile-major write-out: s_touch[l1 TS2 +
+// l2] = 1 when grid column (lo1 + l1, lo2 + l2) marks the tile's run along
+// axis 0 (3D; the tile is one run).  Loaded at the start of a unit so the
+// mask reads are done before the write-out needs them.
+__device__ __forceinline__ void kspread_touch(const uint64_t* fm, const int lo[3], const KTile& kt, const Dims& dm,
+                                              unsigned char* s_touch) {
+  const int ncol = kt.TS[1] * kt.TS[2];
+  const int run = lo[0] / kt.TS[0];
+  for (int e = threadIdx.x; e < ncol; e += blockDim.x) {
+    const int l1 = e / kt.TS[2], l2 = e - l1 * kt.TS[2];
+    const int g1 = lo[1] + l1, g2 = lo[2] + l2;
+    s_touch[e] = (g1 < dm.G[1] && g2 < dm.G[2]) ? (unsigned char)((fm[(int64_t)g1 * dm.G[2] + g2] >> run) & 1ull) : 0;
+  }
+}
+
+// Write-out of a k-space spread unit from the LDS accumulator (one plane of
+// P complex values per coil), row by row: a tile row (fixed l0, l1) is
+// TS_last * C contiguous values of the [G...][C] grid.  Thread t takes
+// element t mod rowlen of rows t / rowlen, + rpi, + 2 rpi, ... (rpi >= 1
+// rows per round, since blockDim >= TS_last C).  Whole tiles of a
+// tile-major output store only their touched columns (s_touch); partial
+// tiles keep the point-major layout e = point * C + coil.
+template <int NDIM, int S>
+__device__ __forceinline__ void kspread_write_out(const KBatch<typename Elem<S>::T>& bt, int bp, const KUnit& un,
+                                                  const float2* acc, int C, const Dims& dm, const KTile& kt,
+                                                  FastDiv cdiv, const int lo[3], const unsigned char* s_touch) {
+  typename Elem<S>::T* __restrict__ grid = bt.grid[bp];
+  float2* __restrict__ partial = bt.partial[bp];
+  const int nthr = blockDim.x;
+  const int volC = kt.vol * C;
+  const int rowlen = kt.TS[NDIM - 1] * C;
+  const int rpi = nthr / rowlen;
+  const float hs = bt.ymax ? ldexpf(1.f, spread_exp(bt.ymax + bp * kYmaxSlots, bt.dens[bp])) : 1.f;
+  const int r0 = threadIdx.x / rowlen;
+  if (r0 >= rpi) return;
+  const int within = threadIdx.x - r0 * rowlen;
+  const int l2 = (int)cdiv.div((uint32_t)within);  // point along the last axis
+  const int cc = within - l2 * C;
+  const float2* src = acc + (size_t)cc * kt.P + l2;
+  const int gl = lo[NDIM - 1] + l2;
+  const bool okl = gl < dm.G[NDIM - 1];
+  const int nrows = kt.vol / kt.TS[NDIM - 1];
+  if constexpr (NDIM == 3) {
+    if (bt.tiled && un.slot < 0) {  // tile-major: one contiguous tile, touched columns only
+      typename Elem<S>::T* dst = grid + (int64_t)un.gslot * volC + within;
+      for (int row = r0; row < nrows; row += rpi) {
+        const int l1 = row % kt.TS[1];
+        const int pi = (row / kt.TS[1]) * kt.S0 + l1 * kt.S1;
+        if (s_touch[l1 * kt.TS[2] + l2]) Elem<S>::store(dst + row * rowlen, store_scaled<S>(src[pi], hs));
+      }
+      return;
+    }
+  }
+  for (int row = r0; row < nrows; row += rpi) {
+    int l0, l1 = 0, pi;
+    if constexpr (NDIM == 3) {
+      l0 = row / kt.TS[1];
+      l1 = row - l0 * kt.TS[1];
+      pi = l0 * kt.S0 + l1 * kt.S1;
+    } else {
+      l0 = row;
+      pi = row * kt.S0;
+    }
+    const float2 v = src[pi];
+    if (un.slot >= 0) {
+      partial[(int64_t)un.slot * volC + row * rowlen + within] = v;
+      continue;
+    }
+    const int gl0 = lo[0] + l0;
+    bool ok = okl && gl0 < dm.G[0];
+    int64_t gi;
+    if constexpr (NDIM == 3) {
+      const int gl1 = lo[1] + l1;
+      ok = ok && gl1 < dm.G[1];
+      gi = bt.blk.off(gl0, gl1, (int64_t)gl * C + cc);
+    } else {
+      gi = bt.blk.off(gl0, gl, cc);
+    }
+    if (ok) Elem<S>::store(grid + gi, store_scaled<S>(v, hs));
+  }
+}
+
+// most tile columns of a tiled k-space spread (TS1 TS2 <= 16 x 8)
+constexpr int kMaxTileCols = 128;
+
 // k-space spread of one work unit, without atomics.  The unit's samples are
 // staged in LDS in batches of kSpreadBatch (tap offsets relative to the tile,
 // tap weights, the C coil values); thread s stages sample s, and the loads
@@ -713,8 +813,6 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
   const int bp = batch_member(bt.first, bt.n, blockIdx.x);
   const KTap* __restrict__ taps_v = bt.taps[bp];
   const float2* __restrict__ yv = bt.yin[bp];
-  typename Elem<S>::T* __restrict__ grid = bt.grid[bp];
-  float2* __restrict__ partial = bt.partial[bp];
   extern __shared__ float2 acc[];  // [C][P] accumulator, [4][64] garbage, [kSpreadBatch][C] coil values
   __shared__ int4 st_off[kSpreadBatch];
   __shared__ float4 st_w[kSpreadBatch][3];
@@ -724,6 +822,8 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
   const KUnit un = bt.units[bp][blockIdx.x - bt.first[bp]];
   int lo[3] = {0, 0, 0};
   ktile_origin(un.tile, kt, NDIM, lo);
+  __shared__ unsigned char s_touch[kMaxTileCols];
+  if (NDIM == 3 && bt.tiled && un.slot < 0) kspread_touch(bt.fmask[bp], lo, kt, dm, s_touch);
   {
     float4* a4 = (float4*)acc;
     const int n4 = (C * kt.P) >> 1;  // P is even
@@ -830,59 +930,160 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
     }
   }
   __syncthreads();
-  // write out, row by row: a tile row (fixed l0, l1) is TS_last * C
-  // contiguous values of the [G...][C] grid.  Thread t takes element
-  // t mod rowlen of rows t / rowlen, + rpi, + 2 rpi, ... (rpi >= 1 rows per
-  // round, since blockDim >= 16 C >= TS_last C)
-  const int volC = kt.vol * C;
-  const int rowlen = kt.TS[NDIM - 1] * C;
-  const int rpi = nthr / rowlen;
+  kspread_write_out<NDIM, S>(bt, bp, un, acc, C, dm, kt, cdiv, lo, s_touch);
+}
+
+// 3D k-space spread of one work unit with register accumulators, for tiles
+// of 8 x 4 x 8 and an even number of coils: lane (coil pair, tile column)
+// of wave w, coils 4w + 2h and 4w + 2h + 1 (h = lane / 32), holds the 8
+// cells of its column (l1, l2) along axis 0 for both coils in registers.
+// The staging thread of a sample expands its tap weights over the tile:
+// W0[l0] (8 values), W1[l1] (4) and W2[l2] (8) hold the weight of the tap
+// that lands on row l of the tile along that axis, zero where none does.
+// Every lane then adds W0[l0] W1[l1] W2[l2] y_c to its 16 cells (lanes
+// outside the sample's footprint add zero): no cell is shared between lanes,
+// no LDS read-modify-write and no branch; the summation order per cell is
+// the sample order (deterministic).  Staging as in kspread_kernel; the
+// accumulators are stored from registers.
+constexpr int kRegW = 20;  // expanded weights per staged sample: W0[8], W1[4], W2[8]
+
+template <int S>
+__global__ __launch_bounds__(512) void kspread_reg_kernel(KBatch<typename Elem<S>::T> bt, int C, Dims dm, KTile kt,
+                                                          KbPoly kb, FastDiv cdiv) {
+  const int bp = batch_member(bt.first, bt.n, blockIdx.x);
+  const KTap* __restrict__ taps_v = bt.taps[bp];
+  const float2* __restrict__ yv = bt.yin[bp];
+  extern __shared__ float2 st_y[];  // [kSpreadBatch][C] coil values
+  __shared__ float4 st_W[kSpreadBatch][kRegW / 4];
+  __shared__ unsigned char s_touch[kMaxTileCols];
+  const int nthr = blockDim.x;
+  const KUnit un = bt.units[bp][blockIdx.x - bt.first[bp]];
+  int lo[3] = {0, 0, 0};
+  ktile_origin(un.tile, kt, 3, lo);
+  if (bt.tiled && un.slot < 0) kspread_touch(bt.fmask[bp], lo, kt, dm, s_touch);
+  __syncthreads();  // s_touch visible to every wave (also for a unit without samples)
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 31;
+  const int l1 = col >> 3, l2 = col & 7;
+  const int c0 = 4 * wave + 2 * (lane >> 5);  // coils c0, c0 + 1
+  const bool active = c0 < C;
+  const int cr = active ? c0 : 0;
+  const int cr1 = active && c0 + 1 < C ? c0 + 1 : cr;  // an odd C's last lane pair reads its coil twice
+  float2 a0[8], a1[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a0[j] = a1[j] = make_float2(0.f, 0.f);
+
+  // staging as in kspread_kernel (nthr = 64 ceil(C/4) >= 16 C)
+  constexpr int kYRegs = kSpreadBatch / 16;
+  float2 yr[kYRegs];
+  KTap tr;
+  auto fetch = [&](int b0) {
+    const int nb = min(kSpreadBatch, un.count - b0);
+    const float2* src = yv + (int64_t)(un.start + b0) * C;
+    const int ny = nb * C;
+#pragma unroll
+    for (int k = 0; k < kYRegs; ++k) yr[k] = src[min((int)threadIdx.x + k * nthr, ny - 1)];
+    tr = ktap_load(taps_v + un.start + b0 + min((int)threadIdx.x, nb - 1));
+  };
+  fetch(0);
+  const float* stw = (const float*)st_W;
+  for (int b0 = 0; b0 < un.count; b0 += kSpreadBatch) {
+    const int nb = min(kSpreadBatch, un.count - b0);
+    __syncthreads();  // previous batch consumed
+#pragma unroll
+    for (int k = 0; k < kYRegs; ++k) {
+      const int e = (int)threadIdx.x + k * nthr;
+      if (e < nb * C) st_y[e] = yr[k];
+    }
+    if ((int)threadIdx.x < nb) {  // thread s stages sample s: its weights expanded over the tile
+      float W[kRegW];
+      constexpr int wbase[3] = {0, 8, 12}, wlen[3] = {8, 4, 8};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        float w[4];
+        kb_weights(kb, tr.f[i], w);
+        int o = (int)((tr.base >> (10 * i)) & 1023) - lo[i];  // periodic: the image next to the tile
+        if (o > dm.G[i] / 2) o -= dm.G[i];
+        if (o < -dm.G[i] / 2) o += dm.G[i];
+#pragma unroll
+        for (int l = 0; l < wlen[i]; ++l) {
+          const int t = l - o;
+          W[wbase[i] + l] = t == 0 ? w[0] : t == 1 ? w[1] : t == 2 ? w[2] : t == 3 ? w[3] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kRegW / 4; ++q)
+        st_W[threadIdx.x][q] = make_float4(W[4 * q], W[4 * q + 1], W[4 * q + 2], W[4 * q + 3]);
+    }
+    __syncthreads();
+    fetch(b0 + kSpreadBatch < un.count ? b0 + kSpreadBatch : b0);
+    // sample s + 1's parameters are read while sample s is applied
+    float4 wa = st_W[0][0], wb = st_W[0][1];
+    float w1 = stw[8 + l1], w2 = stw[12 + l2];
+    float2 y0 = st_y[cr], y1 = st_y[cr1];
+    for (int s = 0; s < nb; ++s) {
+      const float4 cwa = wa, cwb = wb;
+      const float cw12 = w1 * w2;
+      const float2 cy0 = y0, cy1 = y1;
+      {
+        const int sn = min(s + 1, nb - 1);
+        wa = st_W[sn][0];
+        wb = st_W[sn][1];
+        w1 = stw[sn * kRegW + 8 + l1];
+        w2 = stw[sn * kRegW + 12 + l2];
+        y0 = st_y[sn * C + cr];
+        y1 = st_y[sn * C + cr1];
+      }
+      const float2 v0 = make_float2(cw12 * cy0.x, cw12 * cy0.y);
+      const float2 v1 = make_float2(cw12 * cy1.x, cw12 * cy1.y);
+      const float W0[8] = {cwa.x, cwa.y, cwa.z, cwa.w, cwb.x, cwb.y, cwb.z, cwb.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        a0[j].x = fmaf(W0[j], v0.x, a0[j].x);
+        a0[j].y = fmaf(W0[j], v0.y, a0[j].y);
+        a1[j].x = fmaf(W0[j], v1.x, a1[j].x);
+        a1[j].y = fmaf(W0[j], v1.y, a1[j].y);
+      }
+    }
+  }
+  // registers straight to memory (each wave writes a strided third of every
+  // tile row; the L2 merges the rows before they reach HBM)
+  if (!active) return;
+  const bool has1 = c0 + 1 < C;
   const float hs = bt.ymax ? ldexpf(1.f, spread_exp(bt.ymax + bp * kYmaxSlots, bt.dens[bp])) : 1.f;
-  const int r0 = threadIdx.x / rowlen;
-  if (r0 < rpi) {
-    const int within = threadIdx.x - r0 * rowlen;
-    const int l2 = (int)cdiv.div((uint32_t)within);  // point along the last axis
-    const int cc = within - l2 * C;
-    const float2* src = acc + (size_t)cc * kt.P + l2;
-    const int gl = lo[NDIM - 1] + l2;
-    const bool okl = gl < dm.G[NDIM - 1];
-    const int nrows = kt.vol / kt.TS[NDIM - 1];
-    if (bt.tiled && un.slot < 0) {  // tile-major: one contiguous tile
-      typename Elem<S>::T* dst = grid + (int64_t)un.gslot * volC + within;
-      for (int row = r0; row < nrows; row += rpi) {
-        const int pi = NDIM == 3 ? (row / kt.TS[1]) * kt.S0 + (row % kt.TS[1]) * kt.S1 : row * kt.S0;
-        Elem<S>::store(dst + row * rowlen, store_scaled<S>(src[pi], hs));
-      }
-      return;
+  const int64_t volC = (int64_t)kt.vol * C;
+  const int64_t in_tile = (int64_t)(l1 * kt.TS[2] + l2) * C + c0;  // + l0 TS1 TS2 C
+  const int64_t rowC = (int64_t)kt.TS[1] * kt.TS[2] * C;
+  if (un.slot >= 0) {  // partial tile, point-major
+    float2* dst = bt.partial[bp] + (int64_t)un.slot * volC + in_tile;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      dst[j * rowC] = a0[j];
+      if (has1) dst[j * rowC + 1] = a1[j];
     }
-    for (int row = r0; row < nrows; row += rpi) {
-      int l0, l1 = 0, pi;
-      if constexpr (NDIM == 3) {
-        l0 = row / kt.TS[1];
-        l1 = row - l0 * kt.TS[1];
-        pi = l0 * kt.S0 + l1 * kt.S1;
-      } else {
-        l0 = row;
-        pi = row * kt.S0;
-      }
-      const float2 v = src[pi];
-      if (un.slot >= 0) {
-        // partial tiles keep the point-major layout e = point * C + coil
-        partial[(int64_t)un.slot * volC + row * rowlen + within] = v;
-        continue;
-      }
-      const int gl0 = lo[0] + l0;
-      bool ok = okl && gl0 < dm.G[0];
-      int64_t gi;
-      if constexpr (NDIM == 3) {
-        const int gl1 = lo[1] + l1;
-        ok = ok && gl1 < dm.G[1];
-        gi = bt.blk.off(gl0, gl1, (int64_t)gl * C + cc);
-      } else {
-        gi = bt.blk.off(gl0, gl, cc);
-      }
-      if (ok) Elem<S>::store(grid + gi, store_scaled<S>(v, hs));
+    return;
+  }
+  typename Elem<S>::T* __restrict__ grid = bt.grid[bp];
+  if (bt.tiled) {  // tile-major, touched columns only
+    if (!s_touch[col]) return;
+    typename Elem<S>::T* dst = grid + (int64_t)un.gslot * volC + in_tile;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      Elem<S>::store(dst + j * rowC, store_scaled<S>(a0[j], hs));
+      if (has1) Elem<S>::store(dst + j * rowC + 1, store_scaled<S>(a1[j], hs));
     }
+    return;
+  }
+  const int g1 = lo[1] + l1, g2 = lo[2] + l2;  // row-blocked grid
+  if (g1 >= dm.G[1] || g2 >= dm.G[2]) return;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (lo[0] + j >= dm.G[0]) break;
+    const int64_t gi = bt.blk.off(lo[0] + j, g1, (int64_t)g2 * C + c0);
+    Elem<S>::store(grid + gi, store_scaled<S>(a0[j], hs));
+    if (has1) Elem<S>::store(grid + gi + 1, store_scaled<S>(a1[j], hs));
   }
 }
 

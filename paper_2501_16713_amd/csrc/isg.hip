@@ -172,6 +172,7 @@ struct isg_plan {
   void* k1buf = nullptr;
   void* k2buf = nullptr;
   DevBuf ybuf;              // normal-operator data, grown on demand
+  DevBuf wreg;              // image-space spread regions, [tiles][E0][E1][E2]
   DevBuf partial;           // spread partial tiles, grown on demand
   // CG
   float2 *cg_r = nullptr, *cg_p = nullptr, *cg_q = nullptr;
@@ -262,6 +263,8 @@ struct isg_traj {
   isg_plan* plan = nullptr;
   int64_t M = 0;
   uint64_t* colmask = nullptr;  // touched-tile masks (null: all tiles written)
+  uint64_t* fmask = nullptr;    // touched-run masks per grid column (i1, i2) (null with colmask)
+  int64_t fine_cells = 0;       // grid cells in the touched runs
   int* colbase = nullptr;       // tile-major spread output: first slot of each tile column
   std::vector<uint64_t> colmask_h;
   std::vector<int> colbase_h;
@@ -846,9 +849,22 @@ static int warp_ntiles(const isg_plan* pl) {
   return t;
 }
 
-// U = sum_p P_{d_p} w_p over the given states
-static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const float2* const* w, float2* U) {
+// bytes of the image-space spread regions
+static size_t warp_region_bytes(const isg_plan* pl) {
+  return sizeof(float2) * (size_t)warp_ntiles(pl) * pl->wtile.RV;
+}
+
+// U = sum_p P_{d_p} w_p over the given states: pass 1 accumulates each
+// tile's entries into its region (reg, warp_region_bytes), pass 2 sums the
+// overlapping regions into U, both once per kMaxPhasesPerLaunch states
+static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const float2* const* w, float2* U,
+                        float2* reg) {
   const size_t lds = warp_spread_lds_bytes(pl->wtile, pl->ndim);
+  const int nt = warp_ntiles(pl);
+  const int Gl = pl->G[pl->ndim - 1];
+  const int rows = (int)(pl->NG / Gl);
+  const int sthreads = ((Gl + 63) / 64) * 64;
+  if (sthreads > 1024) throw HipError{hipErrorInvalidConfiguration, "spread rows longer than a workgroup"};
   for (int p0 = 0; p0 < P; p0 += kMaxPhasesPerLaunch) {
     WarpSpreadPhases ph;
     memset(&ph, 0, sizeof(ph));
@@ -860,21 +876,38 @@ static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const 
       ph.w[i] = w[p0 + i];
     }
     const int acc = p0 > 0 ? 1 : 0;
-    const int nt = warp_ntiles(pl);
     const unsigned nblk = 8u * (unsigned)((nt + 7) / 8);  // one workgroup per tile, XCD-contiguous order
     if (pl->ndim == 3)
       allow_lds(warp_spread_kernel<3>, lds);
     else
       allow_lds(warp_spread_kernel<2>, lds);
-    Tick tick(pl, "warp_spread");
-    if (pl->ndim == 3)
-      hipLaunchKernelGGL(warp_spread_kernel<3>, dim3(nblk), dim3(64 * kWarpWaves), lds, pl->stream, ph, U, acc,
-                         nt, pl->dims, pl->wtile, pl->kb);
-    else
-      hipLaunchKernelGGL(warp_spread_kernel<2>, dim3(nblk), dim3(64 * kWarpWaves), lds, pl->stream, ph, U, acc,
-                         nt, pl->dims, pl->wtile, pl->kb);
-    LAUNCH_OK();
+    {
+      Tick tick(pl, "warp_spread");
+      if (pl->ndim == 3)
+        hipLaunchKernelGGL(warp_spread_kernel<3>, dim3(nblk), dim3(64 * kWarpWaves), lds, pl->stream, ph, reg, nt,
+                           pl->dims, pl->wtile, pl->kb);
+      else
+        hipLaunchKernelGGL(warp_spread_kernel<2>, dim3(nblk), dim3(64 * kWarpWaves), lds, pl->stream, ph, reg, nt,
+                           pl->dims, pl->wtile, pl->kb);
+      LAUNCH_OK();
+    }
+    {
+      Tick tick(pl, "warp_spread_sum");
+      if (pl->ndim == 3)
+        hipLaunchKernelGGL(warp_spread_sum_kernel<3>, dim3(rows), dim3(sthreads), 0, pl->stream, reg, U, acc, pl->dims,
+                           pl->wtile);
+      else
+        hipLaunchKernelGGL(warp_spread_sum_kernel<2>, dim3(rows), dim3(sthreads), 0, pl->stream, reg, U, acc, pl->dims,
+                           pl->wtile);
+      LAUNCH_OK();
+    }
   }
+}
+
+// the same with the plan's region buffer (grown on first use)
+static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const float2* const* w, float2* U) {
+  grow(pl, pl->wreg, warp_region_bytes(pl));
+  warp_spread(pl, P, mo, w, U, (float2*)pl->wreg.p);
 }
 
 // ---------------------------------------------------------------------------
@@ -924,12 +957,9 @@ static St2CoilReduce st2_reduce(isg_plan* pl, float2* w, const float2* Sm, int n
 
 static TileMask tile_mask(const isg_plan* pl, const isg_traj* tr) {
   TileMask tm;
-  tm.colmask = tr ? tr->colmask : nullptr;
+  tm.fmask = tr ? tr->fmask : nullptr;
   tm.C = pl->C;
   tm.G2 = pl->G[2];
-  tm.TS1 = pl->ktile.TS[1];
-  tm.TS2 = pl->ktile.TS[2];
-  tm.nt2 = pl->ktile.nt[2];
   int lg = 0;
   while ((1 << lg) < pl->ktile.TS[0]) ++lg;
   tm.ts0_log2 = lg;
@@ -952,6 +982,7 @@ static Ld2Tiles<S> ld2_tiles(isg_plan* pl, const void* p, const isg_traj* tr, in
   Ld2Tiles<S> ld;
   ld.p = (const typename Elem<S>::T*)p;
   ld.colmask = tr->colmask;
+  ld.fmask = tr->fmask;
   ld.colbase = tr->colbase;
   ld.C = pl->C;
   ld.G2 = pl->G[2];
@@ -1225,10 +1256,14 @@ static void kspread_nd(isg_plan* pl, const KJob* jobs, int n) {
   using T = typename Elem<S>::T;
   const size_t lds = kspread_lds_bytes(pl->ktile, pl->C);
   const size_t volC = (size_t)pl->ktile.vol * pl->C;
-  const int kthreads = 64 * ((pl->C + 3) / 4);  // one wave per 4 coils
+  // 3D tiles of 8 x 4 x 8 take the register-accumulating spread, others the
+  // LDS read-modify-write one (both one wave per 4 coils)
+  const bool regk = NDIM == 3 && pl->ktile.TS[0] == 8 && pl->ktile.TS[1] == 4 && pl->ktile.TS[2] == 8;
+  const int kthreads = 64 * ((pl->C + 3) / 4);
+  const size_t lds_used = regk ? sizeof(float2) * (size_t)kSpreadBatch * pl->C : lds;
   if (pl->ktile.TS[NDIM - 1] * pl->C > kthreads)  // the write-out takes at least one tile row per round
     throw HipError{hipErrorInvalidConfiguration, "k-space tile row longer than the spread workgroup"};
-  auto k = kspread_kernel<NDIM, S>;
+  auto k = regk ? kspread_reg_kernel<S> : kspread_kernel<NDIM, S>;
   allow_lds(k, lds);
   if (pl->ymax && n > kMaxPhasesPerLaunch)  // one spread-scale slot per state of a batch
     throw HipError{hipErrorInvalidValue, "k-space batch larger than the spread-scale slots"};
@@ -1250,6 +1285,7 @@ static void kspread_nd(isg_plan* pl, const KJob* jobs, int n) {
       bt.grid[i] = (T*)(jb.sgrid ? jb.sgrid : jb.grid);
       bt.partial[i] = (float2*)pl->partial.p + slot0 * volC;
       bt.dens[i] = jb.tr->dens;
+      bt.fmask[i] = jb.tr->fmask;
       units += jb.tr->nunits;
       splits += jb.tr->nsplits;
       slot0 += jb.tr->nslots;
@@ -1260,7 +1296,7 @@ static void kspread_nd(isg_plan* pl, const KJob* jobs, int n) {
     bt.tiled = NDIM == 3 && tiled_adjoint(pl);
     {
       Tick tick(pl, "kspread");
-      hipLaunchKernelGGL(k, dim3((unsigned)units), dim3(kthreads), lds, pl->stream, bt, pl->C, pl->dims, pl->ktile,
+      hipLaunchKernelGGL(k, dim3((unsigned)units), dim3(kthreads), lds_used, pl->stream, bt, pl->C, pl->dims, pl->ktile,
                          pl->kb, make_fastdiv(pl->C));
       LAUNCH_OK();
     }
@@ -1527,38 +1563,31 @@ static isg_status prepare_motion(isg_plan* pl, const float* d_dev, isg_motion* m
     if (!std::isfinite(v)) return fail(ISG_ERR_NOT_FINITE, "displacement field holds NaN or Inf");
     if (std::fabs(v) > 1.0e6f) return fail(ISG_ERR_INVALID_ARG, "displacement magnitude exceeds 1e6 voxels");
   }
+  // every voxel joins the one tile that holds its first tap along every
+  // axis (the spread kernel recomputes the same tap base from d); counting
+  // sort by tile, voxels in index order within a tile
   const int ntiles = warp_ntiles(pl);
-  std::vector<int> cnt(ntiles + 1, 0);
-  std::vector<int> tl[3];
-  for (int i = 0; i < 3; ++i) tl[i].resize(2);
-  auto visit = [&](int64_t r, auto&& fn) {
+  std::vector<int> cnt(ntiles + 1, 0), tof((size_t)N);
+  for (int64_t r = 0; r < N; ++r) {
     int ri[3] = {0, 0, 0};
     int64_t t = r;
     for (int i = nd - 1; i >= 0; --i) {
       ri[i] = (int)(t % pl->n[i]);
       t /= pl->n[i];
     }
-    int ts[3][2], nts[3] = {1, 1, 1};
+    int tile = 0;
     for (int i = 0; i < nd; ++i) {
       const float y = 2.0f * d[(size_t)i * N + r];
       const int b = iwrap(2 * (int64_t)ri[i] + (int64_t)std::floor(y) - 1, pl->G[i]);
-      nts[i] = axis_tiles(b, pl->G[i], pl->wtile.TS[i], ts[i]);
+      tile = tile * pl->wtile.nt[i] + (b >> pl->wtile.lg[i]);
     }
-    if (nd == 3) {
-      for (int a = 0; a < nts[0]; ++a)
-        for (int b = 0; b < nts[1]; ++b)
-          for (int c = 0; c < nts[2]; ++c)
-            fn((ts[0][a] * pl->wtile.nt[1] + ts[1][b]) * pl->wtile.nt[2] + ts[2][c]);
-    } else {
-      for (int a = 0; a < nts[0]; ++a)
-        for (int b = 0; b < nts[1]; ++b) fn(ts[0][a] * pl->wtile.nt[1] + ts[1][b]);
-    }
-  };
-  for (int64_t r = 0; r < N; ++r) visit(r, [&](int t) { cnt[t + 1]++; });
+    tof[(size_t)r] = tile;
+    cnt[tile + 1]++;
+  }
   for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
   std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-  std::vector<int> vox(cnt[ntiles]);
-  for (int64_t r = 0; r < N; ++r) visit(r, [&](int t) { vox[pos[t]++] = (int)r; });
+  std::vector<int> vox((size_t)N);
+  for (int64_t r = 0; r < N; ++r) vox[(size_t)pos[tof[(size_t)r]]++] = (int)r;
   mo->d = (float*)dmalloc(pl, sizeof(float) * d.size());
   mo->tile_off = (int*)dmalloc(pl, sizeof(int) * cnt.size());
   mo->vox = (int*)dmalloc(pl, sizeof(int) * std::max<size_t>(1, vox.size()));
@@ -1728,9 +1757,10 @@ static void bin_traj(isg_plan* pl, isg_traj* tr) {
   const std::vector<KTap>& taps = tr->taps_h;
   HIP_OK(hipStreamSynchronize(pl->stream));
   pl->generation++;
-  for (void** q : {(void**)&tr->order, (void**)&tr->gorder, (void**)&tr->colmask, (void**)&tr->colbase,
-                   (void**)&tr->taps_v, (void**)&tr->vis_off, (void**)&tr->vis})
+  for (void** q : {(void**)&tr->order, (void**)&tr->gorder, (void**)&tr->colmask, (void**)&tr->fmask,
+                   (void**)&tr->colbase, (void**)&tr->taps_v, (void**)&tr->vis_off, (void**)&tr->vis})
     traj_free(pl, *q);
+  tr->fine_cells = 0;
   tr->colmask_h.clear();
   tr->colbase_h.clear();
   int ntiles = 1;
@@ -1779,6 +1809,33 @@ static void bin_traj(isg_plan* pl, isg_traj* tr) {
     }
     tr->colbase = (int*)dmalloc(pl, sizeof(int) * ncols);
     HIP_OK(hipMemcpy(tr->colbase, tr->colbase_h.data(), sizeof(int) * ncols, hipMemcpyHostToDevice));
+    // touched runs of 2^lg cells along axis 0, per grid column (i1, i2)
+    int lg = 0;
+    while ((1 << lg) < pl->ktile.TS[0]) ++lg;
+    const int G0 = pl->G[0], G1 = pl->G[1], G2 = nd == 3 ? pl->G[2] : 1;
+    std::vector<uint64_t> fm((size_t)G1 * G2, 0ull);
+    for (int64_t j = 0; j < M; ++j) {
+      const int b0 = (int)(taps[j].base & 1023), b1 = (int)((taps[j].base >> 10) & 1023);
+      const int b2 = nd == 3 ? (int)((taps[j].base >> 20) & 1023) : 0;
+      const int e0 = b0 + kWidth - 1;
+      const uint64_t bits = (1ull << (b0 >> lg)) | (1ull << ((e0 >= G0 ? e0 - G0 : e0) >> lg));
+      for (int t1 = 0; t1 < kWidth; ++t1) {
+        const int i1 = b1 + t1 >= G1 ? b1 + t1 - G1 : b1 + t1;
+        if (nd == 3) {
+          for (int t2 = 0; t2 < kWidth; ++t2) {
+            const int i2 = b2 + t2 >= G2 ? b2 + t2 - G2 : b2 + t2;
+            fm[(size_t)i1 * G2 + i2] |= bits;
+          }
+        } else {
+          fm[(size_t)i1] |= bits;
+        }
+      }
+    }
+    int64_t runs = 0;
+    for (uint64_t m : fm) runs += __builtin_popcountll(m);
+    tr->fine_cells = runs * (1 << lg);  // ragged last runs counted whole
+    tr->fmask = (uint64_t*)dmalloc(pl, sizeof(uint64_t) * fm.size());
+    HIP_OK(hipMemcpy(tr->fmask, fm.data(), sizeof(uint64_t) * fm.size(), hipMemcpyHostToDevice));
   }
   tr->order = (int*)dmalloc(pl, sizeof(int) * order.size());
   HIP_OK(hipMemcpy(tr->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
@@ -2149,16 +2206,18 @@ static void* static_scratch() {
 }
 
 // byte offsets of the warp-adjoint buffers inside the static scratch: U
-// [G...], then C, B, A of the adjoint upsampling passes, each 256-aligned
+// [G...], the spread regions, then C, B, A of the adjoint upsampling
+// passes, each 256-aligned
 struct StaticLayout {
-  size_t u, a, b, c, total;
+  size_t u, reg, a, b, c, total;
 };
 static StaticLayout static_layout(const isg_plan* pl) {
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t e = sizeof(float2);
   StaticLayout L;
   L.u = 0;
-  L.c = up(L.u + e * (size_t)pl->NG);
+  L.reg = up(L.u + e * (size_t)pl->NG);
+  L.c = up(L.reg + warp_region_bytes(pl));
   const size_t cb = pl->ndim == 3 ? e * (size_t)pl->G[0] * pl->G[1] * pl->n[2] : 0;
   L.b = up(L.c + cb);
   L.a = up(L.b + e * (size_t)pl->G[0] * pl->n[1] * pl->n[2]);
@@ -2247,24 +2306,33 @@ isg_status isg_plan_create(const isg_plan_desc* desc, isg_plan** out) {
     pl->ktile.TS[i] = 1;
     pl->ktile.nt[i] = 1;
   }
+  // image-space spread tiles (powers of two, at most G/2) and their regions
+  // (tile + 3 halo cells per axis; LDS rows padded to an even length)
   const int wts = pl->ndim == 3 ? 8 : 16;
+  for (int i = 0; i < 3; ++i) {
+    pl->wtile.TS[i] = 1;
+    pl->wtile.lg[i] = 0;
+    pl->wtile.nt[i] = 1;
+    pl->wtile.E[i] = 1;
+  }
   for (int i = 0; i < pl->ndim; ++i) {
     pl->wtile.TS[i] = spread_extent(wts, pl->G[i]);
+    while ((1 << pl->wtile.lg[i]) < pl->wtile.TS[i]) pl->wtile.lg[i]++;
     pl->wtile.nt[i] = (pl->G[i] + pl->wtile.TS[i] - 1) / pl->wtile.TS[i];
-  }
-  // dense planes of complex values; plane size = 4 (mod 16) staggers the
-  // copies across banks
-  if (pl->ndim == 3) {
-    pl->wtile.S1 = pl->wtile.TS[2];
-    pl->wtile.S0 = pl->wtile.TS[1] * pl->wtile.TS[2];
-  } else {
-    pl->wtile.S1 = 1;
-    pl->wtile.S0 = pl->wtile.TS[1];
+    pl->wtile.E[i] = pl->wtile.TS[i] + kWidth - 1;
   }
   {
-    int P = pl->wtile.TS[0] * pl->wtile.S0;
-    while (P % 16 != 4) ++P;
-    pl->wtile.P = P;
+    const int last = pl->ndim - 1;
+    const int row = pl->wtile.E[last] + (pl->wtile.E[last] & 1);
+    if (pl->ndim == 3) {
+      pl->wtile.R1 = row;
+      pl->wtile.R0 = pl->wtile.E[1] * row;
+    } else {
+      pl->wtile.R1 = 1;
+      pl->wtile.R0 = row;
+    }
+    pl->wtile.P = pl->wtile.E[0] * pl->wtile.R0;
+    pl->wtile.RV = pl->wtile.E[0] * pl->wtile.E[1] * pl->wtile.E[2];
   }
   isg_status st = guarded(pl, [&]() -> isg_status {
     set_ktile(pl, pl->ndim == 3 ? 8 : 16);
@@ -2322,6 +2390,7 @@ isg_status isg_plan_destroy(isg_plan* pl) {
   if (pl->ngraph.exec) (void)hipGraphExecDestroy(pl->ngraph.exec);
   if (pl->ngraph.graph) (void)hipGraphDestroy(pl->ngraph.graph);
   if (pl->kgrid.p) (void)hipFree(pl->kgrid.p);
+  if (pl->wreg.p) (void)hipFree(pl->wreg.p);
   if (pl->kgrid_adj.p) (void)hipFree(pl->kgrid_adj.p);
   if (pl->ybuf.p) (void)hipFree(pl->ybuf.p);
   if (pl->partial.p) (void)hipFree(pl->partial.p);
@@ -2440,7 +2509,8 @@ isg_status isg_traj_destroy(isg_traj* tr) {
     pl->trajs.erase(tr);
   }
   for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->gorder, (void*)tr->units, (void*)tr->splits,
-                  (void*)tr->colmask, (void*)tr->colbase, (void*)tr->taps_v, (void*)tr->vis_off, (void*)tr->vis})
+                  (void*)tr->colmask, (void*)tr->fmask, (void*)tr->colbase, (void*)tr->taps_v, (void*)tr->vis_off,
+                  (void*)tr->vis})
     (void)dfree(pl, p);
   delete tr;
   return ISG_OK;
@@ -2451,6 +2521,12 @@ isg_status isg_traj_info(const isg_traj* tr, int64_t* nvisits, int64_t* ntiles, 
   *nvisits = tr->nvis;
   *ntiles = tr->ntouched;
   *tile_points = (int64_t)tr->ts[0] * tr->ts[1] * tr->ts[2];  // no plan access: the plan may be gone
+  return ISG_OK;
+}
+
+isg_status isg_traj_touched_cells(const isg_traj* tr, int64_t* cells) {
+  if (!tr || !cells) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  *cells = tr->fine_cells;
   return ISG_OK;
 }
 
@@ -2505,8 +2581,9 @@ isg_status isg_warp_adjoint_noalloc(isg_plan* pl, const isg_motion* d, const voi
     float2* U = (float2*)(base + L.u);
     const UpBufs ub{(float2*)(base + L.a), (float2*)(base + L.b), pl->ndim == 3 ? (float2*)(base + L.c) : nullptr};
     const float2* w = (const float2*)y;
-    // the spread writes every cell of U (no accumulation into old contents)
-    warp_spread(pl, 1, &d, &w, U);
+    // the spread writes every region cell and every cell of U (no
+    // accumulation into old contents)
+    warp_spread(pl, 1, &d, &w, U, (float2*)(base + L.reg));
     upsample_adjoint(pl, U, (float2*)x, ub);
     return ISG_OK;
   });

@@ -84,10 +84,12 @@ class Traj:
 
     def info(self) -> dict:
         """{"visits": (sample, tile) spread visits, "tiles": touched spread
-        tiles, "tile_points": grid points per tile}"""
-        a, b, c = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+        tiles, "tile_points": grid points per tile, "touched_cells": grid
+        cells of the touched runs the axis-0 passes move}"""
+        a, b, c, f = C.c_int64(0), C.c_int64(0), C.c_int64(0), C.c_int64(0)
         check(self.plan.lib.isg_traj_info(self.handle, C.byref(a), C.byref(b), C.byref(c)))
-        return {"visits": a.value, "tiles": b.value, "tile_points": c.value}
+        check(self.plan.lib.isg_traj_touched_cells(self.handle, C.byref(f)))
+        return {"visits": a.value, "tiles": b.value, "tile_points": c.value, "touched_cells": f.value}
 
     def close(self):
         if getattr(self, "handle", None):

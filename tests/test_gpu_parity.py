@@ -191,12 +191,15 @@ def _cg_problem(isg):
 # Bounds on the FP32 CG iterate's relative distance from the FP64 oracle's
 # after 8 iterations.  lambda_max of this problem's normal operator is about
 # 52 (power iteration on the oracle), so kappa = (52 + lambda)/lambda is 11.4,
-# 105 and 5200; CG amplifies the FP32 operator's ~1e-6 relative error by up
-# to about k kappa.  The measured errors on MI355X are 9.8e-6, 6.0e-5 and
-# 5.3e-4 (x0 = 0) and 1.3e-6 (x0 != 0, lambda 0.5, 5 iterations); each bound
-# is about 5x its measured value, so a defect of a few 1e-4 relative in one
-# iteration fails.
-_CG_TOL = {5.0: 5e-5, 0.5: 3e-4, 1e-2: 3e-3}
+# 105 and 5200; CG amplifies the FP32 operator's ~1e-6 relative error (and
+# the FP32 rounding of its vectors) by up to about k kappa, and how much of
+# that bound is reached depends on the rounding pattern.  Measured on MI355X
+# with two image-space spreads that sum in different orders: 9.8e-6 and
+# 1.8e-5, 6.0e-5 and 3.3e-4, 5.3e-4 and 4.8e-4 (x0 = 0), and 1.3e-6 (x0 != 0,
+# lambda 0.5, 5 iterations).  Each bound is about 3x the larger measured
+# value, far below k kappa 1e-6 for the small lambdas, so a defect of about
+# 1e-3 relative in one iteration fails.
+_CG_TOL = {5.0: 6e-5, 0.5: 1e-3, 1e-2: 2e-3}
 _CG_TOL_X0 = 1e-5
 
 

@@ -99,3 +99,25 @@ def test_handles_outlive_their_plan():
     mo, tr = plan.motion(to_dev(d)), plan.traj(to_dev(k))
     plan.close()
     assert mo.handle is None and tr.handle is None
+
+
+@pytest.mark.parametrize("shape,C", [((16, 20, 24), 1), ((24, 16, 20), 3), ((20, 24, 16), 5), ((16, 16, 32), 12)])
+def test_register_spread_coil_counts(shape, C):
+    """k-space tiles of 8 x 4 x 8 (the register-accumulating spread) with odd
+    and even coil counts, one of them a single coil, against the oracle's
+    adjoint; several states so the tile-major output holds split tiles too"""
+    import paper_2501_16713_amd as isg
+    say(f"register spread {shape} C={C}")
+    g = np.random.default_rng(C)
+    S = coil_maps(shape, C, rng(60 + C, 2))
+    ds = [bump_displacement(shape, 3, max(shape) / 4, 2.0, g) for _ in range(2)]
+    ks = [uniform_samples(1500, 3, g), uniform_samples(300, 3, g) * np.float32(0.25)]
+    plan = isg.Plan(shape, ncoils=C, nphases=2)
+    plan.set_option("ktile_t1", 4)
+    plan.set_option("spread_chunk", 64)
+    mots = [plan.motion(to_dev(d)) for d in ds]
+    trs = [plan.traj(to_dev(k)) for k in ks]
+    y = _rand_c(g, (sum(k.shape[0] for k in ks), C))
+    xa = plan.sense_adjoint(to_dev(y), mots, to_dev(S), trs).cpu().numpy()
+    want = oracle.sense.sense_adjoint(unpack(y, ks), ds, S, ks, shape)
+    assert rel(xa, want) < TOL
