@@ -913,17 +913,15 @@ static void warp_spread(isg_plan* pl, int P, const isg_motion* const* mo, const 
 // ---------------------------------------------------------------------------
 // coil-expanded k-space front end and back end
 // ---------------------------------------------------------------------------
-// |N|^{-1/2} of the coil passes.  FP32 grids take it whole at the image
-// end (first load of the forward, last store of the adjoint).  Half-precision
-// grids take n_i^{-1/2} at the store of the axis-i pass and n_last^{-1/2} at
-// the image end, so no unnormalised pass grows a stored intermediate by up to
-// n_i (out of FP16 range) and every grid holds values on the scale of the data.
-static float image_end_scale(const isg_plan* pl) {
-  return (float)(1.0 / std::sqrt(pl->storage == kFP32 ? (double)pl->N : (double)pl->n[pl->ndim - 1]));
-}
-static float axis_store_scale(const isg_plan* pl, int i) {
-  return pl->storage == kFP32 ? 1.f : (float)(1.0 / std::sqrt((double)pl->n[i]));
-}
+// |N|^{-1/2} of the coil passes, taken whole at the image end (first load
+// of the forward, last store of the adjoint).  The pruned intermediates
+// between the passes ([n0][n1][G2][C] and [n0][G1][G2][C]) are FP32 in every
+// precision form; only the coil-expanded grid itself (the forward axis-0
+// pass's output, the spread's output) takes the plan's storage, so a
+// half-precision form rounds once per direction.  With the normalised kernel
+// and the input scale, the grid holds values on the scale of the data (at
+// most about |N|^{1/2} at the k-space centre: inside FP16 range).
+static float image_end_scale(const isg_plan* pl) { return (float)(1.0 / std::sqrt((double)pl->N)); }
 
 static Ld2CoilExpand ld2_expand(isg_plan* pl, const float2* m, const float2* Sm, int n, int n1, int L) {
   Ld2CoilExpand ld;
@@ -1021,22 +1019,22 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
     // S_c m / c(x/G) |N|^{-1/2}, centred pad, F along axis 2
     run_fft2<-1, kJFast, kBFast, 1>(pl, "fft_coil_fwd_last", G2, ld2_expand(pl, m, Sm, n2, n1, G2),
-                                 st2<S>(pl->k1buf, (int64_t)G2 * C, C, kDense),
+                                 st2<kFP32>(pl->k1buf, (int64_t)G2 * C, C, kDense),
                                  make_tile2((int64_t)n0 * n1, C, G2, C));
     // centred pad, F along axis 1 (into the row-blocked k2buf)
     run_fft2<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax1", G1,
-                                 ld2<S>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
-                                 st2_axis1<S>(pl->k2buf, pl->blk_k2, kDense, axis_store_scale(pl, 1)),
+                                 ld2<kFP32>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
+                                 st2_axis1<kFP32>(pl->k2buf, pl->blk_k2, kDense, 1.f),
                                  xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
     // centred pad, F along axis 0
-    run_fft2<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2_rows<S>(pl, pl->k2buf, pl->blk_k2, kCentred, G0),
-                                 st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), axis_store_scale(pl, 0)),
+    run_fft2<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2_rows<kFP32>(pl, pl->k2buf, pl->blk_k2, kCentred, G0),
+                                 st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), 1.f),
                                  make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
     run_fft2<-1, kJFast, kBFast, 1>(pl, "fft_coil_fwd_last", G1, ld2_expand(pl, m, Sm, n1, 0, G1),
-                                 st2<S>(pl->k1buf, (int64_t)G1 * C, C, kDense), make_tile2(n0, C, G1, C));
-    run_fft2<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2<S>(pl, pl->k1buf, 0, (int64_t)G1 * C, kCentred, G0),
-                                 st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), axis_store_scale(pl, 0)),
+                                 st2<kFP32>(pl->k1buf, (int64_t)G1 * C, C, kDense), make_tile2(n0, C, G1, C));
+    run_fft2<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2<kFP32>(pl, pl->k1buf, 0, (int64_t)G1 * C, kCentred, G0),
+                                 st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), 1.f),
                                  make_tile2(1, (int64_t)G1 * C, G0, 0));
   } else if (pl->ndim == 3) {
     {  // S_c m / c(x/G) |N|^{-1/2}, centred pad, F along axis 2
@@ -1054,20 +1052,19 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
       ld.n1 = n1;
       ld.nd = make_fastdiv(n2);
       ld.cd = make_fastdiv(C);
-      run_pass(pl, "fft_coil_fwd_last", ld, NoMid(), st_strided<S>(pl->k1buf, (int64_t)G2 * C, C, G2, G2, kDense, g), g,
+      run_pass(pl, "fft_coil_fwd_last", ld, NoMid(), st_strided<kFP32>(pl->k1buf, (int64_t)G2 * C, C, G2, G2, kDense, g), g,
                line_plan(pl, G2), -1.f, nullptr, 0.f);
     }
     {  // centred pad, F along axis 1
       TileGeom g = make_geom(n0, (int64_t)G2 * C, G1, 0);
-      run_pass(pl, "fft_coil_fwd_ax1", ld_strided<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g), NoMid(),
-               st_strided<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g,
-                             axis_store_scale(pl, 1)), g,
+      run_pass(pl, "fft_coil_fwd_ax1", ld_strided<kFP32>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g), NoMid(),
+               st_strided<kFP32>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g), g,
                line_plan(pl, G1), -1.f, nullptr, 0.f);
     }
     {  // centred pad, F along axis 0
       TileGeom g = make_geom(1, (int64_t)G1 * G2 * C, G0, 0);
-      run_pass(pl, "fft_coil_fwd_ax0", ld_strided<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g), NoMid(),
-               st_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g, axis_store_scale(pl, 0)), g,
+      run_pass(pl, "fft_coil_fwd_ax0", ld_strided<kFP32>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g), NoMid(),
+               st_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g), g,
                line_plan(pl, G0), -1.f, nullptr, 0.f);
     }
   } else {
@@ -1086,13 +1083,13 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
       ld.n1 = 0;
       ld.nd = make_fastdiv(n1);
       ld.cd = make_fastdiv(C);
-      run_pass(pl, "fft_coil_fwd_last", ld, NoMid(), st_strided<S>(pl->k1buf, (int64_t)G1 * C, C, G1, G1, kDense, g), g,
+      run_pass(pl, "fft_coil_fwd_last", ld, NoMid(), st_strided<kFP32>(pl->k1buf, (int64_t)G1 * C, C, G1, G1, kDense, g), g,
                line_plan(pl, G1), -1.f, nullptr, 0.f);
     }
     {
       TileGeom g = make_geom(1, (int64_t)G1 * C, G0, 0);
-      run_pass(pl, "fft_coil_fwd_ax0", ld_strided<S>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g), NoMid(),
-               st_strided<S>(grid, 0, (int64_t)G1 * C, G0, G0, kDense, g, axis_store_scale(pl, 0)), g,
+      run_pass(pl, "fft_coil_fwd_ax0", ld_strided<kFP32>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g), NoMid(),
+               st_strided<S>(grid, 0, (int64_t)G1 * C, G0, G0, kDense, g), g,
                line_plan(pl, G0), -1.f, nullptr, 0.f);
     }
   }
@@ -1110,39 +1107,37 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
     if (tr && tiled_adjoint(pl))  // spread output tile-major (touched tiles only)
       run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0, ld2_tiles<S>(pl, grid, tr, G0),
-                                   st2_rows<S>(pl->k2buf, pl->blk_k2, kCentred, axis_store_scale(pl, 0)),
+                                   st2_rows<kFP32>(pl->k2buf, pl->blk_k2, kCentred, 1.f),
                                    make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
     else
       run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0,
                                       ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
-                                   st2_rows<S>(pl->k2buf, pl->blk_k2, kCentred, axis_store_scale(pl, 0)),
+                                   st2_rows<kFP32>(pl->k2buf, pl->blk_k2, kCentred, 1.f),
                                    make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
     run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax1", G1,
-                                 ld2_axis1<S>(pl, pl->k2buf, pl->blk_k2, kDense, G1),
-                                 st2<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred,
-                                        axis_store_scale(pl, 1)),
+                                 ld2_axis1<kFP32>(pl, pl->k2buf, pl->blk_k2, kDense, G1),
+                                 st2<kFP32>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, 1.f),
                                  xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
-    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_last", G2, ld2<S>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
+    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_last", G2, ld2<kFP32>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
                                  st2_reduce(pl, w, Sm, n2, n1, G2, undo), make_tile2((int64_t)n0 * n1, C, G2, C));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
     run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0, ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
-                                 st2<S>(pl->k1buf, 0, (int64_t)G1 * C, kCentred, axis_store_scale(pl, 0)),
+                                 st2<kFP32>(pl->k1buf, 0, (int64_t)G1 * C, kCentred, 1.f),
                                  make_tile2(1, (int64_t)G1 * C, G0, 0));
-    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_last", G1, ld2<S>(pl, pl->k1buf, (int64_t)G1 * C, C, kDense, G1),
+    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_last", G1, ld2<kFP32>(pl, pl->k1buf, (int64_t)G1 * C, C, kDense, G1),
                                  st2_reduce(pl, w, Sm, n1, 0, G1, undo), make_tile2(n0, C, G1, C));
   } else if (pl->ndim == 3) {
     {  // F^H along axis 0, centred crop
       TileGeom g = make_geom(1, (int64_t)G1 * G2 * C, G0, 0);
       run_pass(pl, "fft_coil_adj_ax0", ld_strided<S>(grid, 0, (int64_t)G1 * G2 * C, G0, G0, kDense, g), NoMid(),
-               st_strided<S>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g, axis_store_scale(pl, 0)), g,
+               st_strided<kFP32>(pl->k2buf, 0, (int64_t)G1 * G2 * C, n0, G0, kCentred, g), g,
                line_plan(pl, G0), +1.f,
                nullptr, 0.f);
     }
     {  // F^H along axis 1, centred crop
       TileGeom g = make_geom(n0, (int64_t)G2 * C, G1, 0);
-      run_pass(pl, "fft_coil_adj_ax1", ld_strided<S>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g), NoMid(),
-               st_strided<S>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g,
-                             axis_store_scale(pl, 1)), g,
+      run_pass(pl, "fft_coil_adj_ax1", ld_strided<kFP32>(pl->k2buf, (int64_t)G1 * G2 * C, (int64_t)G2 * C, G1, G1, kDense, g), NoMid(),
+               st_strided<kFP32>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, n1, G1, kCentred, g), g,
                line_plan(pl, G1), +1.f, nullptr, 0.f);
     }
     {  // F^H along axis 2, centred crop, 1/c(x/G) |N|^{-1/2}, conj(S_c), coil sum
@@ -1159,14 +1154,14 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
       st.C = C;
       st.n1 = n1;
       st.nd = make_fastdiv(n2);
-      run_pass(pl, "fft_coil_adj_last", ld_strided<S>(pl->k1buf, (int64_t)G2 * C, C, G2, G2, kDense, g), NoMid(), st, g,
+      run_pass(pl, "fft_coil_adj_last", ld_strided<kFP32>(pl->k1buf, (int64_t)G2 * C, C, G2, G2, kDense, g), NoMid(), st, g,
                line_plan(pl, G2), +1.f, nullptr, 0.f);
     }
   } else {
     {
       TileGeom g = make_geom(1, (int64_t)G1 * C, G0, 0);
       run_pass(pl, "fft_coil_adj_ax0", ld_strided<S>(grid, 0, (int64_t)G1 * C, G0, G0, kDense, g), NoMid(),
-               st_strided<S>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g, axis_store_scale(pl, 0)), g,
+               st_strided<kFP32>(pl->k1buf, 0, (int64_t)G1 * C, n0, G0, kCentred, g), g,
                line_plan(pl, G0), +1.f,
                nullptr, 0.f);
     }
@@ -1184,7 +1179,7 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
       st.C = C;
       st.n1 = 0;
       st.nd = make_fastdiv(n1);
-      run_pass(pl, "fft_coil_adj_last", ld_strided<S>(pl->k1buf, (int64_t)G1 * C, C, G1, G1, kDense, g), NoMid(), st, g,
+      run_pass(pl, "fft_coil_adj_last", ld_strided<kFP32>(pl->k1buf, (int64_t)G1 * C, C, G1, G1, kDense, g), NoMid(), st, g,
                line_plan(pl, G1), +1.f, nullptr, 0.f);
     }
   }
@@ -1374,14 +1369,15 @@ static void set_half_scale(isg_plan* pl, const float2* v, int64_t n) {
 // scratch of the k-space stages for `nb` states processed together: their
 // grids (kgrid, [nb][NG][C]) and their visit-ordered data (ybuf)
 static void ensure_kspace(isg_plan* pl, int nb = 1, int64_t visits = 0, int64_t adj_tiles = 0) {
-  const size_t es = pl->storage == kFP32 ? 8 : 4;
+  const size_t es = pl->storage == kFP32 ? 8 : 4;  // grid elements
+  const size_t ei = sizeof(float2);                  // intermediates: FP32 in every form
   const int64_t C = pl->C;
   if (!pl->k1buf) {
     if (pl->ndim == 3) {
-      pl->k1buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->n[1] * pl->G[2] * C);
-      pl->k2buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->G[1] * pl->G[2] * C);
+      pl->k1buf = plan_alloc(pl, ei * (size_t)pl->n[0] * pl->n[1] * pl->G[2] * C);
+      pl->k2buf = plan_alloc(pl, ei * (size_t)pl->n[0] * pl->G[1] * pl->G[2] * C);
     } else {
-      pl->k1buf = plan_alloc(pl, es * (size_t)pl->n[0] * pl->G[1] * C);
+      pl->k1buf = plan_alloc(pl, ei * (size_t)pl->n[0] * pl->G[1] * C);
     }
     pl->wbuf = (float2*)plan_alloc(pl, sizeof(float2) * (size_t)pl->N * pl->P);
   }

@@ -266,6 +266,10 @@ WORKLOADS = {
     # mixed precision at scale: 256^3, 16 coils, 8 phases, ~1.5M samples/phase
     "mixed_256": Workload("mixed_256", 5, (256, 256, 256), 16, 8, 10.0, 6, 32.0,
                           [5860] * 8, 256, 20, 1e-3, 30),
+    # the same at 128^3 (16 coils, 8 phases, a quarter of the spokes: the same
+    # radial sampling density), small enough for a 30-iteration FP64 CG
+    "mixed_128": Workload("mixed_128", 6, (128, 128, 128), 16, 8, 10.0, 6, 16.0,
+                          [1460] * 8, 128, 20, 1e-3, 30),
 }
 
 

@@ -13,8 +13,8 @@ Each is checked with the options bench.py times for its headline form (row
 blocking 2, k-space tile extent 4, spread chunk 1024, all 6 states per
 k-space launch, graph replay) and with the plain options (no blocking, tile
 extent 8, chunk 512, one state per launch, no graph): 1e-5 relative L2 for
-FP32 grids, 1e-3 for FP16 grids; BF16 grids against their own bound 2^-8
-(8-bit significand), the error printed per result."""
+FP32 grids, 1e-3 for FP16 and BF16 grids (one rounding per direction), the
+error printed per result."""
 import json
 import os
 import sys
@@ -34,7 +34,7 @@ import make_batched160_reference as ref_script  # noqa: E402  (seeded selections
 
 TUNED = {"kblock": 2, "ktile_t1": 4, "spread_chunk": 1024, "phase_batch": 6, "graph": 1}
 PLAIN = {"kblock": 0, "ktile_t1": 8, "spread_chunk": 512, "phase_batch": 1, "graph": 0}
-BARS = {"fp32": 1e-5, "fp16": 1e-3, "bf16": 2.0 ** -8}
+BARS = {"fp32": 1e-5, "fp16": 1e-3, "bf16": 1e-3}
 
 
 @pytest.fixture(scope="module")

@@ -3,13 +3,15 @@ BF16 or FP16 pairs (FP32 arithmetic in registers and LDS), against the FP64
 oracle on the 96^3, 8-coil, 192k-sample workload, with the error stated per
 result.
 
-Bars.  Each direction stores three rounded grids (after the last-axis, the
-middle-axis and the axis-0 pass).  Rounding to nearest leaves a relative
-error of at most u (u = 2^-8 for BF16's 8-bit significand, 2^-11 for FP16's
-11 bits), about u/sqrt(3) in RMS for independent errors, and three such
-stores add in quadrature to about u: 3.9e-3 for BF16 and 4.9e-4 for FP16.
-FP16 is held to the 1e-3 target; BF16 cannot reach it on A^H and is held to
-its own bound u.
+Bars.  Only the coil-expanded grid itself is stored in half precision (the
+forward axis-0 pass's output and the spread's output); the pruned
+intermediates between the FFT passes stay FP32, so each direction rounds
+once.  Rounding to nearest leaves a relative error of at most u (u = 2^-8
+for BF16's 8-bit significand, 2^-11 for FP16's 11 bits), about u/sqrt(3) in
+RMS; in the adjoint the rounding noise of the oversampled grid is white
+across the 2^3 times larger image and the crop keeps an eighth of it.  Both
+are held to the 1e-3 target (north of the measured errors by a factor of
+2 to 10).
 
 Range.  The spread of radial data piles thousands of samples onto the
 cells near the k-space centre, and a smooth image puts most of its energy
@@ -26,7 +28,7 @@ from gpu_util import pack, rel, say, to_dev, unpack
 
 pytestmark = pytest.mark.gpu
 
-BARS = {"fp16": 1e-3, "bf16": 2.0 ** -8}
+BARS = {"fp16": 1e-3, "bf16": 1e-3}
 
 
 @pytest.fixture(scope="module")

@@ -8,8 +8,9 @@ stated per result.
 * forward A_0 x at 512 seeded samples, all 16 coils;
 * adjoint A_0^H y at 4096 seeded voxels for seeded complex noise y.
 
-Bars as in test_gpu_mixed.py: 1e-5 for FP32, 1e-3 for FP16, 2^-8 (the BF16
-unit roundoff) for BF16.
+Bars as in test_gpu_mixed.py: 1e-5 for FP32, 1e-3 for FP16 and BF16 grids
+(one rounding per direction: the intermediates between the FFT passes stay
+FP32).
 """
 import json
 import os
@@ -28,7 +29,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.join(HERE, "golden"))
 import make_mixed256_reference as ref_script  # noqa: E402  (seeded selections and data only)
 
-BARS = {"fp32": 1e-5, "fp16": 1e-3, "bf16": 2.0 ** -8}
+BARS = {"fp32": 1e-5, "fp16": 1e-3, "bf16": 1e-3}
 
 
 @pytest.fixture(scope="module")
