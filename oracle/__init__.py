@@ -26,6 +26,16 @@ reordering beyond what the equation states:
 * ``cg``      - conjugate gradients on the l2 form of Eq. 11.
 * ``dense``   - brute-force dense matrices of T and G from explicit sums
                 (no FFT), used only to pin the FFT-based functions.
+* ``wavelet`` - the orthonormal multi-level Haar transform W of the
+                l1 terms of Eq. 11 and Eq. 13.
+* ``fista``   - wavelet-FISTA for Eq. 11 / Eq. 13 and the power iteration
+                for its step size.
+* ``inversion`` - Appendix 1: naive and iterative inversion of T (Eq. 12-13).
+* ``register``  - gradient-descent registration with T_d as the warp (the
+                gradient-based alternative to the demons step).
+* ``gridrecon`` - bulk-translation linear phase, Pipe-Menon density
+                compensation and direct gridding reconstruction (section
+                "Motion Capturing for Segmented Data Acquisitions").
 
 Every function is pinned in ``tests/test_oracle_*.py`` against something
 other than itself: adjoint identities, brute-force sums, exact special cases
@@ -34,3 +44,4 @@ finite differences.  The one function without such a pin is listed in its
 module header as "parity unpinned".
 """
 from . import kernel, grid, warp, kspace, sense, cg, dense  # noqa: F401
+from . import wavelet, fista, inversion, register, gridrecon  # noqa: F401
