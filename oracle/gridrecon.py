@@ -17,15 +17,18 @@ Readings (the paper gives no formulas for these steps):
   G^H(conj(ph) o y);
 * density compensation by the iteration of Pipe and Menon (MRM 1999) with
   the gridding kernel itself: w_0 = 1, w_{i+1} = w_i / (P w_i),
-  (P w)_j = sum_l w_l sum_q c(kappa_j - q) c(kappa_l - q), i.e. a spread of
-  the weights onto the oversampled grid followed by a gather at the
-  samples (unnormalised Kaiser-Bessel kernel of ``kernel``);
+  (P w)_j = sum_l w_l sum_q c~(kappa_j - q) c~(kappa_l - q), i.e. a spread
+  of the weights onto the oversampled grid followed by a gather at the
+  samples, with the Kaiser-Bessel kernel of ``kernel`` scaled to unit
+  integral per axis, c~ = c / C(0), so that w_j is about the reciprocal of
+  the number of samples per grid cell around sample j;
 * direct gridding reconstruction of multi-coil data:
   x = sum_c conj(S_c) o G^H(w o conj(ph) o y_c).
 """
 import numpy as np
 
 from .grid import gather, spread
+from .kernel import kb_ft
 from .kspace import grid_coords, nufft_adjoint, nufft_forward
 
 
@@ -51,11 +54,20 @@ def dcf(k: np.ndarray, shape, iters: int, alpha: int = 2) -> np.ndarray:
     """Pipe-Menon density compensation weights after `iters` iterations."""
     gshape = tuple(alpha * n for n in shape)
     kap = grid_coords(k, gshape)
+    unit = kb_ft(0.0) ** (2 * len(shape))  # two kernel factors per axis, each divided by C(0)
     w = np.ones(k.shape[0])
     for _ in range(iters):
-        pw = gather(spread(w.astype(np.complex128), kap, gshape), kap).real
+        pw = gather(spread(w.astype(np.complex128), kap, gshape), kap).real / unit
         w = w / pw
     return w
+
+
+def dcf_apply(w: np.ndarray, k: np.ndarray, shape, alpha: int = 2) -> np.ndarray:
+    """P w with the unit-integral kernel (the quantity the iteration drives to 1)."""
+    gshape = tuple(alpha * n for n in shape)
+    kap = grid_coords(k, gshape)
+    unit = kb_ft(0.0) ** (2 * len(shape))
+    return gather(spread(np.asarray(w, dtype=np.complex128), kap, gshape), kap).real / unit
 
 
 def grid_recon(y: np.ndarray, k: np.ndarray, S: np.ndarray, shape, w=None, t=None) -> np.ndarray:
