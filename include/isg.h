@@ -310,6 +310,100 @@ isg_status isg_cg_solve(isg_plan* plan, int nphases, const void* y,
                         const isg_traj* const* k, double lambda, int iters,
                         void* x, double* resnorm);
 
+/* ---------------------------------------------------------------------------
+ * Reconstruction layer around the operators
+ * ------------------------------------------------------------------------- */
+
+/* Translate the object during the samples of a trajectory (bulk motion;
+ * section "Motion Capturing for Segmented Data Acquisitions"): t (device
+ * float32 [M][ndim], voxels, component i along array axis i), or NULL to
+ * remove a translation set before.  Sample j of every forward model that
+ * uses the trajectory is multiplied by exp(-2 pi i k_j . t_j) (the linear
+ * phase of a shifted object), and the adjoints by its conjugate (which
+ * corrects data acquired from a shifted object by the linear phase shift);
+ * normal operators are unchanged (the phases cancel).  The phase is formed
+ * in FP64.  Synchronous. */
+isg_status isg_traj_set_shift(isg_traj* traj, const float* t);
+
+/* Density compensation weights of a trajectory by the iteration of Pipe and
+ * Menon: w = 1, then `iters` times w <- w / (P w), (P w)_j = sum_l w_l
+ * sum_q c(kappa_j - q) c(kappa_l - q) with the interpolation kernel scaled
+ * to unit integral per axis (a spread of the weights onto the oversampled
+ * grid and a gather at the samples).  w: device float32 [M].  The spread
+ * sums with atomic adds, so the last bits vary from run to run.
+ * Synchronous. */
+isg_status isg_traj_dcf(isg_plan* plan, const isg_traj* traj, int iters, float* w);
+
+/* Direct k-space gridding reconstruction (Eq. 1-2 with the "density
+ * corrected" data of the notation table), coil-combined:
+ * x = sum_c conj(S_c) . G^H(w . conj(ph) . y_c), with w the weights (device
+ * float32 [M], NULL: 1) and ph the trajectory's translation phases (if
+ * set).  y: device complex64 [M][C]; x: device complex64 image.  A plan of
+ * a lower resolution and a trajectory of the samples near the k-space origin
+ * (k rescaled to that plan's cycles/voxel) give the low-resolution image
+ * navigator of the paper's motion capture. */
+isg_status isg_grid_recon(isg_plan* plan, const isg_traj* traj, const void* y, const float* w, const void* S,
+                          void* x);
+
+/* Orthonormal Haar wavelet transform W (the sparsifying transform of Eq. 11
+ * and Eq. 13): `levels` levels of the separable one-dimensional map
+ * (a, b) -> ((a + b)/sqrt2, (a - b)/sqrt2) along every axis, the Mallat
+ * layout (low-pass band first along every axis, each level on the previous
+ * level's low-pass box).  Every n_i must be divisible by 2^levels
+ * (INVALID_ARG otherwise; levels 1..9).  x, w: device complex64 images,
+ * out-of-place.  W^H = W^{-1}. */
+isg_status isg_wavelet_forward(isg_plan* plan, int levels, const void* x, void* w);
+isg_status isg_wavelet_inverse(isg_plan* plan, int levels, const void* w, void* x);
+
+/* Largest eigenvalue of sum_p A_p^H A_p (isg_power_iteration) or of T_d^H
+ * T_d (isg_warp_power_iteration) by the power method from the caller's
+ * start vector v (device complex64 image, overwritten with the last unit
+ * iterate): v <- N v / ||N v||, `iters` times; *lmax = ||N v|| of the last
+ * step (host).  Twice lmax, or more, is the Lipschitz constant FISTA
+ * needs.  NOT_FINITE if ||N v|| is zero or not finite.  Synchronizes. */
+isg_status isg_power_iteration(isg_plan* plan, int nphases, const isg_motion* const* d, const void* S,
+                               const isg_traj* const* k, int iters, void* v, double* lmax);
+isg_status isg_warp_power_iteration(isg_plan* plan, const isg_motion* d, int iters, void* v, double* lmax);
+
+/* Wavelet-FISTA (Beck and Teboulle) with constant step 1/L for
+ *   min_x ||y - A x||^2 + lambda ||W x||_1                         (Eq. 11)
+ * over the stacked nonrigid SENSE operators, and for
+ *   min_p ||q - T_d p||^2 + lambda ||W p||_1                       (Eq. 13)
+ * (isg_warp_fista_solve, Appendix 1): x_k = W^H S(W(z_k - (2/L)(A^H A z_k -
+ * A^H y))), S the complex soft threshold at lambda/L of every detail
+ * coefficient (the approximation coefficients are not penalised), t_{k+1} =
+ * (1 + sqrt(1 + 4 t_k^2))/2, z_{k+1} = x_k + ((t_k - 1)/t_{k+1})(x_k - x_{k-1});
+ * z_1 = x_0 = the x passed in, overwritten with x_iters.  lipschitz = L
+ * must be at least 2 lambda_max(A^H A) (see the power iteration).
+ * change (host, may be NULL) receives ||x_k - x_{k-1}|| for k = 1..iters.
+ * Synchronizes. */
+isg_status isg_fista_solve(isg_plan* plan, int nphases, const void* y, const isg_motion* const* d, const void* S,
+                           const isg_traj* const* k, double lambda, double lipschitz, int levels, int iters, void* x,
+                           double* change);
+isg_status isg_warp_fista_solve(isg_plan* plan, const isg_motion* d, const void* q, double lambda, double lipschitz,
+                                int levels, int iters, void* p, double* change);
+
+/* Appendix 1, l2 form of Eq. 13: conjugate gradients on (T_d^H T_d +
+ * lambda I) p = T_d^H q, exactly `iters` iterations from the p passed in
+ * (overwritten with p_iters); resnorm (host, may be NULL) receives
+ * ||r_0|| .. ||r_iters||.  The naive inverse of Fig. 10a is isg_warp with a
+ * motion prepared from -d.  Synchronizes; CG_BREAKDOWN as isg_cg_solve. */
+isg_status isg_warp_cg_solve(isg_plan* plan, const isg_motion* d, const void* q, double lambda, int iters, void* p,
+                             double* resnorm);
+
+/* Nonrigid registration by gradient descent with T_d as the warp (the
+ * gradient-based alternative to the demons step of section "Nonrigid
+ * Respiratory Motion Correction"): minimises
+ *   E(d) = ||T_d ref - mov||^2 + mu sum_i sum_a ||D_a d_i||^2,
+ * D_a the periodic forward difference along axis a, by d <- d - step
+ * grad E(d), `iters` times; grad E = 2 Re(conj(T_d ref - mov) dT_d ref/dd)
+ * + 2 mu (-Laplacian d).  ref, mov: device complex64 images; d: device
+ * float32 [ndim][n...] (voxels), the start on entry and d_iters on return;
+ * energy (host, may be NULL) receives E(d_0) .. E(d_iters).  No motion
+ * handle is needed (the field is read directly).  Synchronizes. */
+isg_status isg_register(isg_plan* plan, const void* ref, const void* mov, double mu, double step, int iters,
+                        float* d, double* energy);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,19 @@ SIGNATURES = {
     "isg_sense_grad": (C.c_int, [_p, C.c_int, _p, _p, _p, _p, _p, _p, _p]),
     "isg_cg_solve": (C.c_int, [_p, C.c_int, _p, _p, _p, _p, C.c_double, C.c_int, _p,
                                C.POINTER(C.c_double)]),
+    "isg_traj_set_shift": (C.c_int, [_p, _p]),
+    "isg_traj_dcf": (C.c_int, [_p, _p, C.c_int, _p]),
+    "isg_grid_recon": (C.c_int, [_p, _p, _p, _p, _p, _p]),
+    "isg_wavelet_forward": (C.c_int, [_p, C.c_int, _p, _p]),
+    "isg_wavelet_inverse": (C.c_int, [_p, C.c_int, _p, _p]),
+    "isg_power_iteration": (C.c_int, [_p, C.c_int, _p, _p, _p, C.c_int, _p, C.POINTER(C.c_double)]),
+    "isg_warp_power_iteration": (C.c_int, [_p, _p, C.c_int, _p, C.POINTER(C.c_double)]),
+    "isg_fista_solve": (C.c_int, [_p, C.c_int, _p, _p, _p, _p, C.c_double, C.c_double, C.c_int, C.c_int, _p,
+                                  C.POINTER(C.c_double)]),
+    "isg_warp_fista_solve": (C.c_int, [_p, _p, _p, C.c_double, C.c_double, C.c_int, C.c_int, _p,
+                                       C.POINTER(C.c_double)]),
+    "isg_warp_cg_solve": (C.c_int, [_p, _p, _p, C.c_double, C.c_int, _p, C.POINTER(C.c_double)]),
+    "isg_register": (C.c_int, [_p, _p, _p, C.c_double, C.c_double, C.c_int, _p, C.POINTER(C.c_double)]),
 }
 
 

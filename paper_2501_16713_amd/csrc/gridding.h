@@ -539,6 +539,7 @@ struct KBatch {
   float2* partial[kMaxPhasesPerLaunch];
   Blk blk;  // row-blocked layout of every grid of the batch
   const float* oscale;  // gather: results multiplied by oscale[0] (device), unless null
+  const float2* phase[kMaxPhasesPerLaunch];  // gather into sample order: times phase[j] (bulk translation), unless null
   // half-precision grids, else null: the gather into visit order takes the
   // largest |re|, |im| of member i into ymax[i kYmaxSlots ...] (zeroed
   // beforehand); the spread stores member i times 2^spread_exp(those, dens[i])
@@ -649,7 +650,8 @@ __global__ __launch_bounds__(kGridThreads) void kgather_kernel(KBatch<typename E
       const int v1 = vis_off[j + 1];
       for (int v = vis_off[j]; v < v1; ++v) y[(int64_t)vis[v] * C + c] = acc;
     } else {
-      y[j * C + c] = acc;
+      const float2* ph = bt.phase[p];
+      y[j * C + c] = ph ? cmul(acc, ph[j]) : acc;
     }
   }
   // every lane of the wavefront is active again here
@@ -659,15 +661,23 @@ __global__ __launch_bounds__(kGridThreads) void kgather_kernel(KBatch<typename E
 // y_visit[v][c] = y[order[v]][c]: data in sample order to spread-visit order
 // (half-precision grids: also the largest |re|, |im| into the kYmaxSlots
 // words at ymax unless null)
+// With phase != null the values are multiplied by conj(phase[j]) (the
+// adjoint of a bulk translation's linear phase), with w != null by w[j]
+// (density compensation).
 __global__ __launch_bounds__(kGridThreads) void visit_permute_kernel(const float2* __restrict__ y,
                                                                      const int* __restrict__ order, int64_t nvis,
                                                                      int C, float2* __restrict__ yv,
-                                                                     unsigned* __restrict__ ymax) {
+                                                                     unsigned* __restrict__ ymax,
+                                                                     const float2* __restrict__ phase,
+                                                                     const float* __restrict__ w) {
   const int64_t e = (int64_t)blockIdx.x * kGridThreads + threadIdx.x;
   float m = 0.f;
   if (e < nvis * C) {
     const int64_t v = e / C;
-    const float2 val = y[(int64_t)order[v] * C + (e - v * C)];
+    const int64_t j = order[v];
+    float2 val = y[j * C + (e - v * C)];
+    if (phase) val = cmulc(phase[j], val);
+    if (w) val = cscale(val, w[j]);
     yv[e] = val;
     m = fmaxf(fabsf(val.x), fabsf(val.y));
   }

@@ -22,6 +22,7 @@
 #include "gridding.h"
 #include "passes.h"
 #include "solver.h"
+#include "recon.h"
 
 using namespace isg;
 
@@ -180,6 +181,8 @@ struct isg_plan {
   CgScalars* cg_sc = nullptr;
   DevBuf cg_hist;
   DevBuf tune_out;  // autotuner output image
+  DevBuf sol;       // FISTA / power iteration / registration vectors, grown on demand
+  DevBuf sol_part;  // their FP64 partial sums and histories
   hipStream_t own_stream = nullptr;  // CG capture stream when the caller's is the null stream
   int64_t bytes = 0;
   // bumped whenever device memory a captured graph may reference is freed or
@@ -284,6 +287,8 @@ struct isg_traj {
   int chunk = 0;                  // spread chunk the units were built for
   int ts[3] = {0, 0, 0};          // k-space tile shape the bins were built for
   float dens = 1.f;               // bound on the samples whose kernel reaches one grid cell
+  float* k = nullptr;             // [M][ndim] the trajectory (cycles/voxel), for the translation phases
+  float2* phase = nullptr;        // [M] exp(-2 pi i k_j . t_j) of a bulk translation, or null
   std::vector<int> tile_first;    // host: tile-sorted visits of tile t are tile_first[t] .. tile_first[t+1]
   std::vector<KTap> taps_h;       // host copy of taps (re-binning for another tile shape)
 };
@@ -1220,6 +1225,7 @@ static void kgather_t(isg_plan* pl, const KJob* jobs, int n, bool to_visits, con
       bt.taps[i] = jb.tr->taps;
       bt.count[i] = jb.tr->M;
       bt.gorder[i] = jb.tr->gorder;
+      bt.phase[i] = to_visits ? nullptr : jb.tr->phase;  // into visit order (normal operator): the phases cancel
       bt.vis_off[i] = to_visits ? jb.tr->vis_off : nullptr;
       bt.vis[i] = to_visits ? jb.tr->vis : nullptr;
       bt.yout[i] = jb.yout;
@@ -1331,12 +1337,14 @@ static void kspread_t(isg_plan* pl, const KJob* jobs, int n) {
 // data of one state in sample order -> spread-visit order (into yv); with
 // half-precision grids also the largest |re|, |im| into batch slot `slot`
 // (zeroed beforehand)
-static float2* to_visit_order(isg_plan* pl, const isg_traj* tr, const float2* y, float2* yv, int slot) {
+static float2* to_visit_order(isg_plan* pl, const isg_traj* tr, const float2* y, float2* yv, int slot,
+                              const float* w = nullptr) {
   const int64_t n = tr->nvis * pl->C;
   if (n > 0) {
     Tick tick(pl, "visit_permute");
     hipLaunchKernelGGL(visit_permute_kernel, dim3(blocks_for(n, kGridThreads)), dim3(kGridThreads), 0, pl->stream, y,
-                       tr->order, tr->nvis, pl->C, yv, pl->ymax ? pl->ymax + (size_t)slot * kYmaxSlots : nullptr);
+                       tr->order, tr->nvis, pl->C, yv, pl->ymax ? pl->ymax + (size_t)slot * kYmaxSlots : nullptr,
+                       tr->phase, w);
     LAUNCH_OK();
   }
   return yv;
@@ -1929,6 +1937,8 @@ static isg_status prepare_traj(isg_plan* pl, const float* k_dev, int64_t M, isg_
   tr->M = M;
   tr->taps = (KTap*)dmalloc(pl, sizeof(KTap) * taps.size());
   HIP_OK(hipMemcpy(tr->taps, taps.data(), sizeof(KTap) * taps.size(), hipMemcpyHostToDevice));
+  tr->k = (float*)dmalloc(pl, sizeof(float) * k.size());
+  HIP_OK(hipMemcpy(tr->k, k.data(), sizeof(float) * k.size(), hipMemcpyHostToDevice));
   bin_traj(pl, tr);
   return ISG_OK;
 }
@@ -2175,6 +2185,373 @@ static isg_status tune(isg_plan* pl, int P, const float2* x, const isg_motion* c
 }
 
 // ---------------------------------------------------------------------------
+// solvers
+// ---------------------------------------------------------------------------
+// Conjugate gradients on N x = b: apply(in, out) enqueues out = N in, rhs(out)
+// enqueues out = b; x holds x0 on entry and x_iters on return; resnorm
+// (host, may be null) receives ||r_0|| .. ||r_iters||.  Synchronizes.
+template <class Apply, class Rhs>
+static isg_status cg_core(isg_plan* pl, Apply&& apply, Rhs&& rhs, int iters, float2* xv, double* resnorm) {
+    const int64_t N = pl->N;
+    if (!pl->cg_r) {
+      pl->cg_r = (float2*)plan_alloc(pl, sizeof(float2) * N);
+      pl->cg_p = (float2*)plan_alloc(pl, sizeof(float2) * N);
+      pl->cg_q = (float2*)plan_alloc(pl, sizeof(float2) * N);
+      pl->cg_part = (double*)plan_alloc(pl, sizeof(double) * kDotBlocks);
+      pl->cg_sc = (CgScalars*)plan_alloc(pl, sizeof(CgScalars));
+    }
+    grow(pl, pl->cg_hist, sizeof(double) * (iters + 1));
+    double* hist = (double*)pl->cg_hist.p;
+    const unsigned vb = (unsigned)std::min<int64_t>(kDotBlocks, blocks_for(N, kVecThreads));
+    // r = b - N x0 with b = sum_p A_p^H y_p; p = r; rho = <r, r>.  For
+    // x0 = 0 (the usual start) N x0 is exactly zero, so r = b without an
+    // application of N: ||x0||^2, read back once, decides.
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, xv, xv, N, pl->cg_part);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb, hist);
+    LAUNCH_OK();
+    double x0_sq = -1.0;
+    HIP_OK(hipMemcpyAsync(&x0_sq, hist, sizeof(double), hipMemcpyDeviceToHost, pl->stream));
+    HIP_OK(hipStreamSynchronize(pl->stream));
+    rhs(pl->cg_p);
+    if (x0_sq == 0.0) {
+      hipLaunchKernelGGL(copy_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_p, N);
+    } else {
+      apply(xv, pl->cg_q);
+      hipLaunchKernelGGL(sub_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_p, pl->cg_q, N);
+      hipLaunchKernelGGL(copy_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_r, N);
+    }
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_r, N,
+                       pl->cg_part);
+    hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb, pl->cg_sc,
+                       hist);
+    LAUNCH_OK();
+    auto iteration = [&]() {
+      apply(pl->cg_p, pl->cg_q);
+      Tick tick(pl, "cg_vector");
+      hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_q, N,
+                         pl->cg_part);
+      hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb,
+                         pl->cg_sc);
+      hipLaunchKernelGGL(cg_update_xr_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, xv, pl->cg_r, pl->cg_p,
+                         pl->cg_q, N, pl->cg_sc, pl->cg_part);
+      hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb, pl->cg_sc,
+                         hist);
+      hipLaunchKernelGGL(cg_update_p_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_r, N,
+                         pl->cg_sc);
+      LAUNCH_OK();
+    };
+    const char* ng = getenv("ISG_NO_GRAPH");
+    const bool use_graph = iters > 1 && !(ng && atoi(ng));
+    // a graph cannot be captured on the null stream: run the solve on a
+    // plan-owned stream, ordered after the caller's work
+    hipStream_t caller = pl->stream;
+    if (use_graph && caller == nullptr) {
+      if (!pl->own_stream) HIP_OK(hipStreamCreateWithFlags(&pl->own_stream, hipStreamNonBlocking));
+      HIP_OK(hipStreamSynchronize(nullptr));
+      pl->stream = pl->own_stream;
+    }
+    struct Restore {
+      isg_plan* p;
+      hipStream_t s;
+      ~Restore() { p->stream = s; }
+    } restore{pl, caller};
+    if (use_graph) {
+      // make sure every lazily grown buffer exists before capture
+      iteration();
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      HIP_OK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
+      pl->capturing = true;
+      try {
+        iteration();
+      } catch (...) {
+        pl->capturing = false;
+        hipGraph_t g2 = nullptr;
+        (void)hipStreamEndCapture(pl->stream, &g2);
+        if (g2) (void)hipGraphDestroy(g2);
+        throw;
+      }
+      pl->capturing = false;
+      HIP_OK(hipStreamEndCapture(pl->stream, &graph));
+      HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      for (int it = 1; it < iters; ++it) HIP_OK(hipGraphLaunch(exec, pl->stream));
+      HIP_OK(hipStreamSynchronize(pl->stream));
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+    } else {
+      for (int it = 0; it < iters; ++it) iteration();
+    }
+    CgScalars sc;
+    HIP_OK(hipMemcpyAsync(&sc, pl->cg_sc, sizeof(sc), hipMemcpyDeviceToHost, pl->stream));
+    HIP_OK(hipStreamSynchronize(pl->stream));
+    if (resnorm) HIP_OK(hipMemcpy(resnorm, hist, sizeof(double) * (iters + 1), hipMemcpyDeviceToHost));
+    if (sc.breakdown) return fail(ISG_ERR_CG_BREAKDOWN, "CG breakdown: Re<p, N p> <= 0 or not finite");
+    return ISG_OK;
+}
+
+// the warp's normal operator (T^H T + lambda I) z (Eq. 13, l2 form)
+static void op_warp_normal(isg_plan* pl, const isg_motion* mo, const float2* z, double lam, float2* out) {
+  upsample(pl, z, pl->ugrid);
+  warp_gather(pl, pl->ugrid, mo, pl->mbuf);
+  const float2* w = pl->mbuf;
+  warp_spread(pl, 1, &mo, &w, pl->ugrid);
+  upsample_adjoint(pl, pl->ugrid, out);
+  if (lam != 0.0) {
+    hipLaunchKernelGGL(axpy_kernel, dim3(std::min<int64_t>(blocks_for(pl->N, kVecThreads), 4096)), dim3(kVecThreads),
+                       0, pl->stream, out, z, (float)lam, pl->N);
+    LAUNCH_OK();
+  }
+}
+
+// ---- orthonormal Haar wavelet (Mallat layout), `levels` levels ---------------
+static bool wavelet_levels_ok(const isg_plan* pl, int levels) {
+  if (levels < 1 || levels > 9) return false;
+  for (int i = 0; i < pl->ndim; ++i)
+    if (pl->n[i] % (1 << levels)) return false;
+  return true;
+}
+
+static Box full_box(const isg_plan* pl, int level) {  // box of `level` in the full image array
+  Box b;
+  b.b[0] = pl->n[0] >> level;
+  b.b[1] = pl->n[1] >> level;
+  b.b[2] = pl->ndim == 3 ? pl->n[2] >> level : 1;
+  b.s[0] = (int64_t)pl->n[1] * (pl->ndim == 3 ? pl->n[2] : 1);
+  b.s[1] = pl->ndim == 3 ? pl->n[2] : 1;
+  b.s[2] = 1;
+  return b;
+}
+
+static Box compact_box(const Box& f) {  // the same extents, stored compactly
+  Box b = f;
+  b.s[2] = 1;
+  b.s[1] = f.b[2];
+  b.s[0] = (int64_t)f.b[1] * f.b[2];
+  return b;
+}
+
+static void haar_launch(isg_plan* pl, bool inv, const float2* src, const Box& sb, float2* dst, const Box& db) {
+  const int64_t blocks = (int64_t)(sb.b[0] / 2) * (sb.b[1] / 2) * (pl->ndim == 3 ? sb.b[2] / 2 : 1);
+  const dim3 g((unsigned)((blocks + 255) / 256));
+  if (pl->ndim == 3) {
+    if (inv)
+      hipLaunchKernelGGL((haar_level_kernel<3, 1>), g, dim3(256), 0, pl->stream, src, sb, dst, db);
+    else
+      hipLaunchKernelGGL((haar_level_kernel<3, 0>), g, dim3(256), 0, pl->stream, src, sb, dst, db);
+  } else {
+    if (inv)
+      hipLaunchKernelGGL((haar_level_kernel<2, 1>), g, dim3(256), 0, pl->stream, src, sb, dst, db);
+    else
+      hipLaunchKernelGGL((haar_level_kernel<2, 0>), g, dim3(256), 0, pl->stream, src, sb, dst, db);
+  }
+  LAUNCH_OK();
+}
+
+static void box_copy(isg_plan* pl, const float2* src, const Box& sb, float2* dst, const Box& db) {
+  const int64_t n = (int64_t)sb.b[0] * sb.b[1] * sb.b[2];
+  hipLaunchKernelGGL(box_copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pl->stream, src, sb, dst, db,
+                     pl->ndim);
+  LAUNCH_OK();
+}
+
+// w = W x; tmp: scratch image (N); x != w
+static void wavelet_forward(isg_plan* pl, int levels, const float2* x, float2* w, float2* tmp) {
+  Tick tick(pl, "wavelet");
+  for (int l = 0; l < levels; ++l) {
+    const Box fb = full_box(pl, l);
+    if (l == 0) {
+      haar_launch(pl, false, x, fb, w, fb);
+    } else {  // the low-pass box of w, through tmp
+      const Box cb = compact_box(fb);
+      box_copy(pl, w, fb, tmp, cb);
+      haar_launch(pl, false, tmp, cb, w, fb);
+    }
+  }
+}
+
+// x = W^H w; tmp: scratch image (N); x != w; w is left unchanged.  x is the
+// working array: the coefficients are copied into it, then every level from
+// the coarsest on is inverted in place through tmp.
+static void wavelet_inverse(isg_plan* pl, int levels, const float2* w, float2* x, float2* tmp) {
+  Tick tick(pl, "wavelet");
+  HIP_OK(hipMemcpyAsync(x, w, sizeof(float2) * pl->N, hipMemcpyDeviceToDevice, pl->stream));
+  for (int l = levels - 1; l >= 0; --l) {
+    const Box fb = full_box(pl, l);
+    const Box cb = compact_box(fb);
+    box_copy(pl, x, fb, tmp, cb);
+    haar_launch(pl, true, tmp, cb, x, fb);
+  }
+}
+
+static void soft_threshold(isg_plan* pl, float2* w, int levels, float tau) {
+  const int n1 = pl->n[1], n2 = pl->ndim == 3 ? pl->n[2] : 1;
+  const int a0 = pl->n[0] >> levels, a1 = pl->n[1] >> levels, a2 = pl->ndim == 3 ? pl->n[2] >> levels : 1;
+  Tick tick(pl, "soft_threshold");
+  hipLaunchKernelGGL(soft_threshold_kernel, dim3(blocks_for(pl->N, 256)), dim3(256), 0, pl->stream, w, pl->N, n1, n2,
+                     a0, a1, a2, tau);
+  LAUNCH_OK();
+}
+
+// solver vectors: `count` images of N complex values, and `parts` doubles
+static float2* sol_vectors(isg_plan* pl, int count, double** part, int parts) {
+  grow(pl, pl->sol, sizeof(float2) * (size_t)pl->N * count);
+  grow(pl, pl->sol_part, sizeof(double) * (size_t)std::max(parts, 1));
+  if (part) *part = (double*)pl->sol_part.p;
+  return (float2*)pl->sol.p;
+}
+
+// ---- FISTA: x_k = W^H S_{lam/L} W (z_k - (2/L)(A^H A z_k - A^H y)) ----------
+template <class Apply, class Rhs>
+static isg_status fista_core(isg_plan* pl, Apply&& apply_AhA, Rhs&& rhs, double lam, double L, int levels, int iters,
+                             float2* x, double* change) {
+  const int64_t N = pl->N;
+  const unsigned vb = (unsigned)std::min<int64_t>(kDotBlocks, blocks_for(N, kVecThreads));
+  double* part = nullptr;
+  float2* V = sol_vectors(pl, 6, &part, kDotBlocks + iters + 1);
+  float2 *Z = V, *Q = V + N, *B = V + 2 * N, *Wc = V + 3 * N, *T = V + 4 * N, *Xn = V + 5 * N;
+  double* hist = part + kDotBlocks;
+  rhs(B);  // A^H y
+  HIP_OK(hipMemcpyAsync(Z, x, sizeof(float2) * N, hipMemcpyDeviceToDevice, pl->stream));  // z_1 = x_0
+  double t = 1.0;
+  for (int it = 0; it < iters; ++it) {
+    apply_AhA(Z, Q);
+    hipLaunchKernelGGL(fista_step_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, Xn, Z, Q, B, (float)(2.0 / L), N);
+    LAUNCH_OK();
+    wavelet_forward(pl, levels, Xn, Wc, T);
+    soft_threshold(pl, Wc, levels, (float)(lam / L));
+    wavelet_inverse(pl, levels, Wc, Xn, T);
+    const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    hipLaunchKernelGGL(fista_momentum_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, Z, x, Xn,
+                       (float)((t - 1.0) / tn), N, change ? part : nullptr);
+    if (change)
+      hipLaunchKernelGGL(norm_to_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, part, (int)vb, hist + it);
+    LAUNCH_OK();
+    t = tn;
+  }
+  HIP_OK(hipStreamSynchronize(pl->stream));
+  if (change && iters > 0) HIP_OK(hipMemcpy(change, hist, sizeof(double) * iters, hipMemcpyDeviceToHost));
+  return ISG_OK;
+}
+
+// ---- power iteration: v <- N v / ||N v|| --------------------------------------
+template <class Apply>
+static isg_status power_core(isg_plan* pl, Apply&& apply, int iters, float2* v, double* lmax) {
+  const int64_t N = pl->N;
+  const unsigned vb = (unsigned)std::min<int64_t>(kDotBlocks, blocks_for(N, kVecThreads));
+  double* part = nullptr;
+  float2* W = sol_vectors(pl, 1, &part, kDotBlocks + 1);
+  double* nrm = part + kDotBlocks;
+  // v_0 = x0 / ||x0||
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, v, v, N, part);
+  hipLaunchKernelGGL(norm_to_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, part, (int)vb, nrm);
+  hipLaunchKernelGGL(scale_by_inverse_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, v, v, nrm, N);
+  LAUNCH_OK();
+  for (int it = 0; it < iters; ++it) {
+    apply(v, W);
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, W, W, N, part);
+    hipLaunchKernelGGL(norm_to_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, part, (int)vb, nrm);
+    hipLaunchKernelGGL(scale_by_inverse_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, v, W, nrm, N);
+    LAUNCH_OK();
+  }
+  double h = 0.0;
+  HIP_OK(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, pl->stream));
+  HIP_OK(hipStreamSynchronize(pl->stream));
+  if (!std::isfinite(h) || h <= 0.0) return fail(ISG_ERR_NOT_FINITE, "power iteration: ||N v|| is zero or not finite");
+  *lmax = iters > 0 ? h : 0.0;
+  return ISG_OK;
+}
+
+// ---- registration: gradient descent on E(d) = ||T_d ref - mov||^2 + mu ||grad d||^2
+static isg_status register_core(isg_plan* pl, const float2* ref, const float2* mov, double mu, double step, int iters,
+                                float* d, double* energy) {
+  const int64_t N = pl->N;
+  const int nd = pl->ndim;
+  const unsigned vb = (unsigned)std::min<int64_t>(kDotBlocks, blocks_for(N, kVecThreads));
+  double* part = nullptr;
+  // vectors: residual r (N complex), then two fields of nd N floats (= nd N / 2 complex each)
+  float2* V = sol_vectors(pl, 1 + nd, &part, 2 * kDotBlocks + iters + 1);
+  float2* r = V;
+  float* dB = (float*)(V + N);
+  float* g = dB + (size_t)nd * N;
+  double *p1 = part, *p2 = part + kDotBlocks, *hist = part + 2 * kDotBlocks;
+  upsample(pl, ref, pl->ugrid);  // u: the reference on the oversampled grid, for every step
+  float* cur = d;
+  float* nxt = dB;
+  auto energy_at = [&](const float* dc, int k) {
+    if (nd == 3)
+      hipLaunchKernelGGL(warp_gather_kernel<3>, dim3(blocks_for(N, kGridThreads)), dim3(kGridThreads), 0, pl->stream,
+                         pl->ugrid, dc, pl->mbuf, pl->dims, pl->kb);
+    else
+      hipLaunchKernelGGL(warp_gather_kernel<2>, dim3(blocks_for(N, kGridThreads)), dim3(kGridThreads), 0, pl->stream,
+                         pl->ugrid, dc, pl->mbuf, pl->dims, pl->kb);
+    hipLaunchKernelGGL(residual_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, r, pl->mbuf, mov, N, p1);
+    if (nd == 3)
+      hipLaunchKernelGGL(smoothness_kernel<3>, dim3(vb), dim3(kVecThreads), 0, pl->stream, dc, pl->dims, p2);
+    else
+      hipLaunchKernelGGL(smoothness_kernel<2>, dim3(vb), dim3(kVecThreads), 0, pl->stream, dc, pl->dims, p2);
+    hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, p1, p2, (int)vb, mu, hist + k);
+    LAUNCH_OK();
+  };
+  for (int it = 0; it < iters; ++it) {
+    energy_at(cur, it);
+    Tick tick(pl, "register_step");
+    if (nd == 3) {
+      hipLaunchKernelGGL(warp_grad_kernel<3>, dim3(blocks_for(N, kGridThreads)), dim3(kGridThreads), 0, pl->stream,
+                         pl->ugrid, cur, r, g, pl->dims, pl->kb);
+      hipLaunchKernelGGL(register_update_kernel<3>, dim3(vb), dim3(kVecThreads), 0, pl->stream, nxt, cur, g, pl->dims,
+                         (float)mu, (float)step);
+    } else {
+      hipLaunchKernelGGL(warp_grad_kernel<2>, dim3(blocks_for(N, kGridThreads)), dim3(kGridThreads), 0, pl->stream,
+                         pl->ugrid, cur, r, g, pl->dims, pl->kb);
+      hipLaunchKernelGGL(register_update_kernel<2>, dim3(vb), dim3(kVecThreads), 0, pl->stream, nxt, cur, g, pl->dims,
+                         (float)mu, (float)step);
+    }
+    LAUNCH_OK();
+    std::swap(cur, nxt);
+  }
+  energy_at(cur, iters);
+  if (cur != d) HIP_OK(hipMemcpyAsync(d, cur, sizeof(float) * nd * N, hipMemcpyDeviceToDevice, pl->stream));
+  HIP_OK(hipStreamSynchronize(pl->stream));
+  if (energy) HIP_OK(hipMemcpy(energy, hist, sizeof(double) * (iters + 1), hipMemcpyDeviceToHost));
+  return ISG_OK;
+}
+
+// ---- direct gridding: x = sum_c conj(S_c) G^H(w conj(ph) y_c) ---------------------
+static void op_grid_recon(isg_plan* pl, const isg_traj* tr, const float2* y, const float* w, const float2* S,
+                          float2* x) {
+  const int64_t tiles = std::max<int64_t>(1, tr->ntouched);
+  ensure_kspace(pl, 1, std::max<int64_t>(1, tr->nvis), tiled_adjoint(pl) ? tiles : 0);
+  if (pl->ymax) zero_ymax(pl, pl->ymax, 1);
+  float2* yv = to_visit_order(pl, tr, y, (float2*)pl->ybuf.p, 0, w);
+  const KJob job{tr, grid_of(pl, 0), yv, nullptr, sgrid_of(pl, 0, tiles)};
+  STORAGE_DISPATCH(pl, kspread_t, pl, &job, 1);
+  STORAGE_DISPATCH(pl, coil_adjoint_t, pl, sgrid_of(pl, 0, tiles), S, x, tr, half_undo(pl, 0, tr, false));
+}
+
+// ---- Pipe-Menon density compensation -----------------------------------------
+static isg_status dcf_core(isg_plan* pl, const isg_traj* tr, int iters, float* w) {
+  const int64_t M = tr->M;
+  grow(pl, pl->sol, sizeof(float) * (size_t)pl->NG);
+  float* grid = (float*)pl->sol.p;
+  const unsigned mb = blocks_for(M, 256);
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(std::min<unsigned>(mb, 4096)), dim3(256), 0, pl->stream, w, M, 1.f);
+  LAUNCH_OK();
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(4096), dim3(256), 0, pl->stream, grid, pl->NG, 0.f);
+    if (pl->ndim == 3) {
+      hipLaunchKernelGGL(dcf_spread_kernel<3>, dim3(mb), dim3(256), 0, pl->stream, tr->taps, w, M, grid, pl->dims, pl->kb);
+      hipLaunchKernelGGL(dcf_update_kernel<3>, dim3(mb), dim3(256), 0, pl->stream, tr->taps, w, M, grid, pl->dims, pl->kb);
+    } else {
+      hipLaunchKernelGGL(dcf_spread_kernel<2>, dim3(mb), dim3(256), 0, pl->stream, tr->taps, w, M, grid, pl->dims, pl->kb);
+      hipLaunchKernelGGL(dcf_update_kernel<2>, dim3(mb), dim3(256), 0, pl->stream, tr->taps, w, M, grid, pl->dims, pl->kb);
+    }
+    LAUNCH_OK();
+  }
+  HIP_OK(hipStreamSynchronize(pl->stream));
+  return ISG_OK;
+}
+
+// ---------------------------------------------------------------------------
 // allocation-free variant of the warp adjoint: its oversampled grid and FFT
 // intermediates live in a fixed device array instead of plan memory
 // ---------------------------------------------------------------------------
@@ -2392,6 +2769,8 @@ isg_status isg_plan_destroy(isg_plan* pl) {
   if (pl->partial.p) (void)hipFree(pl->partial.p);
   if (pl->cg_hist.p) (void)hipFree(pl->cg_hist.p);
   if (pl->tune_out.p) (void)hipFree(pl->tune_out.p);
+  if (pl->sol.p) (void)hipFree(pl->sol.p);
+  if (pl->sol_part.p) (void)hipFree(pl->sol_part.p);
   if (pl->own_stream) (void)hipStreamDestroy(pl->own_stream);
   for (auto& p : pl->pending) {
     (void)hipEventDestroy(p.a);
@@ -2506,7 +2885,7 @@ isg_status isg_traj_destroy(isg_traj* tr) {
   }
   for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->gorder, (void*)tr->units, (void*)tr->splits,
                   (void*)tr->colmask, (void*)tr->fmask, (void*)tr->colbase, (void*)tr->taps_v, (void*)tr->vis_off,
-                  (void*)tr->vis})
+                  (void*)tr->vis, (void*)tr->k, (void*)tr->phase})
     (void)dfree(pl, p);
   delete tr;
   return ISG_OK;
@@ -2775,101 +3154,192 @@ isg_status isg_cg_solve(isg_plan* pl, int P, const void* y, const isg_motion* co
   st = check_phases(pl, P, d, k);
   if (st) return st;
   return guarded(pl, [&]() -> isg_status {
-    const int64_t N = pl->N;
-    if (!pl->cg_r) {
-      pl->cg_r = (float2*)plan_alloc(pl, sizeof(float2) * N);
-      pl->cg_p = (float2*)plan_alloc(pl, sizeof(float2) * N);
-      pl->cg_q = (float2*)plan_alloc(pl, sizeof(float2) * N);
-      pl->cg_part = (double*)plan_alloc(pl, sizeof(double) * kDotBlocks);
-      pl->cg_sc = (CgScalars*)plan_alloc(pl, sizeof(CgScalars));
-    }
-    grow(pl, pl->cg_hist, sizeof(double) * (iters + 1));
-    double* hist = (double*)pl->cg_hist.p;
-    float2* xv = (float2*)x;
-    const unsigned vb = (unsigned)std::min<int64_t>(kDotBlocks, blocks_for(N, kVecThreads));
-    // r = b - N x0 with b = sum_p A_p^H y_p; p = r; rho = <r, r>.  For
-    // x0 = 0 (the usual start) N x0 is exactly zero, so r = b without an
-    // application of N: ||x0||^2, read back once, decides.
-    hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, xv, xv, N, pl->cg_part);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb, hist);
-    LAUNCH_OK();
-    double x0_sq = -1.0;
-    HIP_OK(hipMemcpyAsync(&x0_sq, hist, sizeof(double), hipMemcpyDeviceToHost, pl->stream));
+    return cg_core(
+        pl, [&](const float2* in, float2* out) { op_normal(pl, P, in, lambda, d, (const float2*)S, k, out); },
+        [&](float2* out) { op_sense_adjoint(pl, P, (const float2*)y, d, (const float2*)S, k, out); }, iters,
+        (float2*)x, resnorm);
+  });
+}
+
+isg_status isg_warp_cg_solve(isg_plan* pl, const isg_motion* d, const void* q, double lambda, int iters, void* p,
+                             double* resnorm) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!d || !q || !p) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (d->plan != pl) return fail(ISG_ERR_INVALID_ARG, "motion belongs to another plan");
+  if (q == p) return fail(ISG_ERR_INVALID_ARG, "q and p must differ");
+  if (iters < 0 || iters > 100000) return fail(ISG_ERR_INVALID_ARG, "iters must be in 0..100000");
+  if (!std::isfinite(lambda)) return fail(ISG_ERR_INVALID_ARG, "lambda must be finite");
+  return guarded(pl, [&]() -> isg_status {
+    return cg_core(
+        pl, [&](const float2* in, float2* out) { op_warp_normal(pl, d, in, lambda, out); },
+        [&](float2* out) {  // T^H q
+          const float2* w = (const float2*)q;
+          warp_spread(pl, 1, &d, &w, pl->ugrid);
+          upsample_adjoint(pl, pl->ugrid, out);
+        },
+        iters, (float2*)p, resnorm);
+  });
+}
+
+isg_status isg_wavelet_forward(isg_plan* pl, int levels, const void* x, void* w) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!x || !w) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (x == w) return fail(ISG_ERR_INVALID_ARG, "the wavelet transform is out-of-place: x must differ from w");
+  if (!wavelet_levels_ok(pl, levels))
+    return fail(ISG_ERR_INVALID_ARG, "levels must be in 1..9 with every n_i divisible by 2^levels");
+  return guarded(pl, [&]() -> isg_status {
+    float2* T = sol_vectors(pl, 1, nullptr, 1);
+    wavelet_forward(pl, levels, (const float2*)x, (float2*)w, T);
+    return ISG_OK;
+  });
+}
+
+isg_status isg_wavelet_inverse(isg_plan* pl, int levels, const void* w, void* x) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!x || !w) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (x == w) return fail(ISG_ERR_INVALID_ARG, "the wavelet transform is out-of-place: x must differ from w");
+  if (!wavelet_levels_ok(pl, levels))
+    return fail(ISG_ERR_INVALID_ARG, "levels must be in 1..9 with every n_i divisible by 2^levels");
+  return guarded(pl, [&]() -> isg_status {
+    float2* T = sol_vectors(pl, 1, nullptr, 1);
+    wavelet_inverse(pl, levels, (const float2*)w, (float2*)x, T);
+    return ISG_OK;
+  });
+}
+
+isg_status isg_power_iteration(isg_plan* pl, int P, const isg_motion* const* d, const void* S,
+                               const isg_traj* const* k, int iters, void* v, double* lmax) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!S || !v || !lmax) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (iters < 1 || iters > 100000) return fail(ISG_ERR_INVALID_ARG, "iters must be in 1..100000");
+  st = check_phases(pl, P, d, k);
+  if (st) return st;
+  return guarded(pl, [&]() -> isg_status {
+    return power_core(
+        pl, [&](const float2* in, float2* out) { normal_maybe_graph(pl, P, in, 0.0, d, (const float2*)S, k, out); },
+        iters, (float2*)v, lmax);
+  });
+}
+
+isg_status isg_warp_power_iteration(isg_plan* pl, const isg_motion* d, int iters, void* v, double* lmax) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!d || !v || !lmax) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (d->plan != pl) return fail(ISG_ERR_INVALID_ARG, "motion belongs to another plan");
+  if (iters < 1 || iters > 100000) return fail(ISG_ERR_INVALID_ARG, "iters must be in 1..100000");
+  return guarded(pl, [&]() -> isg_status {
+    return power_core(pl, [&](const float2* in, float2* out) { op_warp_normal(pl, d, in, 0.0, out); }, iters,
+                      (float2*)v, lmax);
+  });
+}
+
+static isg_status fista_args(isg_plan* pl, double lambda, double lipschitz, int levels, int iters) {
+  if (!std::isfinite(lambda) || lambda < 0.0) return fail(ISG_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+  if (!std::isfinite(lipschitz) || lipschitz <= 0.0) return fail(ISG_ERR_INVALID_ARG, "lipschitz must be finite and > 0");
+  if (iters < 0 || iters > 100000) return fail(ISG_ERR_INVALID_ARG, "iters must be in 0..100000");
+  if (!wavelet_levels_ok(pl, levels))
+    return fail(ISG_ERR_INVALID_ARG, "levels must be in 1..9 with every n_i divisible by 2^levels");
+  return ISG_OK;
+}
+
+isg_status isg_fista_solve(isg_plan* pl, int P, const void* y, const isg_motion* const* d, const void* S,
+                           const isg_traj* const* k, double lambda, double lipschitz, int levels, int iters, void* x,
+                           double* change) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!y || !S || !x) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  st = fista_args(pl, lambda, lipschitz, levels, iters);
+  if (st) return st;
+  st = check_phases(pl, P, d, k);
+  if (st) return st;
+  return guarded(pl, [&]() -> isg_status {
+    return fista_core(
+        pl, [&](const float2* in, float2* out) { normal_maybe_graph(pl, P, in, 0.0, d, (const float2*)S, k, out); },
+        [&](float2* out) { op_sense_adjoint(pl, P, (const float2*)y, d, (const float2*)S, k, out); }, lambda,
+        lipschitz, levels, iters, (float2*)x, change);
+  });
+}
+
+isg_status isg_warp_fista_solve(isg_plan* pl, const isg_motion* d, const void* q, double lambda, double lipschitz,
+                                int levels, int iters, void* p, double* change) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!d || !q || !p) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (d->plan != pl) return fail(ISG_ERR_INVALID_ARG, "motion belongs to another plan");
+  if (q == p) return fail(ISG_ERR_INVALID_ARG, "q and p must differ");
+  st = fista_args(pl, lambda, lipschitz, levels, iters);
+  if (st) return st;
+  return guarded(pl, [&]() -> isg_status {
+    return fista_core(
+        pl, [&](const float2* in, float2* out) { op_warp_normal(pl, d, in, 0.0, out); },
+        [&](float2* out) {
+          const float2* w = (const float2*)q;
+          warp_spread(pl, 1, &d, &w, pl->ugrid);
+          upsample_adjoint(pl, pl->ugrid, out);
+        },
+        lambda, lipschitz, levels, iters, (float2*)p, change);
+  });
+}
+
+isg_status isg_register(isg_plan* pl, const void* ref, const void* mov, double mu, double step, int iters, float* d,
+                        double* energy) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!ref || !mov || !d) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (!std::isfinite(mu) || mu < 0.0) return fail(ISG_ERR_INVALID_ARG, "mu must be finite and >= 0");
+  if (!std::isfinite(step) || step <= 0.0) return fail(ISG_ERR_INVALID_ARG, "step must be finite and > 0");
+  if (iters < 0 || iters > 100000) return fail(ISG_ERR_INVALID_ARG, "iters must be in 0..100000");
+  return guarded(pl, [&]() -> isg_status {
+    return register_core(pl, (const float2*)ref, (const float2*)mov, mu, step, iters, d, energy);
+  });
+}
+
+isg_status isg_traj_set_shift(isg_traj* tr, const float* t) {
+  if (!tr) return fail(ISG_ERR_INVALID_ARG, "traj is NULL");
+  isg_plan* pl = tr->plan;
+  if (!pl) return fail(ISG_ERR_INVALID_ARG, "the trajectory's plan was destroyed");
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  return guarded(pl, [&]() -> isg_status {
     HIP_OK(hipStreamSynchronize(pl->stream));
-    op_sense_adjoint(pl, P, (const float2*)y, d, (const float2*)S, k, pl->cg_p);
-    if (x0_sq == 0.0) {
-      hipLaunchKernelGGL(copy_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_p, N);
-    } else {
-      op_normal(pl, P, xv, lambda, d, (const float2*)S, k, pl->cg_q);
-      hipLaunchKernelGGL(sub_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_p, pl->cg_q, N);
-      hipLaunchKernelGGL(copy_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_r, N);
+    pl->generation++;
+    if (!t) {  // back to no translation
+      if (tr->phase) HIP_OK(dfree(pl, tr->phase));
+      tr->phase = nullptr;
+      return ISG_OK;
     }
-    hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_r, pl->cg_r, N,
-                       pl->cg_part);
-    hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb, pl->cg_sc,
-                       hist);
+    if (!tr->phase) tr->phase = (float2*)dmalloc(pl, sizeof(float2) * (size_t)tr->M);
+    hipLaunchKernelGGL(shift_phase_kernel, dim3(blocks_for(tr->M, 256)), dim3(256), 0, pl->stream, tr->k, t,
+                       pl->ndim, tr->M, tr->phase);
     LAUNCH_OK();
-    auto iteration = [&]() {
-      op_normal(pl, P, pl->cg_p, lambda, d, (const float2*)S, k, pl->cg_q);
-      Tick tick(pl, "cg_vector");
-      hipLaunchKernelGGL(dot_partial_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_q, N,
-                         pl->cg_part);
-      hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb,
-                         pl->cg_sc);
-      hipLaunchKernelGGL(cg_update_xr_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, xv, pl->cg_r, pl->cg_p,
-                         pl->cg_q, N, pl->cg_sc, pl->cg_part);
-      hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kVecThreads), 0, pl->stream, pl->cg_part, (int)vb, pl->cg_sc,
-                         hist);
-      hipLaunchKernelGGL(cg_update_p_kernel, dim3(vb), dim3(kVecThreads), 0, pl->stream, pl->cg_p, pl->cg_r, N,
-                         pl->cg_sc);
-      LAUNCH_OK();
-    };
-    const char* ng = getenv("ISG_NO_GRAPH");
-    const bool use_graph = iters > 1 && !(ng && atoi(ng));
-    // a graph cannot be captured on the null stream: run the solve on a
-    // plan-owned stream, ordered after the caller's work
-    hipStream_t caller = pl->stream;
-    if (use_graph && caller == nullptr) {
-      if (!pl->own_stream) HIP_OK(hipStreamCreateWithFlags(&pl->own_stream, hipStreamNonBlocking));
-      HIP_OK(hipStreamSynchronize(nullptr));
-      pl->stream = pl->own_stream;
-    }
-    struct Restore {
-      isg_plan* p;
-      hipStream_t s;
-      ~Restore() { p->stream = s; }
-    } restore{pl, caller};
-    if (use_graph) {
-      // make sure every lazily grown buffer exists before capture
-      iteration();
-      hipGraph_t graph = nullptr;
-      hipGraphExec_t exec = nullptr;
-      HIP_OK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
-      pl->capturing = true;
-      try {
-        iteration();
-      } catch (...) {
-        pl->capturing = false;
-        hipGraph_t g2 = nullptr;
-        (void)hipStreamEndCapture(pl->stream, &g2);
-        if (g2) (void)hipGraphDestroy(g2);
-        throw;
-      }
-      pl->capturing = false;
-      HIP_OK(hipStreamEndCapture(pl->stream, &graph));
-      HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-      for (int it = 1; it < iters; ++it) HIP_OK(hipGraphLaunch(exec, pl->stream));
-      HIP_OK(hipStreamSynchronize(pl->stream));
-      (void)hipGraphExecDestroy(exec);
-      (void)hipGraphDestroy(graph);
-    } else {
-      for (int it = 0; it < iters; ++it) iteration();
-    }
-    CgScalars sc;
-    HIP_OK(hipMemcpyAsync(&sc, pl->cg_sc, sizeof(sc), hipMemcpyDeviceToHost, pl->stream));
     HIP_OK(hipStreamSynchronize(pl->stream));
-    if (resnorm) HIP_OK(hipMemcpy(resnorm, hist, sizeof(double) * (iters + 1), hipMemcpyDeviceToHost));
-    if (sc.breakdown) return fail(ISG_ERR_CG_BREAKDOWN, "CG breakdown: Re<p, N p> <= 0 or not finite");
+    return ISG_OK;
+  });
+}
+
+isg_status isg_traj_dcf(isg_plan* pl, const isg_traj* tr, int iters, float* w) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!tr || !w) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (tr->plan != pl) return fail(ISG_ERR_INVALID_ARG, "trajectory belongs to another plan");
+  if (iters < 0 || iters > 10000) return fail(ISG_ERR_INVALID_ARG, "iters must be in 0..10000");
+  return guarded(pl, [&]() -> isg_status { return dcf_core(pl, tr, iters, w); });
+}
+
+isg_status isg_grid_recon(isg_plan* pl, const isg_traj* tr, const void* y, const float* w, const void* S, void* x) {
+  isg_status st = check_plan(pl);
+  if (st) return st;
+  if (!tr || !y || !S || !x) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  if (tr->plan != pl) return fail(ISG_ERR_INVALID_ARG, "trajectory belongs to another plan");
+  for (int i = 0; i < 3; ++i)
+    if (tr->ts[i] != pl->ktile.TS[i])
+      return fail(ISG_ERR_STATE, "trajectory was prepared for another k-space tile shape: re-create it");
+  return guarded(pl, [&]() -> isg_status {
+    op_grid_recon(pl, tr, (const float2*)y, w, (const float2*)S, (float2*)x);
     return ISG_OK;
   });
 }

@@ -91,6 +91,17 @@ class Traj:
         check(self.plan.lib.isg_traj_touched_cells(self.handle, C.byref(f)))
         return {"visits": a.value, "tiles": b.value, "tile_points": c.value, "touched_cells": f.value}
 
+    def set_shift(self, t: torch.Tensor | None) -> None:
+        """Translate the object by t (float32 [M][ndim], voxels) during the
+        samples: forward models gain exp(-2 pi i k.t), adjoints its conjugate;
+        None removes the translation."""
+        self.plan._sync_stream()
+        if t is None:
+            check(self.plan.lib.isg_traj_set_shift(self.handle, None))
+            return
+        t = _require(t, torch.float32, (self.M, self.plan.ndim), "t")
+        check(self.plan.lib.isg_traj_set_shift(self.handle, _ptr(t)))
+
     def close(self):
         if getattr(self, "handle", None):
             self.plan.lib.isg_traj_destroy(self.handle)
@@ -330,3 +341,112 @@ class Plan:
         check(self.lib.isg_cg_solve(self.handle, P, _ptr(y), dm, _ptr(S), km, float(lam), int(iters),
                                     _ptr(x), hist))
         return x, list(hist)
+
+    def warp_cg_solve(self, q, motion: Motion, lam: float, iters: int, p0=None):
+        """CG on (T_d^H T_d + lam I) p = T_d^H q (Appendix 1, l2 form);
+        returns (p, residual norms [iters + 1])."""
+        q = self._image(q, "q")
+        p = torch.zeros(self.shape, dtype=torch.complex64, device=self.device) if p0 is None \
+            else self._image(p0, "p0").clone()
+        hist = (C.c_double * (iters + 1))()
+        self._sync_stream()
+        check(self.lib.isg_warp_cg_solve(self.handle, motion.handle, _ptr(q), float(lam), int(iters), _ptr(p), hist))
+        return p, list(hist)
+
+    # -- sparsity-regularised reconstruction (Eq. 11, Eq. 13) ----------------
+    def wavelet_forward(self, x, levels: int, out=None) -> torch.Tensor:
+        """W x: orthonormal Haar, `levels` levels, Mallat layout."""
+        x = self._image(x)
+        out = self._empty_image() if out is None else self._image(out, "out")
+        self._sync_stream()
+        check(self.lib.isg_wavelet_forward(self.handle, int(levels), _ptr(x), _ptr(out)))
+        return out
+
+    def wavelet_inverse(self, w, levels: int, out=None) -> torch.Tensor:
+        """W^H w."""
+        w = self._image(w, "w")
+        out = self._empty_image() if out is None else self._image(out, "out")
+        self._sync_stream()
+        check(self.lib.isg_wavelet_inverse(self.handle, int(levels), _ptr(w), _ptr(out)))
+        return out
+
+    def power_iteration(self, motions, S, trajs, iters: int, v0):
+        """Largest eigenvalue of sum_p A_p^H A_p from start vector v0;
+        returns (lambda_max estimate, last unit iterate)."""
+        S = _require(S, torch.complex64, (self.ncoils,) + self.shape, "S")
+        P, dm, km = self._handles(motions, trajs)
+        v = self._image(v0, "v0").clone()
+        lmax = C.c_double(0.0)
+        self._sync_stream()
+        check(self.lib.isg_power_iteration(self.handle, P, dm, _ptr(S), km, int(iters), _ptr(v), C.byref(lmax)))
+        return lmax.value, v
+
+    def warp_power_iteration(self, motion: Motion, iters: int, v0):
+        """Largest eigenvalue of T_d^H T_d; returns (estimate, last unit iterate)."""
+        v = self._image(v0, "v0").clone()
+        lmax = C.c_double(0.0)
+        self._sync_stream()
+        check(self.lib.isg_warp_power_iteration(self.handle, motion.handle, int(iters), _ptr(v), C.byref(lmax)))
+        return lmax.value, v
+
+    def fista_solve(self, y, motions, S, trajs, lam: float, lipschitz: float, levels: int, iters: int, x0=None):
+        """Wavelet-FISTA for ||y - A x||^2 + lam ||W x||_1 (Eq. 11); returns
+        (x, [||x_k - x_{k-1}||, k = 1..iters])."""
+        S = _require(S, torch.complex64, (self.ncoils,) + self.shape, "S")
+        P, dm, km = self._handles(motions, trajs)
+        y = _require(y, torch.complex64, (self.data_rows(trajs), self.ncoils), "y")
+        x = torch.zeros(self.shape, dtype=torch.complex64, device=self.device) if x0 is None \
+            else self._image(x0, "x0").clone()
+        hist = (C.c_double * max(iters, 1))()
+        self._sync_stream()
+        check(self.lib.isg_fista_solve(self.handle, P, _ptr(y), dm, _ptr(S), km, float(lam), float(lipschitz),
+                                       int(levels), int(iters), _ptr(x), hist))
+        return x, list(hist)[:iters]
+
+    def warp_fista_solve(self, q, motion: Motion, lam: float, lipschitz: float, levels: int, iters: int, p0=None):
+        """Wavelet-FISTA for ||q - T_d p||^2 + lam ||W p||_1 (Eq. 13)."""
+        q = self._image(q, "q")
+        p = torch.zeros(self.shape, dtype=torch.complex64, device=self.device) if p0 is None \
+            else self._image(p0, "p0").clone()
+        hist = (C.c_double * max(iters, 1))()
+        self._sync_stream()
+        check(self.lib.isg_warp_fista_solve(self.handle, motion.handle, _ptr(q), float(lam), float(lipschitz),
+                                            int(levels), int(iters), _ptr(p), hist))
+        return p, list(hist)[:iters]
+
+    # -- registration, density compensation, gridding ------------------------
+    def register(self, ref, mov, mu: float, step: float, iters: int, d0=None):
+        """Gradient descent on ||T_d ref - mov||^2 + mu sum ||D_a d_i||^2;
+        returns (d float32 [ndim][*shape], energies [iters + 1])."""
+        ref = self._image(ref, "ref")
+        mov = self._image(mov, "mov")
+        d = torch.zeros((self.ndim,) + self.shape, dtype=torch.float32, device=self.device) if d0 is None \
+            else _require(d0, torch.float32, (self.ndim,) + self.shape, "d0").clone()
+        hist = (C.c_double * (iters + 1))()
+        self._sync_stream()
+        check(self.lib.isg_register(self.handle, _ptr(ref), _ptr(mov), float(mu), float(step), int(iters),
+                                    _ptr(d), hist))
+        return d, list(hist)
+
+    def dcf(self, traj: Traj, iters: int) -> torch.Tensor:
+        """Pipe-Menon density compensation weights, float32 [M]."""
+        if traj.plan is not self:
+            raise ValueError("trajectory belongs to another plan")
+        w = torch.empty(traj.M, dtype=torch.float32, device=self.device)
+        self._sync_stream()
+        check(self.lib.isg_traj_dcf(self.handle, traj.handle, int(iters), _ptr(w)))
+        return w
+
+    def grid_recon(self, traj: Traj, y, S, w=None, out=None) -> torch.Tensor:
+        """sum_c conj(S_c) G^H(w conj(ph) y_c); y complex64 [M][C]."""
+        if traj.plan is not self:
+            raise ValueError("trajectory belongs to another plan")
+        y = _require(y, torch.complex64, (traj.M, self.ncoils), "y")
+        S = _require(S, torch.complex64, (self.ncoils,) + self.shape, "S")
+        if w is not None:
+            w = _require(w, torch.float32, (traj.M,), "w")
+        out = self._empty_image() if out is None else self._image(out, "out")
+        self._sync_stream()
+        check(self.lib.isg_grid_recon(self.handle, traj.handle, _ptr(y), _ptr(w) if w is not None else None,
+                                      _ptr(S), _ptr(out)))
+        return out

@@ -15,12 +15,16 @@ Acquisitions"), each against something other than itself:
   summation by parts of the smoothness term;
 * linear phase: the direct NDFT of a shifted compact image (exact sign and
   scale); Pipe-Menon weights: constant on a Cartesian sampling, where
-  P w = 1 exactly, and P w -> 1 for most of a random sampling.
+  P w = 1 exactly, and P w -> 1 for most of a random sampling;
+* Appendix-1 inversion: integer translations (whole-sample rolls, where the
+  naive inverse is exact up to the zero-field warp and the normal operator
+  does not depend on the shift), and CG on the l2 form well ahead of the
+  negated field for a nonrigid one.
 """
 import numpy as np
 import pytest
 
-from oracle import fista, gridrecon, kspace, register, wavelet, warp
+from oracle import fista, gridrecon, inversion, kspace, register, wavelet, warp
 from synth import bump_displacement, ellipsoid_phantom, rng
 
 R2 = np.sqrt(2.0)
@@ -231,3 +235,39 @@ def test_dcf_is_uniform_on_cartesian_samples_and_a_fixed_point():
         pw = gridrecon.dcf_apply(wr, kr, (n, n))
         med.append(np.median(np.abs(pw - 1.0)))
     assert med[0] > med[1] > med[2] and med[2] < 1e-3
+
+
+# --------------------------------------------------------------------------
+# Appendix 1: inverting a nonrigid transform
+# --------------------------------------------------------------------------
+def test_inversion_exact_for_integer_translations():
+    """an integer constant field s moves whole samples: T_s x = roll(T_0 x,
+    -s) with T_0 the (nearly identity) zero-field warp, which commutes with
+    integer rolls.  So the naive inverse T_{-s} T_s x is T_0 T_0 x (with the
+    wrong sign it would be rolled by 2s), and the normal operator does not
+    depend on s"""
+    shape = (12, 10)
+    g = np.random.default_rng(8)
+    p = _rand_c(g, shape)
+    d = np.stack([np.full(shape, 3.0), np.full(shape, -2.0)])
+    zero = np.zeros_like(d)
+    q = warp.warp(p, d)
+    assert np.allclose(q, np.roll(warp.warp(p, zero), (-3, 2), axis=(0, 1)), atol=1e-12)
+    assert np.allclose(inversion.naive(q, d), warp.warp(warp.warp(p, zero), zero), atol=1e-12)
+    assert np.linalg.norm(inversion.naive(q, d) - p) < 5e-3 * np.linalg.norm(p)
+    assert np.allclose(inversion.normal(p, d, 0.25), inversion.normal(p, zero, 0.25), atol=1e-12)
+    assert np.linalg.norm(inversion.normal(p, d, 0.25) - 1.25 * p) < 5e-3 * np.linalg.norm(p)
+
+
+def test_iterative_inverse_beats_the_negated_field():
+    """for a nonrigid field the negated field is only a first-order inverse;
+    CG on the l2 form recovers the image several times better"""
+    from oracle import cg
+    shape = (32, 32)
+    p = ellipsoid_phantom(shape, 6, rng(75, 0))
+    d = bump_displacement(shape, 3, 5.0, 2.5, rng(75, 1)).astype(np.float64)
+    q = warp.warp(p, d)
+    err_naive = np.linalg.norm(inversion.naive(q, d) - p)
+    x, hist = cg.cg(lambda v: inversion.normal(v, d, 1e-4), warp.warp_adjoint(q, d), 30)
+    assert hist[-1] < 1e-3 * hist[0]
+    assert np.linalg.norm(x - p) < 0.3 * err_naive
