@@ -51,6 +51,16 @@ def stage_bytes(tag, n, G, C, es, M=0):
     return table.get(tag)
 
 
+def kspace_bytes(stage, info, M, C, es):
+    """algorithmic bytes of one state's k-space gather or spread: the
+    touched cells of the coil grid, the 16-byte tap record per sample, and
+    the visit-ordered coil values (8 C bytes per (sample, tile) visit)"""
+    cells = info["touched_cells"] * C * es
+    if stage == "kspread":  # touched cells written; tap records and visit values read
+        return cells + info["visits"] * (16 + 8 * C)
+    return M * 16 + cells + info["visits"] * 8 * C  # footprint read; visit values written
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +80,9 @@ def main():
     ap.add_argument("--kblock", type=int, default=3, help="k-space array row blocking (log2, 0 = plain) with --no-tune")
     ap.add_argument("--cg-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip timing the reconstruction layer (wavelet, FISTA, registration, gridding recon, "
+                         "the nonrigid-transform inversion)")
     ap.add_argument("--breakdown", action="store_true", help="print a per-stage timing table to stderr")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain elementwise copy (negation) of this many MiB (counter calibration)")
@@ -202,19 +215,14 @@ def main():
     per_launch = stage_bytes(dominant, w.shape, G, w.ncoils, es)
     infos = [t.info() for t in trs]
     if dominant in ("fft_coil_fwd_ax0", "fft_coil_adj_ax0"):
-        # these passes touch only the spread tiles some sample reaches
-        tot = sum(i["tiles"] * i["tile_points"] * w.ncoils * es for i in infos)
+        # these passes move only the 8-cell runs along axis 0 that some
+        # sample's taps reach (the touched cells), one state per launch
+        tot = sum(i["touched_cells"] * w.ncoils * es for i in infos)
         per_launch = tot // len(trs) + w.shape[0] * G[1] * G[2] * w.ncoils * es
     if per_launch is None and dominant in ("kspread", "kgather"):
         # one state per launch unless batched: bytes of all states / launches
-        tot = 0
-        for i, k in zip(infos, inp["k"]):
-            tile_bytes = i["tiles"] * i["tile_points"] * w.ncoils * es
-            if dominant == "kspread":  # touched tiles written; tap records and visit data read
-                tot += tile_bytes + i["visits"] * (16 + 8 * w.ncoils)
-            else:  # tap records, touched-tile footprint read; visit-ordered values written
-                tot += k.shape[0] * 16 + tile_bytes + i["visits"] * 8 * w.ncoils
-        per_launch = tot * args.steps // max(1, dom[0])
+        per_launch = sum(kspace_bytes(dominant, i, k.shape[0], w.ncoils, es) for i, k in zip(infos, inp["k"]))
+        per_launch = per_launch * args.steps // max(1, dom[0])
     roofline = None
     if per_launch and dom[0] > 0:
         avg_ms = dom[1] / dom[0]
@@ -234,7 +242,15 @@ def main():
     else:
         head = "plain" if (args.kblock, args.ktile, args.chunk, args.batch, args.graph) == (0, 8, 512, 1, 0) \
             else "fixed"
+    golden = golden_normal(w)
     forms = {f"{head}_{args.storage}": {"ms": round(ms_per_step, 4), "options": opts}}
+    if golden is not None:
+        forms[f"{head}_{args.storage}"]["rel_err_vs_fp64"] = golden_err(ref_out, golden)
+
+    # ---- the reconstruction layer around the operator, at the same size ----
+    rows = None
+    if not args.no_rows:
+        rows = recon_rows(plan, mots, trs, x, S, stream, log)
     del plan, mots, trs
     for f in [f.strip() for f in args.forms.split(",") if f.strip()]:
         storage = f if f in ("bf16", "fp16") else "fp32"
@@ -245,6 +261,8 @@ def main():
         plain_opts = {"kblock": 0, "ktile_t1": 8, "spread_chunk": 512, "phase_batch": 1, "graph": 0}
         p2, m2, t2, o2, ms2, opts2, _ = run_form(storage, tune, None if tune else plain_opts)
         entry = {"ms": round(ms2, 4), "options": opts2}
+        if golden is not None:
+            entry["rel_err_vs_fp64"] = golden_err(o2, golden)
         if storage == args.storage:  # same storage, other options: only the summation order may differ
             diff = torch.linalg.vector_norm(o2 - ref_out) / torch.linalg.vector_norm(ref_out)
             entry["rel_diff_vs_headline"] = float(diff.item())
@@ -287,17 +305,135 @@ def main():
                    "storage": args.storage, "options": opts},
         "per_state_applies_per_s": round(value * w.nphases, 3),
         "gridding_gpts_per_s": {
+            # whole apply: both k-space directions / both warp directions per apply time
             "kspace_point_coil_interps": round(2 * total_samples * w.ncoils * value / 1e9, 4),
             "warp_voxels": round(2 * w.nphases * int(np.prod(w.shape)) * value / 1e9, 4),
+            # per kernel, from its own time in one apply (eager pass with events)
+            "per_kernel": per_kernel_gpts(stages, total_samples * w.ncoils, w.nphases * int(np.prod(w.shape))),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
         "tune": tune_report,
         "cg": cg,
+        "rows": rows,
         "stages_ms": {k: round(v[1], 4) for k, v in sorted(stages.items(), key=lambda kv: -kv[1][1])},
     }
     print(json.dumps(line), flush=True)
+
+
+def per_kernel_gpts(stages, point_coils, voxels):
+    """Gpts/s of the gridding kernels from their stage times in one apply:
+    k-space (sample, coil) interpolations for the gather (K5) and spread (K6,
+    with its split-tile reduce), voxels over all states for the warp gather
+    (K3) and spread (K4, with its halo sum)"""
+    def ms(*tags):
+        return sum(stages.get(t, (0, 0.0))[1] for t in tags)
+
+    out = {}
+    for name, pts, tags in (("K3_warp_gather", voxels, ("warp_gather",)),
+                            ("K4_warp_spread", voxels, ("warp_spread", "warp_spread_sum")),
+                            ("K5_kspace_gather", point_coils, ("kgather",)),
+                            ("K6_kspace_spread", point_coils, ("kspread", "kspread_reduce"))):
+        t = ms(*tags)
+        if t > 0:
+            out[name] = {"gpts_per_s": round(pts / (t * 1e-3) / 1e9, 3), "ms": round(t, 4)}
+    return out
+
+
+def golden_normal(w):
+    """the stored FP64 oracle values of N x at seeded voxels for this
+    workload (written by tests/golden/make_batched160_reference.py from the
+    oracle alone), or None"""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "batched160.json")
+    if w.name != "batched_160" or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("workload") != w.name or abs(rec.get("lambda", -1) - w.lam) > 0:
+        return None
+    return np.array(rec["voxels"]), np.array(rec["normal"]) @ np.array([1.0, 1j])
+
+
+def golden_err(out, golden):
+    import numpy as np
+    vox, want = golden
+    got = out.reshape(-1).cpu().numpy()[vox].astype(np.complex128)
+    return float(f"{np.linalg.norm(got - want) / np.linalg.norm(want):.3e}")
+
+
+def recon_rows(plan, mots, trs, x, S, stream, log):
+    """Per-iteration times of the reconstruction layer at the benchmark's
+    size (state 0's field, the largest state's samples), and the Appendix-1
+    inversion on the 64 x 64 warp workload: the recovery error of the naive
+    inverse (the negated field), of CG on the l2 form and of 400 iterations of
+    wavelet-FISTA with lambda = 1e-6, against the ground-truth image."""
+    import numpy as np
+    import torch
+    import paper_2501_16713_amd as isg
+    from synth import WORKLOADS, make_inputs
+
+    def timed(fn, reps, per):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return round(e0.elapsed_time(e1) / (reps * per), 4)
+
+    out = {}
+    with torch.cuda.stream(stream):
+        mo, big = mots[0], trs[-1]
+        q = plan.warp(x, mo)
+        y = plan.sense_forward(x, mots, S, trs)
+        yb = y[-big.M:].contiguous()
+        buf = torch.empty_like(x)
+        wv = plan.wavelet_forward(x, 3)
+        lam_w, _ = plan.warp_power_iteration(mo, 4, x)
+        out["warp_cg_iter_ms"] = timed(lambda: plan.warp_cg_solve(q, mo, 1e-3, 10), 2, 10)
+        out["wavelet_fwd_ms"] = timed(lambda: plan.wavelet_forward(x, 3, out=buf), 5, 1)
+        out["wavelet_inv_ms"] = timed(lambda: plan.wavelet_inverse(wv, 3, out=buf), 5, 1)
+        out["warp_fista_iter_ms"] = timed(lambda: plan.warp_fista_solve(q, mo, 1e-6, 2.2 * lam_w, 3, 10), 2, 10)
+        out["power_iter_ms"] = timed(lambda: plan.power_iteration(mots, S, trs, 3, x), 1, 3)
+        out["fista_iter_ms"] = timed(lambda: plan.fista_solve(y, mots, S, trs, 1e-3, 2.0, 3, 3), 1, 3)
+        mov = plan.warp(x, mots[1])
+        out["register_step_ms"] = timed(lambda: plan.register(x, mov, 0.05, 0.02, 10), 2, 10)
+        out["dcf_iter_ms"] = timed(lambda: plan.dcf(big, 10), 1, 10)
+        wd = plan.dcf(big, 5)
+        out["grid_recon_ms"] = timed(lambda: plan.grid_recon(big, yb, S, w=wd, out=buf), 5, 1)
+        out["grid_recon_samples"] = big.M
+
+        # Appendix 1 on the 64 x 64 warp workload
+        w1 = WORKLOADS["warp2d_64"]
+        inp = make_inputs(w1, with_traj=False)
+        p_true = torch.from_numpy(inp["x"]).to(x.device)
+        d = torch.from_numpy(inp["d"][0]).to(x.device)
+        p2 = isg.Plan(w1.shape)
+        m2, mneg = p2.motion(d), p2.motion(-d)
+        q2 = p2.warp(p_true, m2)
+
+        def err(a):
+            return float(f"{(torch.linalg.vector_norm(a - p_true) / torch.linalg.vector_norm(p_true)).item():.4e}")
+
+        l2, _ = p2.warp_power_iteration(m2, 30, q2)
+        t0 = time.time()
+        pc, _ = p2.warp_cg_solve(q2, m2, 1e-6, 100)
+        t_cg = time.time() - t0
+        t0 = time.time()
+        pf, _ = p2.warp_fista_solve(q2, m2, 1e-6, 2.2 * l2, 3, 400)
+        t_f = time.time() - t0
+        out["inversion_warp2d_64"] = {
+            "naive_rel_err": err(p2.warp(q2, mneg)),
+            "cg_rel_err": err(pc), "cg_iters": 100, "cg_lambda": 1e-6, "cg_s": round(t_cg, 4),
+            "fista_rel_err": err(pf), "fista_iters": 400, "fista_lambda": 1e-6, "fista_levels": 3,
+            "fista_s": round(t_f, 4), "lipschitz": round(2.2 * l2, 4)}
+        del p2, m2, mneg
+    log(f"reconstruction layer: {out}")
+    return out
 
 
 def device_copy_gbps(stream, mib=1024, reps=5):
@@ -334,6 +470,18 @@ def measured_traffic(stage, workload, storage):
     return rec["stages"][stage]["traffic_bytes"]
 
 
+def cpu_model():
+    """the host CPU's model name (as lscpu prints it), from /proc/cpuinfo"""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(inp, w, log):
     """The FP64 oracle timed on this host on a bounded sample of the same
     workload, scaled to applies/s.  One apply is P x (T + T^H) plus
@@ -349,9 +497,12 @@ def cpu_baseline(inp, w, log):
     from threadpoolctl import threadpool_limits
     import oracle
 
-    # scipy.fft with workers=-1 (the oracle's FFTs) starts os.cpu_count()
-    # threads; everything else in the sampled steps runs on one thread
-    cores = os.cpu_count() or 1
+    # the oracle's FFTs (scipy.fft) run on the host's CPU share: the thread
+    # count OMP_NUM_THREADS grants, else the CPUs this process may use;
+    # everything else in the sampled steps runs on one thread
+    cores = int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0)) or 1
+    saved = oracle.warp.WORKERS, oracle.kspace.WORKERS
+    oracle.warp.WORKERS = oracle.kspace.WORKERS = cores
     x = inp["x"].astype(np.complex128)
     d, k, S = inp["d"][0], inp["k"][0], inp["S"]
     shape = w.shape
@@ -376,21 +527,40 @@ def cpu_baseline(inp, w, log):
         yk = oracle.kspace.nufft_forward(S[0].astype(np.complex128) * x, k)
         oracle.kspace.nufft_adjoint(yk, k, shape)
         t_coil = time.time() - t
-    t_warp = t_up + 32 * t_gather_sub
+        # the FFT-bearing steps again with scipy.fft on one thread
+        oracle.warp.WORKERS = oracle.kspace.WORKERS = 1
+        try:
+            t = time.time()
+            oracle.warp.upsample(x)
+            t_up1 = time.time() - t
+            t = time.time()
+            yk = oracle.kspace.nufft_forward(S[0].astype(np.complex128) * x, k)
+            oracle.kspace.nufft_adjoint(yk, k, shape)
+            t_coil1 = time.time() - t
+        finally:
+            oracle.warp.WORKERS, oracle.kspace.WORKERS = saved
     t_spread = t_spread_fixed + 32 * max(0.0, t_spread_sub - t_spread_fixed)
-    t_warp_adj = t_up + t_spread
-    per_apply = w.nphases * (t_warp + t_warp_adj) + w.nphases * w.ncoils * t_coil
+
+    def per_apply_of(t_up_, t_coil_):
+        return w.nphases * (2 * t_up_ + 32 * t_gather_sub + t_spread) + w.nphases * w.ncoils * t_coil_
+
+    per_apply = per_apply_of(t_up, t_coil)
+    per_apply1 = per_apply_of(t_up1, t_coil1)
     sampled = t_up + t_gather_sub + t_spread_fixed + t_spread_sub + t_coil
     log(f"oracle sample ({sampled:.1f}s): upsample {t_up:.1f}s, gather 1/32 {t_gather_sub:.1f}s, "
         f"spread fixed {t_spread_fixed:.1f}s, spread 1/32 {t_spread_sub:.1f}s, coil unit {t_coil:.1f}s "
-        f"-> {per_apply:.0f}s per apply")
+        f"-> {per_apply:.0f}s per apply; one FFT thread: upsample {t_up1:.1f}s, coil unit {t_coil1:.1f}s "
+        f"-> {per_apply1:.0f}s per apply")
     return {"value": float(f"{1.0 / per_apply:.4g}"), "unit": "applies/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "value_one_fft_thread": float(f"{1.0 / per_apply1:.4g}"),
             "sample": (f"FP64 oracle, state 0, {sampled:.0f}s timed: one coil's G then G^H ({t_coil:.1f}s), "
                        f"the upsampling FFTs ({t_up:.1f}s, also taken for the FFTs of T^H), the warp gather "
                        f"on 1/32 of the voxels ({t_gather_sub:.1f}s) and the warp spread on the same voxels "
                        f"({t_spread_sub:.1f}s, of which a fixed {t_spread_fixed:.1f}s measured with no points); "
                        f"scaled to {w.nphases} states x {w.ncoils} coils -> {per_apply:.0f}s per apply; "
-                       f"FFTs on {cores} threads (scipy workers=-1), the rest on one")}
+                       f"FFTs on {cores} threads, the rest on one; value_one_fft_thread "
+                       f"repeats the upsampling and coil-unit steps with one FFT thread")}
 
 if __name__ == "__main__":
     main()

@@ -12,7 +12,7 @@ of bytes; both counters are scaled by what they read for it.
 
     python3 -m paper_2501_16713_amd.profile_summary --out out/normal_op_batched_160_fp32 \\
         --raw out/prof_raw -- --steps 3 --warmup 1 --cg-iters 0 --no-cpu-baseline --forms "" \\
-        --no-tune --ktile 4 --chunk 1024 --batch 6 --graph 0
+        --no-rows --no-tune --kblock 2 --ktile 4 --chunk 1024 --batch 6 --graph 0
 
 writes OUT.md (the table, with the commands) and OUT.json (read by bench.py,
 which reports the traffic of its dominant stage only while the kernel
@@ -55,7 +55,7 @@ def stage_of(kernel: str) -> str:
         return "runtime_copy (plan-time uploads)"
     if "kspread_reduce" in kernel:
         return "kspread_reduce"
-    if "kspread_kernel" in kernel:
+    if "kspread_kernel" in kernel or "kspread_reg_kernel" in kernel:
         return "kspread"
     if "kgather_kernel" in kernel:
         return "kgather"
