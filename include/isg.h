@@ -189,13 +189,22 @@ isg_status isg_plan_read_timing(isg_plan* plan, char* buf, int64_t len);
  *                         rather than G1 G2 C); 0 is plain row-major.
  *                         Default 3; plain where 2^b does not divide G1 or
  *                         a length has no register FFT.  Internal arrays
- *                         only: no input or output layout changes. */
+ *                         only: no input or output layout changes.
+ *   ISG_OPT_FFT_ADDR      1 (default): the FFT passes whose lengths and
+ *                         layouts allow it address memory through buffer
+ *                         resources (a scalar base per tile and element
+ *                         index, one 32-bit offset per lane, untouched or
+ *                         invalid elements masked by the hardware's
+ *                         out-of-range rule); 0: 64-bit addresses computed
+ *                         per lane and element everywhere.  Same results
+ *                         bit for bit. */
 typedef enum {
   ISG_OPT_SPREAD_CHUNK = 1,
   ISG_OPT_PHASE_BATCH = 2,
   ISG_OPT_GRAPH = 3,
   ISG_OPT_KTILE_T1 = 4,
-  ISG_OPT_KBLOCK = 5
+  ISG_OPT_KBLOCK = 5,
+  ISG_OPT_FFT_ADDR = 6
 } isg_option;
 
 /* Set / read an option.  INVALID_ARG for an unknown option or a value out of

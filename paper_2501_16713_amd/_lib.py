@@ -15,7 +15,7 @@ STATUS_NAMES = {
     6: "ISG_ERR_CG_BREAKDOWN", 7: "ISG_ERR_STATE",
 }
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
-OPTIONS = {"spread_chunk": 1, "phase_batch": 2, "graph": 3, "ktile_t1": 4, "kblock": 5}
+OPTIONS = {"spread_chunk": 1, "phase_batch": 2, "graph": 3, "ktile_t1": 4, "kblock": 5, "fft_addr": 6}
 
 # every symbol the header declares, with (restype, argtypes)
 _p = C.c_void_p

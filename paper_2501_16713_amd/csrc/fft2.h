@@ -163,10 +163,15 @@ __device__ __forceinline__ int slot(int k1, int n2) {
   return k1 * (L2 + 1) + n2;
 }
 
-// The kernel.  Ld: per-thread line setup + element loads at positions of the
-// L-point line (zeros outside the stored range); St: per-thread line setup +
-// element stores (positions outside a crop are skipped).  St may also request
-// an LDS epilogue (coil reduction) through St::kEpilogue.
+// The kernel.  Ld / St: per-thread line setup, then the element loads
+// (stores) of the thread.  Step 1 thread (al, bl, n2) of the tile at (a0, b0)
+// loads positions L2 n1 + n2, n1 = 0..L1-1; step 2 thread (al, bl, k1) stores
+// positions k1 + L1 k2, k2 = 0..L2-1.  Loaders and stores see the tile origin
+// and the thread's place in it separately, so that the part of an address
+// shared by the tile (and by an element index) can stay in scalar registers.
+// St may request an LDS epilogue (coil reduction) through St::kEpilogue; Ld
+// may fill a table in LDS before any load through Ld::kPrologue (its size:
+// lds_extra(ld) on the host).
 // GAP bit 0: the loads zero-pad L/2 stored values, so positions [L/4, 3L/4)
 // are zero; bit 1: the stores crop to L/2 values, so those positions are not
 // stored.  With L1 (L2) a multiple of 4 the gap is the same step-1 inputs
@@ -183,7 +188,6 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
   float2* lines = smem + L;
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
-  for (int i = tid; i < L; i += nthreads) tw[i] = ld.tw[i];
 
   int64_t tile = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
   if (g.tiles > 0) {
@@ -199,6 +203,10 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
   const int64_t b0 = (tile - ta * g.tiles_b) * g.nb;
   if (a0 >= g.A) return;
   const int nl = g.na * g.nb;
+  uint32_t* table = reinterpret_cast<uint32_t*>(lines + (size_t)nl * g.LS);
+  if constexpr (Ld::kPrologue) ld.prologue(table, a0, b0, g);
+  for (int i = tid; i < L; i += nthreads) tw[i] = ld.tw[i];
+  if constexpr (Ld::kPrologue) __syncthreads();  // the loader's table
 
   // ---- step 1: loads and the L1-point DFTs overlap the twiddle copy ----
   const bool act1 = tid < nl * L2;
@@ -206,13 +214,12 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
   float2 v[L1];
   if (act1) {
     decode<MAP1>(tid, g.nb, L2, bl, n2, al);
-    const int64_t a = a0 + al, b = b0 + bl;
-    const bool valid = a < g.A && b < g.B;
-    auto line = ld.setup(a, b, valid);
+    const bool valid = a0 + al < g.A && b0 + bl < g.B;
+    auto line = ld.setup(a0, b0, al, bl, n2, valid, table);
 #pragma unroll
     for (int n1 = 0; n1 < L1; ++n1)
       v[n1] = (kGapIn && n1 >= L1 / 4 && n1 < 3 * L1 / 4) ? make_float2(0.f, 0.f)
-                                                          : ld.template get<L>(line, L2 * n1 + n2, valid);
+                                                          : ld.template get<L1, L2>(line, n1);
     reg_dft<L1, S>(v);
   }
   __syncthreads();  // twiddle table in LDS
@@ -251,12 +258,11 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
     st.epilogue(lines, g, a0, b0);
   } else {
     if (act2) {
-      const int64_t a = a0 + al2, b = b0 + bl2;
-      const bool valid = a < g.A && b < g.B;
-      auto line = st.setup(a, b, valid);
+      const bool valid = a0 + al2 < g.A && b0 + bl2 < g.B;
+      auto line = st.setup(a0, b0, al2, bl2, k1, valid);
 #pragma unroll
       for (int k2 = 0; k2 < L2; ++k2)
-        if (!(kGapOut && k2 >= L2 / 4 && k2 < 3 * L2 / 4)) st.template put<L>(line, k1 + L1 * k2, u[k2], valid);
+        if (!(kGapOut && k2 >= L2 / 4 && k2 < 3 * L2 / 4)) st.template put<L1, L2>(line, k2, u[k2]);
     }
   }
 }
@@ -273,6 +279,16 @@ __device__ __forceinline__ int pad_src(int map, int p) {
   return p;
 }
 
+// Outside the gap the stored index is the position plus a constant of the
+// range: +L/4 (centred) or 0 (spectral) below the gap, -3L/4 (centred) or
+// -L/2 (spectral) above it, 0 for the dense map.
+template <int L>
+__device__ __forceinline__ int gap_shift(int map, bool upper) {
+  if (map == kCentred) return upper ? -(3 * L / 4) : L / 4;
+  if (map == kSpectral) return upper ? -(L / 2) : 0;
+  return 0;
+}
+
 // Load of one element that reads as zero when `on` is false.  The load is
 // issued either way (from `dummy`, any valid address, when off) and the
 // result selected afterwards: a skipped load would sit in a branch of its
@@ -284,10 +300,56 @@ __device__ __forceinline__ float2 masked_load(const typename Elem<S>::T* addr, b
   return on ? v : make_float2(0.f, 0.f);
 }
 
+// ---------------------------------------------------------------------------
+// buffer-addressed access.  A raw buffer resource (stride 0) over 2^31 bytes
+// from a base held in scalar registers; the lane supplies a 32-bit byte
+// offset.  Offsets at or above 2^31 are out of range: such a load returns
+// zero and such a store is dropped, which is how untouched or invalid
+// elements are masked without a branch or a select of the data.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kOOB = 0x80000000u;
+typedef int isg_v2i __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+  // dword 3 of a gfx9 raw buffer: 32-bit data format, no swizzle
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)kOOB, 0x00020000);
+}
+
+template <int S>
+__device__ __forceinline__ float2 buf_load(const void* base, uint32_t off) {
+  if constexpr (S == kFP32) {
+    const isg_v2i r = __builtin_amdgcn_raw_buffer_load_b64(buf_rsrc(base), off, 0, 0);
+    return __builtin_bit_cast(float2, r);
+  } else {
+    const int r = __builtin_amdgcn_raw_buffer_load_b32(buf_rsrc(base), off, 0, 0);
+    typename Elem<S>::T h;
+    __builtin_memcpy(&h, &r, sizeof(r));
+    return Elem<S>::load(&h);
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void buf_store(void* base, uint32_t off, float2 v) {
+  if constexpr (S == kFP32) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(isg_v2i, v), buf_rsrc(base), off, 0, 0);
+  } else {
+    typename Elem<S>::T h;
+    Elem<S>::store(&h, v);
+    int r;
+    __builtin_memcpy(&r, &h, sizeof(r));
+    __builtin_amdgcn_raw_buffer_store_b32(r, buf_rsrc(base), off, 0, 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// general loaders and stores: every address computed per lane and element
+// (any length, map and layout)
+// ---------------------------------------------------------------------------
 // strided load of element p of line (a, b): p[a*sa + j*sj + b]; map: dense,
 // or zero-pad of L/2 stored values (centred or spectral)
 template <int S>
 struct Ld2Strided {
+  static constexpr bool kPrologue = false;
   const typename Elem<S>::T* p;
   int64_t sa, sj;
   int tlog;     // stored position j sits at (j >> tlog) bs + (j & (2^tlog - 1)) sj
@@ -296,31 +358,40 @@ struct Ld2Strided {
   const float2* tw;
   struct Line {
     const typename Elem<S>::T* base;
+    int n2;
+    bool valid;
   };
-  __device__ Line setup(int64_t a, int64_t b, bool) const { return Line{p + a * sa + b}; }
-  template <int L>
-  __device__ float2 get(const Line& ln, int pos, bool valid) const {
-    const int j = pad_src<L>(map, pos);
+  __device__ Line setup(int64_t a0, int64_t b0, int al, int bl, int n2, bool valid, const uint32_t*) const {
+    return Line{p + (a0 + al) * sa + b0 + bl, n2, valid};
+  }
+  template <int L1, int L2>
+  __device__ float2 get(const Line& ln, int n1) const {
+    const int j = pad_src<L1 * L2>(map, L2 * n1 + ln.n2);
     return masked_load<S>(ln.base + (int64_t)(j >> tlog) * bs + (int64_t)(j & ((1 << tlog) - 1)) * sj,
-                          valid && j >= 0, tw);
+                          ln.valid && j >= 0, tw);
   }
 };
 
 // load along axis 0 of a row-blocked array: column b, stored rows j
 template <int S>
 struct Ld2Rows {
+  static constexpr bool kPrologue = false;
   const typename Elem<S>::T* p;
   Blk blk;
   int map;
   const float2* tw;
   struct Line {
     const typename Elem<S>::T* base;
+    int n2;
+    bool valid;
   };
-  __device__ Line setup(int64_t, int64_t b, bool valid) const { return Line{valid ? p + blk.col(b) : p}; }
-  template <int L>
-  __device__ float2 get(const Line& ln, int pos, bool valid) const {
-    const int j = pad_src<L>(map, pos);
-    return masked_load<S>(ln.base + (int64_t)j * blk.rs, valid && j >= 0, tw);
+  __device__ Line setup(int64_t, int64_t b0, int, int bl, int n2, bool valid, const uint32_t*) const {
+    return Line{valid ? p + blk.col(b0 + bl) : p, n2, valid};
+  }
+  template <int L1, int L2>
+  __device__ float2 get(const Line& ln, int n1) const {
+    const int j = pad_src<L1 * L2>(map, L2 * n1 + ln.n2);
+    return masked_load<S>(ln.base + (int64_t)j * blk.rs, ln.valid && j >= 0, tw);
   }
 };
 
@@ -335,12 +406,16 @@ struct St2Strided {
   float scale;  // applied to half-precision stores only
   struct Line {
     typename Elem<S>::T* base;
+    int k1;
+    bool valid;
   };
-  __device__ Line setup(int64_t a, int64_t b, bool) const { return Line{p + a * sa + b}; }
-  template <int L>
-  __device__ void put(const Line& ln, int pos, float2 v, bool valid) const {
-    const int j = pad_src<L>(map, pos);
-    if (valid && j >= 0)
+  __device__ Line setup(int64_t a0, int64_t b0, int al, int bl, int k1, bool valid) const {
+    return Line{p + (a0 + al) * sa + b0 + bl, k1, valid};
+  }
+  template <int L1, int L2>
+  __device__ void put(const Line& ln, int k2, float2 v) const {
+    const int j = pad_src<L1 * L2>(map, ln.k1 + L1 * k2);
+    if (ln.valid && j >= 0)
       Elem<S>::store(ln.base + (int64_t)(j >> tlog) * bs + (int64_t)(j & ((1 << tlog) - 1)) * sj,
                      store_scaled<S>(v, scale));
   }
@@ -356,12 +431,16 @@ struct St2Rows {
   float scale;  // applied to half-precision stores only
   struct Line {
     typename Elem<S>::T* base;
+    int k1;
+    bool valid;
   };
-  __device__ Line setup(int64_t, int64_t b, bool valid) const { return Line{valid ? p + blk.col(b) : p}; }
-  template <int L>
-  __device__ void put(const Line& ln, int pos, float2 v, bool valid) const {
-    const int j = pad_src<L>(map, pos);
-    if (valid && j >= 0) Elem<S>::store(ln.base + (int64_t)j * blk.rs, store_scaled<S>(v, scale));
+  __device__ Line setup(int64_t, int64_t b0, int, int bl, int k1, bool valid) const {
+    return Line{valid ? p + blk.col(b0 + bl) : p, k1, valid};
+  }
+  template <int L1, int L2>
+  __device__ void put(const Line& ln, int k2, float2 v) const {
+    const int j = pad_src<L1 * L2>(map, ln.k1 + L1 * k2);
+    if (ln.valid && j >= 0) Elem<S>::store(ln.base + (int64_t)j * blk.rs, store_scaled<S>(v, scale));
   }
 };
 
@@ -412,6 +491,7 @@ struct TileMask {
 // axis-0 load that reads untouched tiles as zero (dense map)
 template <int S>
 struct Ld2Masked {
+  static constexpr bool kPrologue = false;
   const typename Elem<S>::T* p;
   Blk blk;  // the grid's row-blocked layout
   TileMask tm;
@@ -419,13 +499,17 @@ struct Ld2Masked {
   struct Line {
     const typename Elem<S>::T* base;
     uint64_t mask;
+    int n2;
+    bool valid;
   };
-  __device__ Line setup(int64_t a, int64_t b, bool valid) const {
-    return Line{valid ? p + blk.col(b) : p, valid ? tm.column(b) : 0ull};
+  __device__ Line setup(int64_t, int64_t b0, int, int bl, int n2, bool valid, const uint32_t*) const {
+    const int64_t b = b0 + bl;
+    return Line{valid ? p + blk.col(b) : p, valid ? tm.column(b) : 0ull, n2, valid};
   }
-  template <int L>
-  __device__ float2 get(const Line& ln, int pos, bool valid) const {
-    const bool on = valid && ((ln.mask >> (pos >> tm.ts0_log2)) & 1ull);
+  template <int L1, int L2>
+  __device__ float2 get(const Line& ln, int n1) const {
+    const int pos = L2 * n1 + ln.n2;
+    const bool on = ln.valid && ((ln.mask >> (pos >> tm.ts0_log2)) & 1ull);
     return masked_load<S>(ln.base + (int64_t)pos * blk.rs, on, tw);
   }
 };
@@ -441,13 +525,17 @@ struct St2Masked {
   struct Line {
     typename Elem<S>::T* base;
     uint64_t mask;
+    int k1;
+    bool valid;
   };
-  __device__ Line setup(int64_t a, int64_t b, bool valid) const {
-    return Line{valid ? p + blk.col(b) : p, valid ? tm.column(b) : 0ull};
+  __device__ Line setup(int64_t, int64_t b0, int, int bl, int k1, bool valid) const {
+    const int64_t b = b0 + bl;
+    return Line{valid ? p + blk.col(b) : p, valid ? tm.column(b) : 0ull, k1, valid};
   }
-  template <int L>
-  __device__ void put(const Line& ln, int pos, float2 v, bool valid) const {
-    if (valid && ((ln.mask >> (pos >> tm.ts0_log2)) & 1ull))
+  template <int L1, int L2>
+  __device__ void put(const Line& ln, int k2, float2 v) const {
+    const int pos = ln.k1 + L1 * k2;
+    if (ln.valid && ((ln.mask >> (pos >> tm.ts0_log2)) & 1ull))
       Elem<S>::store(ln.base + (int64_t)pos * blk.rs, store_scaled<S>(v, scale));
   }
 };
@@ -458,6 +546,7 @@ struct St2Masked {
 // that column.  Untouched tiles read as zero.
 template <int S>
 struct Ld2Tiles {
+  static constexpr bool kPrologue = false;
   const typename Elem<S>::T* p;
   const uint64_t* colmask;  // per tile column: touched tiles (their slots)
   const uint64_t* fmask;    // per grid column (i1, i2): touched runs along axis 0
@@ -471,29 +560,267 @@ struct Ld2Tiles {
     const typename Elem<S>::T* base;
     uint64_t mask;  // touched tiles of the tile column
     uint64_t fine;  // touched runs of the grid column
+    int n2;
+    bool valid;
   };
-  __device__ Line setup(int64_t, int64_t b, bool valid) const {
-    if (!valid) return Line{p, 0ull, 0ull};
+  __device__ Line setup(int64_t, int64_t b0, int, int bl, int n2, bool valid, const uint32_t*) const {
+    if (!valid) return Line{p, 0ull, 0ull, n2, false};
+    const int64_t b = b0 + bl;
     const uint32_t q = cdiv.div((uint32_t)b);
     const int c = (int)(b - (int64_t)q * C);
     const uint32_t i1 = g2div.div(q);
     const int i2 = (int)(q - i1 * (uint32_t)G2);
     const int col = (int)(i1 / (uint32_t)ts1) * nt2 + i2 / ts2;
     const int l1 = (int)(i1 % (uint32_t)ts1), l2 = i2 % ts2;
-    return Line{p + (int64_t)colbase[col] * volC + (int64_t)(l1 * ts2 + l2) * C + c, colmask[col], fmask[q]};
+    return Line{p + (int64_t)colbase[col] * volC + (int64_t)(l1 * ts2 + l2) * C + c, colmask[col], fmask[q], n2,
+                true};
   }
-  template <int L>
-  __device__ float2 get(const Line& ln, int pos, bool valid) const {
+  template <int L1, int L2>
+  __device__ float2 get(const Line& ln, int n1) const {
+    const int pos = L2 * n1 + ln.n2;
     const int t0 = pos >> ts0_log2;
-    const bool on = valid && ((ln.fine >> t0) & 1ull);
+    const bool on = ln.valid && ((ln.fine >> t0) & 1ull);
     const int k = __popcll(ln.mask & ((1ull << t0) - 1ull));
     return masked_load<S>(ln.base + (int64_t)k * volC + (int64_t)(pos & ((1 << ts0_log2) - 1)) * rowC, on, tw);
   }
 };
 
+// ---------------------------------------------------------------------------
+// buffer-addressed loaders and stores of the coil and upsampling passes.
+// The tile origin's part of every address is a scalar base, each element
+// index adds a scalar offset, and the lane keeps one 32-bit byte offset for
+// the whole line, so an element costs no vector address arithmetic.  Valid
+// only where the host has checked: both lengths L1, L2 multiples of 4 (the
+// gap ranges of the maps are then whole element indices), a row-blocked
+// stride's block T dividing the element-index step (L2 for loads, L1 for
+// stores) and L/4, and every lane offset below 2^31 bytes.
+// ---------------------------------------------------------------------------
+template <int S>
+struct Ld2StridedF {
+  static constexpr bool kPrologue = false;
+  const typename Elem<S>::T* p;
+  int64_t sa, sj;
+  int tlog;  // as in Ld2Strided (30: plain stride)
+  int64_t bs;
+  int map;
+  const float2* tw;
+  struct Line {
+    const typename Elem<S>::T* base;
+    uint32_t off;
+  };
+  __device__ Line setup(int64_t a0, int64_t b0, int al, int bl, int n2, bool valid, const uint32_t*) const {
+    const int64_t row = tlog >= 30 ? (int64_t)n2 * sj
+                                   : (int64_t)(n2 >> tlog) * bs + (int64_t)(n2 & ((1 << tlog) - 1)) * sj;
+    const int64_t e = (int64_t)al * sa + bl + row;
+    return Line{p + a0 * sa + b0, valid ? (uint32_t)(e * (int64_t)sizeof(typename Elem<S>::T)) : kOOB};
+  }
+  template <int L1, int L2>
+  __device__ float2 get(const Line& ln, int n1) const {
+    const int j = L2 * n1 + gap_shift<L1 * L2>(map, n1 >= 3 * L1 / 4);  // element index's stored row
+    const int64_t r = tlog >= 30 ? (int64_t)j * sj : (int64_t)(j >> tlog) * bs;
+    return buf_load<S>(ln.base + r, ln.off);
+  }
+};
+
+template <int S>
+struct St2StridedF {
+  static constexpr bool kEpilogue = false;
+  typename Elem<S>::T* p;
+  int64_t sa, sj;
+  int tlog;
+  int64_t bs;
+  int map;
+  float scale;  // applied to half-precision stores only
+  struct Line {
+    typename Elem<S>::T* base;
+    uint32_t off;
+  };
+  __device__ Line setup(int64_t a0, int64_t b0, int al, int bl, int k1, bool valid) const {
+    const int64_t row = tlog >= 30 ? (int64_t)k1 * sj
+                                   : (int64_t)(k1 >> tlog) * bs + (int64_t)(k1 & ((1 << tlog) - 1)) * sj;
+    const int64_t e = (int64_t)al * sa + bl + row;
+    return Line{p + a0 * sa + b0, valid ? (uint32_t)(e * (int64_t)sizeof(typename Elem<S>::T)) : kOOB};
+  }
+  template <int L1, int L2>
+  __device__ void put(const Line& ln, int k2, float2 v) const {
+    const int j = L1 * k2 + gap_shift<L1 * L2>(map, k2 >= 3 * L2 / 4);
+    const int64_t r = tlog >= 30 ? (int64_t)j * sj : (int64_t)(j >> tlog) * bs;
+    buf_store<S>(ln.base + r, ln.off, store_scaled<S>(v, scale));
+  }
+};
+
+// axis 0 of a row-blocked array; the tile's nb columns must be contiguous
+template <int S>
+struct Ld2RowsF {
+  static constexpr bool kPrologue = false;
+  const typename Elem<S>::T* p;
+  Blk blk;
+  int map;
+  const float2* tw;
+  struct Line {
+    const typename Elem<S>::T* base;
+    uint32_t off;
+  };
+  __device__ Line setup(int64_t, int64_t b0, int, int bl, int n2, bool valid, const uint32_t*) const {
+    const int64_t e = bl + (int64_t)n2 * blk.rs;
+    return Line{p + blk.col(b0), valid ? (uint32_t)(e * (int64_t)sizeof(typename Elem<S>::T)) : kOOB};
+  }
+  template <int L1, int L2>
+  __device__ float2 get(const Line& ln, int n1) const {
+    const int j = L2 * n1 + gap_shift<L1 * L2>(map, n1 >= 3 * L1 / 4);
+    return buf_load<S>(ln.base + (int64_t)j * blk.rs, ln.off);
+  }
+};
+
+template <int S>
+struct St2RowsF {
+  static constexpr bool kEpilogue = false;
+  typename Elem<S>::T* p;
+  Blk blk;
+  int map;
+  float scale;
+  struct Line {
+    typename Elem<S>::T* base;
+    uint32_t off;
+  };
+  __device__ Line setup(int64_t, int64_t b0, int, int bl, int k1, bool valid) const {
+    const int64_t e = bl + (int64_t)k1 * blk.rs;
+    return Line{p + blk.col(b0), valid ? (uint32_t)(e * (int64_t)sizeof(typename Elem<S>::T)) : kOOB};
+  }
+  template <int L1, int L2>
+  __device__ void put(const Line& ln, int k2, float2 v) const {
+    const int j = L1 * k2 + gap_shift<L1 * L2>(map, k2 >= 3 * L2 / 4);
+    buf_store<S>(ln.base + (int64_t)j * blk.rs, ln.off, store_scaled<S>(v, scale));
+  }
+};
+
+// axis-0 store of the touched runs only (dense map), runs of 8 cells and L1 a
+// multiple of 8: position k1 + L1 k2 lies in run (k1 >> 3) + (L1 / 8) k2, so
+// the lane shifts its column's run mask once by k1 >> 3 and each element
+// tests a bit known at compile time
+template <int S>
+struct St2MaskedF {
+  static constexpr bool kEpilogue = false;
+  typename Elem<S>::T* p;
+  Blk blk;
+  TileMask tm;
+  float scale;
+  struct Line {
+    typename Elem<S>::T* base;
+    uint32_t off;
+    uint64_t mask;
+  };
+  __device__ Line setup(int64_t, int64_t b0, int, int bl, int k1, bool valid) const {
+    const int64_t e = bl + (int64_t)k1 * blk.rs;
+    const uint64_t m = valid ? tm.column(b0 + bl) >> (k1 >> 3) : 0ull;
+    return Line{p + blk.col(b0), (uint32_t)(e * (int64_t)sizeof(typename Elem<S>::T)), m};
+  }
+  template <int L1, int L2>
+  __device__ void put(const Line& ln, int k2, float2 v) const {
+    const bool on = (ln.mask >> ((L1 / 8) * k2)) & 1ull;
+    buf_store<S>(ln.base + (int64_t)(L1 * k2) * blk.rs, on ? ln.off : kOOB, store_scaled<S>(v, scale));
+  }
+};
+
+// Axis-0 load of the tile-major spread output through a table in LDS.  The
+// tile's nb columns b0 .. b0+nb-1 belong to at most ngp consecutive grid
+// columns q = b / C.  Before any load the workgroup writes, for each of those
+// grid columns and each run t0 of 8 cells along axis 0, the byte offset of
+// the run's first cell (coil 0), or kOOB for a run no sample reaches (and for
+// grid columns past the end).  Offsets are taken from the first touched tile
+// of the first tile column in the tile row of q0 = b0 / C: the tile columns
+// are numbered row by row and their slots follow that order, so every grid
+// column of the tile (in that tile row or the next) lies at or after it.  An
+// element at position pos of a lane's line then costs one LDS read (entry
+// (q - q0, pos >> 3)) and one add (the lane's coil and the cell within the
+// run).  Offsets stay below 2^31 bytes (checked on the host).
+template <int S>
+struct Ld2TilesF {
+  static constexpr bool kPrologue = true;
+  const typename Elem<S>::T* p;
+  const uint64_t* colmask;
+  const uint64_t* fmask;
+  const int* colbase;
+  int C, G2, ts1, ts2, nt2;
+  int nruns;   // runs along axis 0 (G0 / 8)
+  int ngp;     // table rows per tile
+  int64_t Q;   // grid columns (G1 G2)
+  int64_t volC, rowC;
+  const float2* tw;
+  struct Line {
+    const typename Elem<S>::T* base;
+    const uint32_t* row;  // the lane's table row
+    int n2;
+    uint32_t coff;        // the lane's coil, bytes
+  };
+  // grid columns and tile columns are below 2^31 (checked on the host)
+  __device__ int64_t row_base(uint32_t q0) const {  // first tile slot of q0's tile row, elements
+    const uint32_t i1 = q0 / (uint32_t)G2;
+    return (int64_t)colbase[(i1 / (uint32_t)ts1) * nt2] * volC;
+  }
+  __device__ void prologue(uint32_t* table, int64_t, int64_t b0, const Tile2&) const {
+    const uint32_t q0 = (uint32_t)b0 / (uint32_t)C;
+    const int64_t base = row_base(q0);
+    for (int e = threadIdx.x; e < ngp * nruns; e += blockDim.x) {
+      const int gp = e / nruns, t0 = e - gp * nruns;
+      const uint32_t q = q0 + gp;
+      uint32_t v = kOOB;
+      if (q < (uint32_t)Q && ((fmask[q] >> t0) & 1ull)) {
+        const uint32_t i1 = q / (uint32_t)G2, i2 = q - i1 * (uint32_t)G2;
+        const uint32_t col = (i1 / (uint32_t)ts1) * nt2 + i2 / (uint32_t)ts2;
+        const int k = __popcll(colmask[col] & ((1ull << t0) - 1ull));
+        const int64_t el = (int64_t)(colbase[col] + k) * volC +
+                           (int64_t)((i1 % (uint32_t)ts1) * ts2 + i2 % (uint32_t)ts2) * C - base;
+        v = (uint32_t)(el * (int64_t)sizeof(typename Elem<S>::T));
+      }
+      table[e] = v;
+    }
+  }
+  __device__ Line setup(int64_t, int64_t b0, int, int bl, int n2, bool, const uint32_t* table) const {
+    const uint32_t q0 = (uint32_t)b0 / (uint32_t)C;
+    const uint32_t b = (uint32_t)b0 + bl;
+    const uint32_t q = b / (uint32_t)C;
+    return Line{p + row_base(q0), table + (q - q0) * nruns, n2,
+                (b - q * (uint32_t)C) * (uint32_t)sizeof(typename Elem<S>::T)};
+  }
+  template <int L1, int L2>
+  __device__ float2 get(const Line& ln, int n1) const {
+    const int lo = (L2 * n1) & 7, hi = (L2 * n1) >> 3;  // known at compile time
+    const int s = lo + ln.n2;
+    const uint32_t e = ln.row[hi + (s >> 3)];
+    const uint32_t cell = (uint32_t)((s & 7) * rowC * (int64_t)sizeof(typename Elem<S>::T));
+    return buf_load<S>(ln.base, e + cell + ln.coff);
+  }
+};
+
+template <int S>
+struct Ld2ImageF : Ld2StridedF<S> {};
+template <int S>
+struct St2ImageF : St2StridedF<S> {};
+
+template <int S>
+inline bool half_gap(const Ld2StridedF<S>& x, int) { return x.map == kCentred || x.map == kSpectral; }
+template <int S>
+inline bool half_gap(const St2StridedF<S>& x, int) { return x.map == kCentred || x.map == kSpectral; }
+template <int S>
+inline bool half_gap(const Ld2ImageF<S>& x, int L) { return half_gap(static_cast<const Ld2StridedF<S>&>(x), L); }
+template <int S>
+inline bool half_gap(const St2ImageF<S>& x, int L) { return half_gap(static_cast<const St2StridedF<S>&>(x), L); }
+template <int S>
+inline bool half_gap(const Ld2RowsF<S>& x, int) { return x.map == kCentred || x.map == kSpectral; }
+template <int S>
+inline bool half_gap(const St2RowsF<S>& x, int) { return x.map == kCentred || x.map == kSpectral; }
+
+// LDS bytes a loader's prologue needs beyond the tile
+template <class T>
+inline size_t lds_extra(const T&) { return 0; }
+template <int S>
+inline size_t lds_extra(const Ld2TilesF<S>& x) { return sizeof(uint32_t) * (size_t)x.ngp * x.nruns; }
+
 // first pass of inverse k-space gridding: S_c . m / c(x/G) |N|^{-1/2},
 // zero-padded (centred) along the last axis; lines are (a, c)
 struct Ld2CoilExpand {
+  static constexpr bool kPrologue = false;
   const float2* m;
   const float2* S;
   AxisTabs dx;
@@ -507,9 +834,12 @@ struct Ld2CoilExpand {
     const float2* mrow;
     const float2* srow;
     float f;
+    int n2;
+    bool valid;
   };
-  __device__ Line setup(int64_t a, int64_t c, bool valid) const {
-    Line ln{m, S, 0.f};
+  __device__ Line setup(int64_t a0, int64_t b0, int al, int bl, int n2, bool valid, const uint32_t*) const {
+    const int64_t a = a0 + al, c = b0 + bl;
+    Line ln{m, S, 0.f, n2, valid};
     if (!valid) return ln;
     float f = dsc ? scale * dsc[0] : scale;
     if (n1) {
@@ -523,10 +853,10 @@ struct Ld2CoilExpand {
     ln.f = f;
     return ln;
   }
-  template <int L>
-  __device__ float2 get(const Line& ln, int pos, bool valid) const {
-    const int j = pad_src<L>(kCentred, pos);
-    const bool on = valid && j >= 0;
+  template <int L1, int L2>
+  __device__ float2 get(const Line& ln, int e1) const {  // e1: the element index (n1 is the axis-1 extent)
+    const int j = pad_src<L1 * L2>(kCentred, L2 * e1 + ln.n2);
+    const bool on = ln.valid && j >= 0;
     const int jj = on ? j : 0;  // every line's element 0 exists: unconditional loads, no branch
     const float* dl = dx.t[n1 ? 2 : 1];
     const float2 v = cscale(cmul(ln.srow[jj], ln.mrow[jj]), ln.f * dl[jj]);

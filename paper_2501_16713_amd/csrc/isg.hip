@@ -135,6 +135,7 @@ struct isg_plan {
   int opt_spread_chunk = 512;  // samples per k-space spread work unit
   int opt_phase_batch = 1;     // states per k-space gather / spread launch
   int opt_graph = 0;           // isg_normal replays a captured graph
+  int opt_fft_addr = 1;        // buffer-addressed FFT passes where allowed
   int opt_ktile_t1 = 8;        // k-space spread tile extent along axis 1
   float* hsc = nullptr;        // half-precision grids: per-call scale [s, 1/s] (device)
   double* hs_part = nullptr;   // partial sums for hsc
@@ -496,7 +497,7 @@ static void launch_fft2(isg_plan* pl, const char* tag, const Ld& ld, const St& s
   const int threads = ((nl * L2 + 63) / 64) * 64;
   if (threads > 512 || nl * L1 > threads)
     throw HipError{hipErrorInvalidConfiguration, "fft2 tile does not fit one workgroup"};
-  const size_t lds = sizeof(float2) * ((size_t)L + (size_t)nl * g.LS);
+  const size_t lds = sizeof(float2) * ((size_t)L + (size_t)nl * g.LS) + lds_extra(ld);
   if (((GAP & 1) && !half_gap(ld, L)) || ((GAP & 2) && !half_gap(st, L)))
     throw HipError{hipErrorInvalidConfiguration, "fft2 gap flags do not match the line maps"};
   auto kern = fft2_kernel<L1, L2, SG, M1, M2, Ld, St, GAP>;
@@ -535,6 +536,182 @@ static void run_fft2(isg_plan* pl, const char* tag, int L, const Ld& ld, const S
     case 512: launch_fft2<16, 32, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
     default: throw HipError{hipErrorInvalidValue, "fft2: unsupported length"};
   }
+}
+
+// ---- buffer-addressed forms (see the F loaders in fft2.h) -------------------
+// lengths whose two factors are both multiples of 4
+static bool fft2_fast_length(int L) {
+  switch (L) {
+    case 32: case 64: case 96: case 128: case 192: case 256: case 320: case 512: return true;
+    default: return false;
+  }
+}
+
+static void fft2_factors(int L, int& L1, int& L2) {
+  switch (L) {
+    case 32: L1 = 4; L2 = 8; break;
+    case 64: L1 = 8; L2 = 8; break;
+    case 96: L1 = 8; L2 = 12; break;
+    case 128: L1 = 8; L2 = 16; break;
+    case 192: L1 = 12; L2 = 16; break;
+    case 256: L1 = 16; L2 = 16; break;
+    case 320: L1 = 16; L2 = 20; break;
+    case 512: L1 = 16; L2 = 32; break;
+    default: L1 = L2 = 0; break;
+  }
+}
+
+constexpr int64_t kLaneSpan = (int64_t)1 << 31;  // lane byte offsets stay below this
+
+// largest lane offset (elements) of a strided access: the tile's lines and
+// the per-lane part of the row, `step` the element-index step (rows L2 for
+// loads, L1 for stores), `cnt` the lane's part (n2 < L2 or k1 < L1)
+static int64_t strided_lane_span(int64_t sa, int64_t sj, int tlog, int64_t bs, const Tile2& g, int cnt) {
+  const int64_t row = tlog >= 30 ? (int64_t)(cnt - 1) * sj
+                                 : (int64_t)((cnt - 1) >> tlog) * bs + (int64_t)((1 << tlog) - 1) * sj;
+  return (int64_t)(g.na - 1) * sa + g.nb + row;
+}
+
+template <class T>
+static bool strided_fast_ok(const T& x, int L, const Tile2& g, bool load, size_t es) {
+  int L1, L2;
+  fft2_factors(L, L1, L2);
+  const int step = load ? L2 : L1, cnt = load ? L2 : L1;
+  if (x.tlog < 30) {
+    const int blk = 1 << x.tlog;
+    if (step % blk) return false;
+    if (x.map != kDense && (L / 4) % blk) return false;
+  }
+  return strided_lane_span(x.sa, x.sj, x.tlog, x.bs, g, cnt) * (int64_t)es < kLaneSpan;
+}
+
+// the nb columns of every tile of an axis-0 pass are contiguous in the
+// row-blocked layout, and the lane offsets fit
+static bool rows_fast_ok(const Blk& blk, int L, const Tile2& g, size_t es) {
+  if (g.na != 1) return false;
+  if (blk.tlog < 30 && (((int64_t)1 << blk.tlog) * blk.g2c) % g.nb) return false;
+  return ((int64_t)g.nb + (int64_t)L * blk.rs) * (int64_t)es < kLaneSpan;
+}
+
+template <class T>
+static bool fast_ok(const T&, int, const Tile2&) { return true; }  // no buffer form: used as is
+template <int S>
+static bool fast_ok(const Ld2Strided<S>& x, int L, const Tile2& g) {
+  return strided_fast_ok(x, L, g, true, sizeof(typename Elem<S>::T));
+}
+template <int S>
+static bool fast_ok(const St2Strided<S>& x, int L, const Tile2& g) {
+  return strided_fast_ok(x, L, g, false, sizeof(typename Elem<S>::T));
+}
+template <int S>
+static bool fast_ok(const Ld2Image<S>& x, int L, const Tile2& g) {
+  return strided_fast_ok(x, L, g, true, sizeof(typename Elem<S>::T));
+}
+template <int S>
+static bool fast_ok(const St2Image<S>& x, int L, const Tile2& g) {
+  return strided_fast_ok(x, L, g, false, sizeof(typename Elem<S>::T));
+}
+template <int S>
+static bool fast_ok(const Ld2Rows<S>& x, int L, const Tile2& g) {
+  return rows_fast_ok(x.blk, L, g, sizeof(typename Elem<S>::T));
+}
+template <int S>
+static bool fast_ok(const St2Rows<S>& x, int L, const Tile2& g) {
+  return rows_fast_ok(x.blk, L, g, sizeof(typename Elem<S>::T));
+}
+template <int S>
+static bool fast_ok(const St2Masked<S>& x, int L, const Tile2& g) {
+  int L1, L2;
+  fft2_factors(L, L1, L2);
+  return x.tm.ts0_log2 == 3 && L1 % 8 == 0 && rows_fast_ok(x.blk, L, g, sizeof(typename Elem<S>::T));
+}
+template <int S>
+static bool fast_ok(const Ld2Tiles<S>& x, int L, const Tile2& g) {
+  // runs of 8 cells; one tile row of tile columns (or two) within 2^31 bytes
+  const int64_t span = 2 * (int64_t)x.nt2 * (L / 8 + 1) * x.volC * (int64_t)sizeof(typename Elem<S>::T);
+  return x.ts0_log2 == 3 && g.na == 1 && span < kLaneSpan && L / 8 <= 64 && g.B + g.nb < kLaneSpan;
+}
+
+template <class T>
+static const T& to_fast(const T& x, int, const Tile2&) { return x; }
+template <int S>
+static Ld2StridedF<S> to_fast(const Ld2Strided<S>& x, int, const Tile2&) {
+  Ld2StridedF<S> f;
+  f.p = x.p; f.sa = x.sa; f.sj = x.sj; f.tlog = x.tlog; f.bs = x.bs; f.map = x.map; f.tw = x.tw;
+  return f;
+}
+template <int S>
+static St2StridedF<S> to_fast(const St2Strided<S>& x, int, const Tile2&) {
+  St2StridedF<S> f;
+  f.p = x.p; f.sa = x.sa; f.sj = x.sj; f.tlog = x.tlog; f.bs = x.bs; f.map = x.map; f.scale = x.scale;
+  return f;
+}
+template <int S>
+static Ld2ImageF<S> to_fast(const Ld2Image<S>& x, int L, const Tile2& g) {
+  Ld2ImageF<S> f;
+  static_cast<Ld2StridedF<S>&>(f) = to_fast(static_cast<const Ld2Strided<S>&>(x), L, g);
+  return f;
+}
+template <int S>
+static St2ImageF<S> to_fast(const St2Image<S>& x, int L, const Tile2& g) {
+  St2ImageF<S> f;
+  static_cast<St2StridedF<S>&>(f) = to_fast(static_cast<const St2Strided<S>&>(x), L, g);
+  return f;
+}
+template <int S>
+static Ld2RowsF<S> to_fast(const Ld2Rows<S>& x, int, const Tile2&) {
+  Ld2RowsF<S> f;
+  f.p = x.p; f.blk = x.blk; f.map = x.map; f.tw = x.tw;
+  return f;
+}
+template <int S>
+static St2RowsF<S> to_fast(const St2Rows<S>& x, int, const Tile2&) {
+  St2RowsF<S> f;
+  f.p = x.p; f.blk = x.blk; f.map = x.map; f.scale = x.scale;
+  return f;
+}
+template <int S>
+static St2MaskedF<S> to_fast(const St2Masked<S>& x, int, const Tile2&) {
+  St2MaskedF<S> f;
+  f.p = x.p; f.blk = x.blk; f.tm = x.tm; f.scale = x.scale;
+  return f;
+}
+template <int S>
+static Ld2TilesF<S> to_fast(const Ld2Tiles<S>& x, int L, const Tile2& g) {
+  Ld2TilesF<S> f;
+  f.p = x.p; f.colmask = x.colmask; f.fmask = x.fmask; f.colbase = x.colbase;
+  f.C = x.C; f.G2 = x.G2; f.ts1 = x.ts1; f.ts2 = x.ts2; f.nt2 = x.nt2;
+  f.nruns = L / 8;
+  f.ngp = (g.nb - 1) / x.C + 2;
+  f.Q = g.B / x.C;
+  f.volC = x.volC; f.rowC = x.rowC; f.tw = x.tw;
+  return f;
+}
+
+template <int SG, int M1, int M2, int GAP, class Ld, class St>
+static void run_fft2_fast(isg_plan* pl, const char* tag, int L, const Ld& ld, const St& st, const Tile2& g) {
+  switch (L) {
+    case 32: launch_fft2<4, 8, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 64: launch_fft2<8, 8, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 96: launch_fft2<8, 12, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 128: launch_fft2<8, 16, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 192: launch_fft2<12, 16, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 256: launch_fft2<16, 16, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 320: launch_fft2<16, 20, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    case 512: launch_fft2<16, 32, SG, M1, M2, GAP>(pl, tag, ld, st, g); break;
+    default: throw HipError{hipErrorInvalidValue, "fft2: no buffer-addressed form for this length"};
+  }
+}
+
+// one register-FFT pass: the buffer-addressed form where the plan allows it
+// and both sides qualify, else the general form
+template <int SG, int M1, int M2, int GAP = 0, class Ld, class St>
+static void fft2_pass(isg_plan* pl, const char* tag, int L, const Ld& ld, const St& st, const Tile2& g) {
+  // the tile geometry the launch will use (XCD order does not change it)
+  if (pl->opt_fft_addr && fft2_fast_length(L) && fast_ok(ld, L, g) && fast_ok(st, L, g))
+    run_fft2_fast<SG, M1, M2, GAP>(pl, tag, L, to_fast(ld, L, g), to_fast(st, L, g), g);
+  else
+    run_fft2<SG, M1, M2, GAP>(pl, tag, L, ld, st, g);
 }
 
 template <int S>
@@ -668,7 +845,7 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
     // allows it (an in-place pass is safe there: a workgroup loads all its
     // lines before any store, and no line is shared between workgroups)
     if (fft2_supported(n2)) {  // F along axis 2
-      run_fft2<-1, kJFast, kJFast>(pl, "fft_up_ax2", n2, ld2_img(pl, x, n2, 1, kDense, n2),
+      fft2_pass<-1, kJFast, kJFast>(pl, "fft_up_ax2", n2, ld2_img(pl, x, n2, 1, kDense, n2),
                                    st2_img(pl->bufA, n2, 1, kDense), make_tile2((int64_t)n0 * n1, 1, n2, 1));
     } else {
       TileGeom g = make_geom((int64_t)n0 * n1, 1, n2, 0);
@@ -676,7 +853,7 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
                st_strided<kFP32>(pl->bufA, n2, 1, n2, n2, kDense, g), g, line_plan(pl, n2), -1.f, nullptr, 0.f);
     }
     if (fft2_supported(n1)) {  // F along axis 1, in place
-      run_fft2<-1, kBFast, kBFast>(pl, "fft_up_ax1", n1, ld2_img(pl, pl->bufA, (int64_t)n1 * n2, n2, kDense, n1),
+      fft2_pass<-1, kBFast, kBFast>(pl, "fft_up_ax1", n1, ld2_img(pl, pl->bufA, (int64_t)n1 * n2, n2, kDense, n1),
                                    st2_img(pl->bufA, (int64_t)n1 * n2, n2, kDense), make_tile2(n0, n2, n1, 0));
     } else {
       TileGeom g = make_geom(n0, n2, n1, 0);
@@ -691,7 +868,7 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
                &line_plan(pl, G0), +1.f);
     }
     if (fft2_supported(G1)) {  // F^H along axis 1 with the spectral pad
-      run_fft2<+1, kBFast, kBFast, 1>(pl, "fft_up_G1", G1,
+      fft2_pass<+1, kBFast, kBFast, 1>(pl, "fft_up_G1", G1,
                                       ld2_img(pl, pl->bufB, (int64_t)n1 * n2, n2, kSpectral, G1),
                                       st2_img(pl->bufC, (int64_t)G1 * n2, n2, kDense), make_tile2(G0, n2, G1, 0));
     } else {
@@ -701,7 +878,7 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
                nullptr, 0.f);
     }
     if (fft2_supported(G2)) {  // F^H along axis 2 with the spectral pad
-      run_fft2<+1, kJFast, kJFast, 1>(pl, "fft_up_G2", G2, ld2_img(pl, pl->bufC, n2, 1, kSpectral, G2),
+      fft2_pass<+1, kJFast, kJFast, 1>(pl, "fft_up_G2", G2, ld2_img(pl, pl->bufC, n2, 1, kSpectral, G2),
                                       st2_img(u, G2, 1, kDense), make_tile2((int64_t)G0 * G1, 1, G2, 1));
     } else {
       TileGeom g = make_geom((int64_t)G0 * G1, 1, G2, 0);
@@ -712,7 +889,7 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
     mid.n_inner = 1;
     mid.three_d = 0;
     if (fft2_supported(n1)) {
-      run_fft2<-1, kJFast, kJFast>(pl, "fft_up_ax1", n1, ld2_img(pl, x, n1, 1, kDense, n1),
+      fft2_pass<-1, kJFast, kJFast>(pl, "fft_up_ax1", n1, ld2_img(pl, x, n1, 1, kDense, n1),
                                    st2_img(pl->bufA, n1, 1, kDense), make_tile2(n0, 1, n1, 1));
     } else {
       TileGeom g = make_geom(n0, 1, n1, 0);
@@ -726,7 +903,7 @@ static void upsample(isg_plan* pl, const float2* x, float2* u) {
                +1.f);
     }
     if (fft2_supported(G1)) {
-      run_fft2<+1, kJFast, kJFast, 1>(pl, "fft_up_G1", G1, ld2_img(pl, pl->bufB, n1, 1, kSpectral, G1),
+      fft2_pass<+1, kJFast, kJFast, 1>(pl, "fft_up_G1", G1, ld2_img(pl, pl->bufB, n1, 1, kSpectral, G1),
                                       st2_img(u, G1, 1, kDense), make_tile2(G0, 1, G1, 1));
     } else {
       TileGeom g = make_geom(G0, 1, G1, 0);
@@ -758,7 +935,7 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out, const U
     mid.three_d = 1;
     // register FFTs along axes 2 and 1 where the length allows (as in upsample)
     if (fft2_supported(G2)) {  // F along axis 2, crop
-      run_fft2<-1, kJFast, kJFast, 2>(pl, "fft_uph_G2", G2, ld2_img(pl, U, G2, 1, kDense, G2),
+      fft2_pass<-1, kJFast, kJFast, 2>(pl, "fft_uph_G2", G2, ld2_img(pl, U, G2, 1, kDense, G2),
                                       st2_img(ub.C, n2, 1, kSpectral), make_tile2((int64_t)G0 * G1, 1, G2, 1));
     } else {
       TileGeom g = make_geom((int64_t)G0 * G1, 1, G2, 0);
@@ -766,7 +943,7 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out, const U
                st_strided<kFP32>(ub.C, n2, 1, n2, G2, kSpectral, g), g, line_plan(pl, G2), -1.f, nullptr, 0.f);
     }
     if (fft2_supported(G1)) {  // F along axis 1, crop
-      run_fft2<-1, kBFast, kBFast, 2>(pl, "fft_uph_G1", G1,
+      fft2_pass<-1, kBFast, kBFast, 2>(pl, "fft_uph_G1", G1,
                                       ld2_img(pl, ub.C, (int64_t)G1 * n2, n2, kDense, G1),
                                       st2_img(ub.B, (int64_t)n1 * n2, n2, kSpectral), make_tile2(G0, n2, G1, 0));
     } else {
@@ -782,7 +959,7 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out, const U
                &line_plan(pl, n0), +1.f);
     }
     if (fft2_supported(n1)) {  // F^H along axis 1, in place
-      run_fft2<+1, kBFast, kBFast>(pl, "fft_uph_ax1", n1, ld2_img(pl, ub.A, (int64_t)n1 * n2, n2, kDense, n1),
+      fft2_pass<+1, kBFast, kBFast>(pl, "fft_uph_ax1", n1, ld2_img(pl, ub.A, (int64_t)n1 * n2, n2, kDense, n1),
                                    st2_img(ub.A, (int64_t)n1 * n2, n2, kDense), make_tile2(n0, n2, n1, 0));
     } else {
       TileGeom g = make_geom(n0, n2, n1, 0);
@@ -791,7 +968,7 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out, const U
                nullptr, 0.f);
     }
     if (fft2_supported(n2)) {  // F^H along axis 2
-      run_fft2<+1, kJFast, kJFast>(pl, "fft_uph_ax2", n2, ld2_img(pl, ub.A, n2, 1, kDense, n2),
+      fft2_pass<+1, kJFast, kJFast>(pl, "fft_uph_ax2", n2, ld2_img(pl, ub.A, n2, 1, kDense, n2),
                                    st2_img(out, n2, 1, kDense), make_tile2((int64_t)n0 * n1, 1, n2, 1));
     } else {
       TileGeom g = make_geom((int64_t)n0 * n1, 1, n2, 0);
@@ -802,7 +979,7 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out, const U
     mid.n_inner = 1;
     mid.three_d = 0;
     if (fft2_supported(G1)) {
-      run_fft2<-1, kJFast, kJFast, 2>(pl, "fft_uph_G1", G1, ld2_img(pl, U, G1, 1, kDense, G1),
+      fft2_pass<-1, kJFast, kJFast, 2>(pl, "fft_uph_G1", G1, ld2_img(pl, U, G1, 1, kDense, G1),
                                       st2_img(ub.B, n1, 1, kSpectral), make_tile2(G0, 1, G1, 1));
     } else {
       TileGeom g = make_geom(G0, 1, G1, 0);
@@ -816,7 +993,7 @@ static void upsample_adjoint(isg_plan* pl, const float2* U, float2* out, const U
                +1.f);
     }
     if (fft2_supported(n1)) {
-      run_fft2<+1, kJFast, kJFast>(pl, "fft_uph_ax1", n1, ld2_img(pl, ub.A, n1, 1, kDense, n1),
+      fft2_pass<+1, kJFast, kJFast>(pl, "fft_uph_ax1", n1, ld2_img(pl, ub.A, n1, 1, kDense, n1),
                                    st2_img(out, n1, 1, kDense), make_tile2(n0, 1, n1, 1));
     } else {
       TileGeom g = make_geom(n0, 1, n1, 0);
@@ -1023,22 +1200,22 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
   const float scale = image_end_scale(pl);
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
     // S_c m / c(x/G) |N|^{-1/2}, centred pad, F along axis 2
-    run_fft2<-1, kJFast, kBFast, 1>(pl, "fft_coil_fwd_last", G2, ld2_expand(pl, m, Sm, n2, n1, G2),
+    fft2_pass<-1, kJFast, kBFast, 1>(pl, "fft_coil_fwd_last", G2, ld2_expand(pl, m, Sm, n2, n1, G2),
                                  st2<kFP32>(pl->k1buf, (int64_t)G2 * C, C, kDense),
                                  make_tile2((int64_t)n0 * n1, C, G2, C));
     // centred pad, F along axis 1 (into the row-blocked k2buf)
-    run_fft2<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax1", G1,
+    fft2_pass<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax1", G1,
                                  ld2<kFP32>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
                                  st2_axis1<kFP32>(pl->k2buf, pl->blk_k2, kDense, 1.f),
                                  xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
     // centred pad, F along axis 0
-    run_fft2<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2_rows<kFP32>(pl, pl->k2buf, pl->blk_k2, kCentred, G0),
+    fft2_pass<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2_rows<kFP32>(pl, pl->k2buf, pl->blk_k2, kCentred, G0),
                                  st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), 1.f),
                                  make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
-    run_fft2<-1, kJFast, kBFast, 1>(pl, "fft_coil_fwd_last", G1, ld2_expand(pl, m, Sm, n1, 0, G1),
+    fft2_pass<-1, kJFast, kBFast, 1>(pl, "fft_coil_fwd_last", G1, ld2_expand(pl, m, Sm, n1, 0, G1),
                                  st2<kFP32>(pl->k1buf, (int64_t)G1 * C, C, kDense), make_tile2(n0, C, G1, C));
-    run_fft2<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2<kFP32>(pl, pl->k1buf, 0, (int64_t)G1 * C, kCentred, G0),
+    fft2_pass<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2<kFP32>(pl, pl->k1buf, 0, (int64_t)G1 * C, kCentred, G0),
                                  st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), 1.f),
                                  make_tile2(1, (int64_t)G1 * C, G0, 0));
   } else if (pl->ndim == 3) {
@@ -1111,25 +1288,25 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
   const float scale = image_end_scale(pl);
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
     if (tr && tiled_adjoint(pl))  // spread output tile-major (touched tiles only)
-      run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0, ld2_tiles<S>(pl, grid, tr, G0),
+      fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0, ld2_tiles<S>(pl, grid, tr, G0),
                                    st2_rows<kFP32>(pl->k2buf, pl->blk_k2, kCentred, 1.f),
                                    make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
     else
-      run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0,
+      fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0,
                                       ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
                                    st2_rows<kFP32>(pl->k2buf, pl->blk_k2, kCentred, 1.f),
                                    make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
-    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax1", G1,
+    fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax1", G1,
                                  ld2_axis1<kFP32>(pl, pl->k2buf, pl->blk_k2, kDense, G1),
                                  st2<kFP32>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, 1.f),
                                  xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
-    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_last", G2, ld2<kFP32>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
+    fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_last", G2, ld2<kFP32>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
                                  st2_reduce(pl, w, Sm, n2, n1, G2, undo), make_tile2((int64_t)n0 * n1, C, G2, C));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
-    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0, ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
+    fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0, ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
                                  st2<kFP32>(pl->k1buf, 0, (int64_t)G1 * C, kCentred, 1.f),
                                  make_tile2(1, (int64_t)G1 * C, G0, 0));
-    run_fft2<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_last", G1, ld2<kFP32>(pl, pl->k1buf, (int64_t)G1 * C, C, kDense, G1),
+    fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_last", G1, ld2<kFP32>(pl, pl->k1buf, (int64_t)G1 * C, C, kDense, G1),
                                  st2_reduce(pl, w, Sm, n1, 0, G1, undo), make_tile2(n0, C, G1, C));
   } else if (pl->ndim == 3) {
     {  // F^H along axis 0, centred crop
@@ -3040,6 +3217,10 @@ isg_status isg_plan_set_option(isg_plan* pl, isg_option option, int64_t value) {
       if (value != 0 && value != 1) return fail(ISG_ERR_INVALID_ARG, "graph option must be 0 or 1");
       pl->opt_graph = (int)value;
       break;
+    case ISG_OPT_FFT_ADDR:
+      if (value != 0 && value != 1) return fail(ISG_ERR_INVALID_ARG, "FFT addressing option must be 0 or 1");
+      pl->opt_fft_addr = (int)value;
+      break;
     case ISG_OPT_KBLOCK:
       if (value != 0 && (value < 1 || value > 6)) return fail(ISG_ERR_INVALID_ARG, "k-space block must be 0 or 1..6");
       {
@@ -3076,6 +3257,7 @@ isg_status isg_plan_get_option(const isg_plan* pl, isg_option option, int64_t* v
     case ISG_OPT_SPREAD_CHUNK: *value = pl->opt_spread_chunk; break;
     case ISG_OPT_PHASE_BATCH: *value = pl->opt_phase_batch; break;
     case ISG_OPT_GRAPH: *value = pl->opt_graph; break;
+    case ISG_OPT_FFT_ADDR: *value = pl->opt_fft_addr; break;
     case ISG_OPT_KTILE_T1: *value = pl->opt_ktile_t1; break;
     case ISG_OPT_KBLOCK: *value = pl->opt_blk_tlog >= 30 ? 0 : pl->opt_blk_tlog; break;
     default: return fail(ISG_ERR_INVALID_ARG, "unknown option");

@@ -7,8 +7,9 @@ floating-point summation order:
   does, so results are compared bit for bit;
 * graph replays re-run the captured kernels, so they are compared bit for
   bit with the eager call, replay after replay, with eager work between;
-* the row-blocked layout of the internal k-space arrays changes addresses
-  only, so results are compared bit for bit;
+* the row-blocked layout of the internal k-space arrays and the addressing
+  form of the FFT passes change addresses only, so results are compared bit
+  for bit;
 * a different spread chunk or k-space tile extent changes only the order in
   which contributions are summed: 1e-6 relative (a few FP32 roundings), and
   the result is still held to the oracle's 1e-5.
@@ -196,3 +197,43 @@ def test_kspace_blocking_is_bit_exact(setup):
         else:
             for a, r in zip(res, ref):
                 assert torch.equal(a, r)
+
+
+@pytest.mark.parametrize("shape,storage,kblocks", [
+    ((16, 32, 48), "fp32", (0, 2)),   # every length has a buffer-addressed form (G = 32, 64, 96)
+    ((32, 48, 64), "fp16", (2, 3)),   # half-precision grids; blocks of 8 rows fail 8 | 12 on axis 1
+    ((20, 24, 16), "fp32", (2,)),     # G = 40, 48 have none, G = 32 has: mixed passes
+    ((48, 40), "bf16", (0,)),         # 2D
+])
+def test_fft_addressing_is_bit_exact(setup, shape, storage, kblocks):
+    """the buffer-addressed FFT passes (a scalar base per tile and element
+    index, one 32-bit lane offset, masking by the out-of-range rule) against
+    per-lane 64-bit addressing: the same arithmetic, so the same bits"""
+    import torch
+    isg = setup[0]
+    w = small_workload(shape=shape, ncoils=3, nphases=2, spokes=(30, 60), cfg=143)
+    inp = make_inputs(w)
+    x = to_dev(inp["x"])
+    M = sum(k.shape[0] for k in inp["k"])
+    y = to_dev((np.random.default_rng(7).standard_normal((M, w.ncoils, 2)) @ [1, 1j]).astype(np.complex64))
+    plan = isg.Plan(w.shape, ncoils=w.ncoils, nphases=w.nphases, storage=storage)
+    S = to_dev(inp["S"])
+    mots = [plan.motion(to_dev(d)) for d in inp["d"]]
+    trs = [plan.traj(to_dev(k)) for k in inp["k"]]
+    assert plan.get_option("fft_addr") == 1
+    for kb in kblocks:
+        if len(shape) == 3:
+            plan.set_option("kblock", kb)
+        res = {}
+        for fa in (1, 0):
+            say(f"{shape} {storage} kblock {kb} fft_addr {fa}")
+            plan.set_option("fft_addr", fa)
+            res[fa] = (plan.sense_forward(x, mots, S, trs), plan.sense_adjoint(y, mots, S, trs),
+                       plan.normal(x, 0.3, mots, S, trs), plan.warp(x, mots[0]), plan.warp_adjoint(x, mots[1]))
+            torch.cuda.synchronize()
+        for a, b in zip(res[1], res[0]):
+            assert torch.equal(a, b)
+    if storage == "fp32":
+        want = oracle.sense.normal(inp["x"], 0.3, inp["d"], inp["S"], inp["k"])
+        plan.set_option("fft_addr", 1)
+        assert rel(plan.normal(x, 0.3, mots, S, trs).cpu().numpy(), want) < 1e-5
