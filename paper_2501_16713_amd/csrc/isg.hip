@@ -23,6 +23,9 @@
 #include "passes.h"
 #include "solver.h"
 #include "recon.h"
+#include "binning.h"
+
+#include <hipcub/device/device_radix_sort.hpp>
 
 using namespace isg;
 
@@ -184,6 +187,7 @@ struct isg_plan {
   DevBuf tune_out;  // autotuner output image
   DevBuf sol;       // FISTA / power iteration / registration vectors, grown on demand
   DevBuf sol_part;  // their FP64 partial sums and histories
+  DevBuf bin;       // motion binning: keys, sorted keys, values, sort scratch, check flags
   hipStream_t own_stream = nullptr;  // CG capture stream when the caller's is the null stream
   int64_t bytes = 0;
   // bumped whenever device memory a captured graph may reference is freed or
@@ -1735,47 +1739,57 @@ static int spread_extent(int want, int G) {
   return std::min(want, cap);
 }
 
+// Every voxel joins the one warp-spread tile that holds its first tap along
+// every axis (the spread kernel recomputes the same tap base from d).  On the
+// device, on the plan's stream: the key of every voxel and a check of the
+// field, a stable radix sort of (tile, voxel) pairs (voxels stay in index
+// order within a tile, so the spread sums in the same order on every call),
+// and the tile offsets from the sorted keys.  Only the 4-byte check result
+// comes back to the host.
 static isg_status prepare_motion(isg_plan* pl, const float* d_dev, isg_motion* mo) {
   const int nd = pl->ndim;
   const int64_t N = pl->N;
-  std::vector<float> d((size_t)nd * N);
-  HIP_OK(hipMemcpy(d.data(), d_dev, sizeof(float) * d.size(), hipMemcpyDeviceToHost));
-  for (float v : d) {
-    if (!std::isfinite(v)) return fail(ISG_ERR_NOT_FINITE, "displacement field holds NaN or Inf");
-    if (std::fabs(v) > 1.0e6f) return fail(ISG_ERR_INVALID_ARG, "displacement magnitude exceeds 1e6 voxels");
-  }
-  // every voxel joins the one tile that holds its first tap along every
-  // axis (the spread kernel recomputes the same tap base from d); counting
-  // sort by tile, voxels in index order within a tile
+  if (N >= ((int64_t)1 << 31)) return fail(ISG_ERR_UNSUPPORTED_SHAPE, "more than 2^31 voxels");
   const int ntiles = warp_ntiles(pl);
-  std::vector<int> cnt(ntiles + 1, 0), tof((size_t)N);
-  for (int64_t r = 0; r < N; ++r) {
-    int ri[3] = {0, 0, 0};
-    int64_t t = r;
-    for (int i = nd - 1; i >= 0; --i) {
-      ri[i] = (int)(t % pl->n[i]);
-      t /= pl->n[i];
-    }
-    int tile = 0;
-    for (int i = 0; i < nd; ++i) {
-      const float y = 2.0f * d[(size_t)i * N + r];
-      const int b = iwrap(2 * (int64_t)ri[i] + (int64_t)std::floor(y) - 1, pl->G[i]);
-      tile = tile * pl->wtile.nt[i] + (b >> pl->wtile.lg[i]);
-    }
-    tof[(size_t)r] = tile;
-    cnt[tile + 1]++;
-  }
-  for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
-  std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-  std::vector<int> vox((size_t)N);
-  for (int64_t r = 0; r < N; ++r) vox[(size_t)pos[tof[(size_t)r]]++] = (int)r;
-  mo->d = (float*)dmalloc(pl, sizeof(float) * d.size());
-  mo->tile_off = (int*)dmalloc(pl, sizeof(int) * cnt.size());
-  mo->vox = (int*)dmalloc(pl, sizeof(int) * std::max<size_t>(1, vox.size()));
-  mo->nentries = (int64_t)vox.size();
-  HIP_OK(hipMemcpy(mo->d, d.data(), sizeof(float) * d.size(), hipMemcpyHostToDevice));
-  HIP_OK(hipMemcpy(mo->tile_off, cnt.data(), sizeof(int) * cnt.size(), hipMemcpyHostToDevice));
-  if (!vox.empty()) HIP_OK(hipMemcpy(mo->vox, vox.data(), sizeof(int) * vox.size(), hipMemcpyHostToDevice));
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < ntiles) ++bits;
+  size_t sort_bytes = 0;
+  HIP_OK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (int*)nullptr, (int*)nullptr, (int*)nullptr,
+                                            (int*)nullptr, (int)N, 0, bits, pl->stream));
+  const size_t ints = (size_t)std::max<int64_t>(N, 1);
+  const size_t off_keys = 0, off_skeys = ints, off_vals = 2 * ints, off_bad = 3 * ints;
+  const size_t tmp_at = ((off_bad + 1) * sizeof(int) + 255) & ~(size_t)255;
+  grow(pl, pl->bin, tmp_at + sort_bytes + 256);
+  int* base = (int*)pl->bin.p;
+  int *keys = base + off_keys, *skeys = base + off_skeys, *vals = base + off_vals, *bad = base + off_bad;
+  void* tmp = (char*)pl->bin.p + tmp_at;
+  mo->d = (float*)dmalloc(pl, sizeof(float) * (size_t)nd * N);
+  mo->tile_off = (int*)dmalloc(pl, sizeof(int) * ((size_t)ntiles + 1));
+  mo->vox = (int*)dmalloc(pl, sizeof(int) * ints);
+  mo->nentries = N;
+  HIP_OK(hipMemcpyAsync(mo->d, d_dev, sizeof(float) * (size_t)nd * N, hipMemcpyDeviceToDevice, pl->stream));
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, pl->stream, bad, (int64_t)1, 0);
+  const unsigned kb = (unsigned)std::min<int64_t>(blocks_for(N, 256), 8192);
+  const int* nt = pl->wtile.nt;
+  const int* lg = pl->wtile.lg;
+  if (nd == 3)
+    hipLaunchKernelGGL(motion_key_kernel<3>, dim3(kb), dim3(256), 0, pl->stream, mo->d, N, pl->n[0], pl->n[1],
+                       pl->n[2], pl->G[0], pl->G[1], pl->G[2], nt[0], nt[1], nt[2], lg[0], lg[1], lg[2], keys, vals,
+                       bad);
+  else
+    hipLaunchKernelGGL(motion_key_kernel<2>, dim3(kb), dim3(256), 0, pl->stream, mo->d, N, pl->n[0], pl->n[1], 1,
+                       pl->G[0], pl->G[1], 1, nt[0], nt[1], 1, lg[0], lg[1], 0, keys, vals, bad);
+  LAUNCH_OK();
+  HIP_OK(hipcub::DeviceRadixSort::SortPairs(tmp, sort_bytes, keys, skeys, vals, mo->vox, (int)N, 0, bits,
+                                            pl->stream));
+  hipLaunchKernelGGL(tile_offsets_kernel, dim3((unsigned)std::min<int64_t>(blocks_for(N + 1, 256), 8192)), dim3(256),
+                     0, pl->stream, skeys, N, ntiles, mo->tile_off);
+  LAUNCH_OK();
+  int flags = 0;
+  HIP_OK(hipMemcpyAsync(&flags, bad, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
+  HIP_OK(hipStreamSynchronize(pl->stream));
+  if (flags & kFieldNotFinite) return fail(ISG_ERR_NOT_FINITE, "displacement field holds NaN or Inf");
+  if (flags & kFieldTooLarge) return fail(ISG_ERR_INVALID_ARG, "displacement magnitude exceeds 1e6 voxels");
   return ISG_OK;
 }
 
