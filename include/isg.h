@@ -229,8 +229,12 @@ isg_status isg_plan_tune(isg_plan* plan, int nphases, const void* x, const isg_m
                          int64_t len);
 
 /* Prepare a displacement field d (device float32 [ndim][n...], voxels) for
- * T_d / T_d^H (Eq. 5): tap bases and tile bins for the spreading adjoint.
- * NOT_FINITE if d holds NaN/Inf. */
+ * T_d / T_d^H (Eq. 5): a copy of d and the voxel lists per tile of the
+ * spreading adjoint, binned on the device on the plan's stream (a stable sort
+ * by tile, so the adjoint sums in the same order on every call).  Returns
+ * after the work completes (the caller may free d); only the 4-byte result of
+ * the field check is copied to the host.  NOT_FINITE if d holds NaN/Inf,
+ * INVALID_ARG if some |d| exceeds 1e6 voxels. */
 isg_status isg_motion_create(isg_plan* plan, const float* d, isg_motion** motion);
 isg_status isg_motion_destroy(isg_motion* motion);
 
