@@ -15,6 +15,8 @@
 // the Taylor series of sin and cos in double precision.
 #pragma once
 
+#include <type_traits>
+
 #include "passes.h"
 
 namespace isg {
@@ -178,6 +180,13 @@ __device__ __forceinline__ int slot(int k1, int n2) {
 // n1 in [L1/4, 3L1/4) (step-2 outputs k2 in [L2/4, 3L2/4)) for every thread:
 // those loads are not issued, and the outputs that are never stored are not
 // computed (dead code).
+// Loaders and stores of the axis-0 passes know which tiles no sample reaches
+// (T::kTileSkip, T::tile_active(b0, g)); other types take every tile.
+template <class T, class = void>
+struct tile_skip : std::false_type {};
+template <class T>
+struct tile_skip<T, std::void_t<decltype(T::kTileSkip)>> : std::bool_constant<T::kTileSkip> {};
+
 template <int L1, int L2, int S, int MAP1, int MAP2, class Ld, class St, int GAP = 0>
 __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
   constexpr int L = L1 * L2;
@@ -203,6 +212,27 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
   const int64_t b0 = (tile - ta * g.tiles_b) * g.nb;
   if (a0 >= g.A) return;
   const int nl = g.na * g.nb;
+  if constexpr (tile_skip<Ld>::value || tile_skip<St>::value) {
+    // a tile of lines whose grid columns no sample reaches: the forward pass
+    // stores nothing there; the adjoint pass reads only zeros and stores zeros
+    bool active = true;
+    if constexpr (tile_skip<Ld>::value) active = ld.tile_active(b0, g);
+    if constexpr (tile_skip<St>::value) active = active && st.tile_active(b0, g);
+    if (!active) {
+      if constexpr (!tile_skip<St>::value && !St::kEpilogue) {
+        if (st.zfill && tid < nl * L1) {  // zfill false: the next pass reads these columns as zero
+          int bz, kz, az;
+          decode<MAP2>(tid, g.nb, L1, bz, kz, az);
+          auto line = st.setup(a0, b0, az, bz, kz, a0 + az < g.A && b0 + bz < g.B);
+#pragma unroll
+          for (int k2 = 0; k2 < L2; ++k2)
+            if (!(kGapOut && k2 >= L2 / 4 && k2 < 3 * L2 / 4))
+              st.template put<L1, L2>(line, k2, make_float2(0.f, 0.f));
+        }
+      }
+      return;
+    }
+  }
   uint32_t* table = reinterpret_cast<uint32_t*>(lines + (size_t)nl * g.LS);
   if constexpr (Ld::kPrologue) ld.prologue(table, a0, b0, g);
   for (int i = tid; i < L; i += nthreads) tw[i] = ld.tw[i];
@@ -398,6 +428,7 @@ struct Ld2Rows {
 template <int S>
 struct St2Strided {
   static constexpr bool kEpilogue = false;
+  bool zfill = true;  // a skipped (untouched) tile of the adjoint axis-0 pass stores zeros
   typename Elem<S>::T* p;
   int64_t sa, sj;
   int tlog;     // as in Ld2Strided
@@ -425,6 +456,7 @@ struct St2Strided {
 template <int S>
 struct St2Rows {
   static constexpr bool kEpilogue = false;
+  bool zfill = true;  // a skipped (untouched) tile of the adjoint axis-0 pass stores zeros
   typename Elem<S>::T* p;
   Blk blk;
   int map;
@@ -486,12 +518,22 @@ struct TileMask {
     const uint32_t q = (uint32_t)b / (uint32_t)C;  // i1 G2 + i2 in 3D, i1 in 2D (< 2^31)
     return fmask[q];
   }
+  // some sample reaches a grid column of the tile's columns b0 .. b0+nb-1
+  __device__ __forceinline__ bool tile_active(int64_t b0, const Tile2& g) const {
+    if (!fmask) return true;
+    const int64_t b1 = (b0 + g.nb < g.B ? b0 + g.nb : g.B) - 1;
+    uint64_t any = 0;
+    for (uint32_t q = (uint32_t)b0 / (uint32_t)C; q <= (uint32_t)b1 / (uint32_t)C; ++q) any |= fmask[q];
+    return any != 0ull;
+  }
 };
 
 // axis-0 load that reads untouched tiles as zero (dense map)
 template <int S>
 struct Ld2Masked {
   static constexpr bool kPrologue = false;
+  static constexpr bool kTileSkip = true;
+  __device__ bool tile_active(int64_t b0, const Tile2& g) const { return tm.tile_active(b0, g); }
   const typename Elem<S>::T* p;
   Blk blk;  // the grid's row-blocked layout
   TileMask tm;
@@ -518,6 +560,8 @@ struct Ld2Masked {
 template <int S>
 struct St2Masked {
   static constexpr bool kEpilogue = false;
+  static constexpr bool kTileSkip = true;
+  __device__ bool tile_active(int64_t b0, const Tile2& g) const { return tm.tile_active(b0, g); }
   typename Elem<S>::T* p;
   Blk blk;  // the grid's row-blocked layout
   TileMask tm;
@@ -547,6 +591,7 @@ struct St2Masked {
 template <int S>
 struct Ld2Tiles {
   static constexpr bool kPrologue = false;
+  static constexpr bool kTileSkip = true;
   const typename Elem<S>::T* p;
   const uint64_t* colmask;  // per tile column: touched tiles (their slots)
   const uint64_t* fmask;    // per grid column (i1, i2): touched runs along axis 0
@@ -556,6 +601,10 @@ struct Ld2Tiles {
   int64_t rowC;   // elements per tile row of axis 0 (TS1 TS2 C)
   FastDiv cdiv, g2div;
   const float2* tw;
+  __device__ bool tile_active(int64_t b0, const Tile2& g) const {
+    const TileMask tm{fmask, C, G2, 1, ts0_log2};
+    return tm.tile_active(b0, g);
+  }
   struct Line {
     const typename Elem<S>::T* base;
     uint64_t mask;  // touched tiles of the tile column
@@ -625,6 +674,7 @@ struct Ld2StridedF {
 template <int S>
 struct St2StridedF {
   static constexpr bool kEpilogue = false;
+  bool zfill = true;  // a skipped (untouched) tile of the adjoint axis-0 pass stores zeros
   typename Elem<S>::T* p;
   int64_t sa, sj;
   int tlog;
@@ -675,6 +725,7 @@ struct Ld2RowsF {
 template <int S>
 struct St2RowsF {
   static constexpr bool kEpilogue = false;
+  bool zfill = true;  // a skipped (untouched) tile of the adjoint axis-0 pass stores zeros
   typename Elem<S>::T* p;
   Blk blk;
   int map;
@@ -701,6 +752,8 @@ struct St2RowsF {
 template <int S>
 struct St2MaskedF {
   static constexpr bool kEpilogue = false;
+  static constexpr bool kTileSkip = true;
+  __device__ bool tile_active(int64_t b0, const Tile2& g) const { return tm.tile_active(b0, g); }
   typename Elem<S>::T* p;
   Blk blk;
   TileMask tm;
@@ -737,6 +790,7 @@ struct St2MaskedF {
 template <int S>
 struct Ld2TilesF {
   static constexpr bool kPrologue = true;
+  static constexpr bool kTileSkip = true;
   const typename Elem<S>::T* p;
   const uint64_t* colmask;
   const uint64_t* fmask;
@@ -747,6 +801,10 @@ struct Ld2TilesF {
   int64_t Q;   // grid columns (G1 G2)
   int64_t volC, rowC;
   const float2* tw;
+  __device__ bool tile_active(int64_t b0, const Tile2& g) const {
+    const TileMask tm{fmask, C, G2, 1, 3};
+    return tm.tile_active(b0, g);
+  }
   struct Line {
     const typename Elem<S>::T* base;
     const uint32_t* row;  // the lane's table row
@@ -793,6 +851,45 @@ struct Ld2TilesF {
   }
 };
 
+// The adjoint axis-1 pass of the coil-expanded arrays along a trajectory's
+// touched grid columns: line (i0, b = i2 C + c) runs over i1, and grid column
+// (i1, i2) holds data only if some sample reaches it (its run mask is not
+// zero).  cm[i2][w] holds bit i1 of those columns (W = ceil(G1 / 64) words,
+// G1 <= 512).  The lane shifts its column's bits right by its own part of the
+// position (n2), so an element index tests one bit known at compile time; an
+// untouched column reads as zero, so the adjoint axis-0 pass need not write
+// the tiles no sample reaches.
+constexpr int kColWords = 8;
+template <int S>
+struct Ld2StridedM : Ld2StridedF<S> {
+  const uint64_t* cm;
+  int cmC, cmW;
+  struct Line {
+    typename Ld2StridedF<S>::Line f;
+    uint64_t m[kColWords];
+  };
+  __device__ Line setup(int64_t a0, int64_t b0, int al, int bl, int n2, bool valid, const uint32_t* t) const {
+    Line ln;
+    ln.f = Ld2StridedF<S>::setup(a0, b0, al, bl, n2, valid, t);
+    const uint64_t* c = cm + (int64_t)((uint32_t)(b0 + bl) / (uint32_t)cmC) * cmW;
+#pragma unroll
+    for (int w = 0; w < kColWords; ++w) {
+      const uint64_t lo = w < cmW && valid ? c[w] : 0ull;
+      const uint64_t hi = w + 1 < cmW && valid ? c[w + 1] : 0ull;
+      ln.m[w] = n2 == 0 ? lo : (lo >> n2) | (hi << (64 - n2));  // n2 < 64
+    }
+    return ln;
+  }
+  template <int L1, int L2>
+  __device__ float2 get(const Line& ln, int n1) const {
+    const int bit = L2 * n1;  // position L2 n1 + n2 after the lane's shift
+    const bool on = (ln.m[bit >> 6] >> (bit & 63)) & 1ull;
+    typename Ld2StridedF<S>::Line f = ln.f;
+    f.off = on ? f.off : kOOB;
+    return Ld2StridedF<S>::template get<L1, L2>(f, n1);
+  }
+};
+
 template <int S>
 struct Ld2ImageF : Ld2StridedF<S> {};
 template <int S>
@@ -808,6 +905,8 @@ template <int S>
 inline bool half_gap(const St2ImageF<S>& x, int L) { return half_gap(static_cast<const St2StridedF<S>&>(x), L); }
 template <int S>
 inline bool half_gap(const Ld2RowsF<S>& x, int) { return x.map == kCentred || x.map == kSpectral; }
+template <int S>
+inline bool half_gap(const Ld2StridedM<S>& x, int L) { return half_gap(static_cast<const Ld2StridedF<S>&>(x), L); }
 template <int S>
 inline bool half_gap(const St2RowsF<S>& x, int) { return x.map == kCentred || x.map == kSpectral; }
 

@@ -272,6 +272,8 @@ struct isg_traj {
   int64_t M = 0;
   uint64_t* colmask = nullptr;  // touched-tile masks (null: all tiles written)
   uint64_t* fmask = nullptr;    // touched-run masks per grid column (i1, i2) (null with colmask)
+  uint64_t* cact = nullptr;     // 3D: bit i1 of word [i2][i1 / 64] set where fmask[(i1, i2)] != 0 (G1 <= 512)
+  int cact_w = 0;               // words per i2
   int64_t fine_cells = 0;       // grid cells in the touched runs
   int* colbase = nullptr;       // tile-major spread output: first slot of each tile column
   std::vector<uint64_t> colmask_h;
@@ -636,6 +638,11 @@ static bool fast_ok(const Ld2Tiles<S>& x, int L, const Tile2& g) {
   return x.ts0_log2 == 3 && g.na == 1 && span < kLaneSpan && L / 8 <= 64 && g.B + g.nb < kLaneSpan;
 }
 
+template <int S>
+static bool fast_ok(const Ld2StridedM<S>& x, int L, const Tile2& g) {
+  return strided_fast_ok(x, L, g, true, sizeof(typename Elem<S>::T));
+}
+
 template <class T>
 static const T& to_fast(const T& x, int, const Tile2&) { return x; }
 template <int S>
@@ -648,6 +655,7 @@ template <int S>
 static St2StridedF<S> to_fast(const St2Strided<S>& x, int, const Tile2&) {
   St2StridedF<S> f;
   f.p = x.p; f.sa = x.sa; f.sj = x.sj; f.tlog = x.tlog; f.bs = x.bs; f.map = x.map; f.scale = x.scale;
+  f.zfill = x.zfill;
   return f;
 }
 template <int S>
@@ -671,7 +679,7 @@ static Ld2RowsF<S> to_fast(const Ld2Rows<S>& x, int, const Tile2&) {
 template <int S>
 static St2RowsF<S> to_fast(const St2Rows<S>& x, int, const Tile2&) {
   St2RowsF<S> f;
-  f.p = x.p; f.blk = x.blk; f.map = x.map; f.scale = x.scale;
+  f.p = x.p; f.blk = x.blk; f.map = x.map; f.scale = x.scale; f.zfill = x.zfill;
   return f;
 }
 template <int S>
@@ -716,6 +724,15 @@ static void fft2_pass(isg_plan* pl, const char* tag, int L, const Ld& ld, const 
     run_fft2_fast<SG, M1, M2, GAP>(pl, tag, L, to_fast(ld, L, g), to_fast(st, L, g), g);
   else
     run_fft2<SG, M1, M2, GAP>(pl, tag, L, ld, st, g);
+}
+
+// a pass that must take the buffer-addressed form (its loader or store has
+// no general one)
+template <int SG, int M1, int M2, int GAP = 0, class Ld, class St>
+static void fft2_pass_fast(isg_plan* pl, const char* tag, int L, const Ld& ld, const St& st, const Tile2& g) {
+  if (!(fft2_fast_length(L) && fast_ok(ld, L, g) && fast_ok(st, L, g)))
+    throw HipError{hipErrorInvalidConfiguration, "fft2: a masked pass needs the buffer-addressed form"};
+  run_fft2_fast<SG, M1, M2, GAP>(pl, tag, L, to_fast(ld, L, g), to_fast(st, L, g), g);
 }
 
 template <int S>
@@ -771,6 +788,31 @@ static St2Strided<S> st2_axis1(void* p, const Blk& blk, int map, float scale) {
   s.tlog = blk.tlog;
   s.bs = blk.bs;
   return s;
+}
+
+// The adjoint axis-1 pass restricted to a trajectory's touched grid columns
+// (see Ld2StridedM): only where its buffer-addressed form runs, so that the
+// adjoint axis-0 pass may leave untouched columns unwritten.
+static bool ax1_masked(const isg_plan* pl, const isg_traj* tr) {
+  if (!tr || !tr->cact || !pl->opt_fft_addr || pl->ndim != 3 || !fft2_fast_length(pl->G[1])) return false;
+  const Tile2 g = make_tile2(pl->n[0], (int64_t)pl->G[2] * pl->C, pl->G[1], 0);
+  Ld2Strided<kFP32> l;
+  l.sa = pl->blk_k2.rs;
+  l.sj = pl->blk_k2.g2c;
+  l.tlog = pl->blk_k2.tlog;
+  l.bs = pl->blk_k2.bs;
+  l.map = kDense;
+  return strided_fast_ok(l, pl->G[1], g, true, sizeof(float2));
+}
+
+static Ld2StridedM<kFP32> ld2_axis1_masked(const isg_plan* pl, const void* p, const Blk& blk, const isg_traj* tr,
+                                           int L) {
+  Ld2StridedM<kFP32> l;
+  static_cast<Ld2StridedF<kFP32>&>(l) = to_fast(ld2_axis1<kFP32>(pl, p, blk, kDense, L), L, Tile2{});
+  l.cm = tr->cact;
+  l.cmC = pl->C;
+  l.cmW = tr->cact_w;
+  return l;
 }
 
 // lines along axis 0 of a row-blocked array: b = column, j = i0
@@ -1207,11 +1249,14 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
     fft2_pass<-1, kJFast, kBFast, 1>(pl, "fft_coil_fwd_last", G2, ld2_expand(pl, m, Sm, n2, n1, G2),
                                  st2<kFP32>(pl->k1buf, (int64_t)G2 * C, C, kDense),
                                  make_tile2((int64_t)n0 * n1, C, G2, C));
-    // centred pad, F along axis 1 (into the row-blocked k2buf)
+    // centred pad, F along axis 1 (into the row-blocked k2buf).  Storing the
+    // touched grid columns only (a column-masked store like Ld2StridedM)
+    // measured slower: its column bits are loaded after the exchange, on the
+    // store path.
     fft2_pass<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax1", G1,
-                                 ld2<kFP32>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
-                                 st2_axis1<kFP32>(pl->k2buf, pl->blk_k2, kDense, 1.f),
-                                 xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
+                                     ld2<kFP32>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
+                                     st2_axis1<kFP32>(pl->k2buf, pl->blk_k2, kDense, 1.f),
+                                     xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
     // centred pad, F along axis 0
     fft2_pass<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2_rows<kFP32>(pl, pl->k2buf, pl->blk_k2, kCentred, G0),
                                  st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), 1.f),
@@ -1291,19 +1336,28 @@ static void coil_adjoint_t(isg_plan* pl, const void* grid, const float2* Sm, flo
   const int C = pl->C;
   const float scale = image_end_scale(pl);
   if (pl->ndim == 3 && fft2_supported(G0) && fft2_supported(G1) && fft2_supported(G2)) {
+    // with the masked axis-1 pass, tiles no sample reaches are not written
+    // (the axis-1 pass reads their columns as zero); else they store zeros
+    const bool masked = ax1_masked(pl, tr);
+    St2Rows<kFP32> k2st = st2_rows<kFP32>(pl->k2buf, pl->blk_k2, kCentred, 1.f);
+    k2st.zfill = !masked;
     if (tr && tiled_adjoint(pl))  // spread output tile-major (touched tiles only)
-      fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0, ld2_tiles<S>(pl, grid, tr, G0),
-                                   st2_rows<kFP32>(pl->k2buf, pl->blk_k2, kCentred, 1.f),
-                                   make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
+      fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0, ld2_tiles<S>(pl, grid, tr, G0), k2st,
+                                       make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
     else
       fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax0", G0,
-                                      ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0),
-                                   st2_rows<kFP32>(pl->k2buf, pl->blk_k2, kCentred, 1.f),
-                                   make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
-    fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax1", G1,
-                                 ld2_axis1<kFP32>(pl, pl->k2buf, pl->blk_k2, kDense, G1),
-                                 st2<kFP32>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, 1.f),
-                                 xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
+                                       ld2_masked<S>(pl, grid, pl->blk_grid, tile_mask(pl, tr), G0), k2st,
+                                       make_tile2(1, (int64_t)G1 * G2 * C, G0, 0));
+    if (masked)
+      fft2_pass_fast<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax1", G1,
+                                            ld2_axis1_masked(pl, pl->k2buf, pl->blk_k2, tr, G1),
+                                            st2<kFP32>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, 1.f),
+                                            xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
+    else
+      fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_ax1", G1,
+                                       ld2_axis1<kFP32>(pl, pl->k2buf, pl->blk_k2, kDense, G1),
+                                       st2<kFP32>(pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, 1.f),
+                                       xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, 0)));
     fft2_pass<+1, kBFast, kBFast, 2>(pl, "fft_coil_adj_last", G2, ld2<kFP32>(pl, pl->k1buf, (int64_t)G2 * C, C, kDense, G2),
                                  st2_reduce(pl, w, Sm, n2, n1, G2, undo), make_tile2((int64_t)n0 * n1, C, G2, C));
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
@@ -1953,8 +2007,10 @@ static void bin_traj(isg_plan* pl, isg_traj* tr) {
   HIP_OK(hipStreamSynchronize(pl->stream));
   pl->generation++;
   for (void** q : {(void**)&tr->order, (void**)&tr->gorder, (void**)&tr->colmask, (void**)&tr->fmask,
-                   (void**)&tr->colbase, (void**)&tr->taps_v, (void**)&tr->vis_off, (void**)&tr->vis})
+                   (void**)&tr->cact, (void**)&tr->colbase, (void**)&tr->taps_v, (void**)&tr->vis_off,
+                   (void**)&tr->vis})
     traj_free(pl, *q);
+  tr->cact_w = 0;
   tr->fine_cells = 0;
   tr->colmask_h.clear();
   tr->colbase_h.clear();
@@ -2031,6 +2087,16 @@ static void bin_traj(isg_plan* pl, isg_traj* tr) {
     tr->fine_cells = runs * (1 << lg);  // ragged last runs counted whole
     tr->fmask = (uint64_t*)dmalloc(pl, sizeof(uint64_t) * fm.size());
     HIP_OK(hipMemcpy(tr->fmask, fm.data(), sizeof(uint64_t) * fm.size(), hipMemcpyHostToDevice));
+    if (nd == 3 && G1 <= 64 * kColWords) {  // the touched grid columns, transposed for the axis-1 passes
+      const int W = (G1 + 63) / 64;
+      std::vector<uint64_t> ca((size_t)G2 * W, 0ull);
+      for (int i1 = 0; i1 < G1; ++i1)
+        for (int i2 = 0; i2 < G2; ++i2)
+          if (fm[(size_t)i1 * G2 + i2]) ca[(size_t)i2 * W + (i1 >> 6)] |= 1ull << (i1 & 63);
+      tr->cact = (uint64_t*)dmalloc(pl, sizeof(uint64_t) * ca.size());
+      tr->cact_w = W;
+      HIP_OK(hipMemcpy(tr->cact, ca.data(), sizeof(uint64_t) * ca.size(), hipMemcpyHostToDevice));
+    }
   }
   tr->order = (int*)dmalloc(pl, sizeof(int) * order.size());
   HIP_OK(hipMemcpy(tr->order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
@@ -3075,8 +3141,8 @@ isg_status isg_traj_destroy(isg_traj* tr) {
     pl->trajs.erase(tr);
   }
   for (void* p : {(void*)tr->taps, (void*)tr->order, (void*)tr->gorder, (void*)tr->units, (void*)tr->splits,
-                  (void*)tr->colmask, (void*)tr->fmask, (void*)tr->colbase, (void*)tr->taps_v, (void*)tr->vis_off,
-                  (void*)tr->vis, (void*)tr->k, (void*)tr->phase})
+                  (void*)tr->colmask, (void*)tr->fmask, (void*)tr->cact, (void*)tr->colbase, (void*)tr->taps_v,
+                  (void*)tr->vis_off, (void*)tr->vis, (void*)tr->k, (void*)tr->phase})
     (void)dfree(pl, p);
   delete tr;
   return ISG_OK;
