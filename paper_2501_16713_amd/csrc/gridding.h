@@ -494,6 +494,10 @@ __global__ __launch_bounds__(1024) void warp_spread_sum_kernel(const float2* __r
 struct KUnit {
   int tile, start, count, slot;
   int gslot;  // tile-major grids: the tile's slot among the touched tiles
+  // 8 x 4 x 8 register spread: the unit's visits are ordered by the rows
+  // their axis-0 taps reach, rows 0-3 only in [0, lo), rows 4-7 only in
+  // [lo, lohi), both halves in [lohi, count) (0, 0 when not ordered)
+  int lo, lohi;
 };
 // a tile whose samples were cut into several units: partial slots
 // first_slot .. first_slot + nslots - 1
@@ -950,12 +954,52 @@ __global__ __launch_bounds__(512) void kspread_kernel(KBatch<typename Elem<S>::T
 // The staging thread of a sample expands its tap weights over the tile:
 // W0[l0] (8 values), W1[l1] (4) and W2[l2] (8) hold the weight of the tap
 // that lands on row l of the tile along that axis, zero where none does.
-// Every lane then adds W0[l0] W1[l1] W2[l2] y_c to its 16 cells (lanes
-// outside the sample's footprint add zero): no cell is shared between lanes,
-// no LDS read-modify-write and no branch; the summation order per cell is
-// the sample order (deterministic).  Staging as in kspread_kernel; the
-// accumulators are stored from registers.
+// Every lane then adds W0[l0] W1[l1] W2[l2] y_c to its cells (lanes outside
+// the sample's footprint add zero): no cell is shared between lanes, no LDS
+// read-modify-write and no branch per sample.  The unit's visits come
+// ordered by the rows their four axis-0 taps reach (rows 0-3 only, rows 4-7
+// only, both halves; see KUnit), so a batch runs as three branch-free loops
+// of which the first two add into four rows only.  The summation order per
+// cell is the unit's visit order (deterministic).  Staging as in
+// kspread_kernel; the accumulators are stored from registers.
 constexpr int kRegW = 20;  // expanded weights per staged sample: W0[8], W1[4], W2[8]
+
+// samples s0 .. s1-1 of the staged batch into rows R0 .. R1-1 of the lane's
+// register column (the other rows carry no weight for these samples);
+// sample s + 1's parameters are read while sample s is applied
+template <int R0, int R1>
+__device__ __forceinline__ void kspread_reg_run(int s0, int s1, const float4 (*st_W)[kRegW / 4], const float* stw,
+                                                const float2* st_y, int C, int l1, int l2, int cr, int cr1,
+                                                float2 (&a0)[8], float2 (&a1)[8]) {
+  if (s0 >= s1) return;
+  float4 wa = st_W[s0][0], wb = st_W[s0][1];
+  float w1 = stw[s0 * kRegW + 8 + l1], w2 = stw[s0 * kRegW + 12 + l2];
+  float2 y0 = st_y[s0 * C + cr], y1 = st_y[s0 * C + cr1];
+  for (int s = s0; s < s1; ++s) {
+    const float4 cwa = wa, cwb = wb;
+    const float cw12 = w1 * w2;
+    const float2 cy0 = y0, cy1 = y1;
+    {
+      const int sn = min(s + 1, s1 - 1);
+      wa = st_W[sn][0];
+      wb = st_W[sn][1];
+      w1 = stw[sn * kRegW + 8 + l1];
+      w2 = stw[sn * kRegW + 12 + l2];
+      y0 = st_y[sn * C + cr];
+      y1 = st_y[sn * C + cr1];
+    }
+    const float2 v0 = make_float2(cw12 * cy0.x, cw12 * cy0.y);
+    const float2 v1 = make_float2(cw12 * cy1.x, cw12 * cy1.y);
+    const float W0[8] = {cwa.x, cwa.y, cwa.z, cwa.w, cwb.x, cwb.y, cwb.z, cwb.w};
+#pragma unroll
+    for (int j = R0; j < R1; ++j) {
+      a0[j].x = fmaf(W0[j], v0.x, a0[j].x);
+      a0[j].y = fmaf(W0[j], v0.y, a0[j].y);
+      a1[j].x = fmaf(W0[j], v1.x, a1[j].x);
+      a1[j].y = fmaf(W0[j], v1.y, a1[j].y);
+    }
+  }
+}
 
 template <int S>
 __global__ __launch_bounds__(512) void kspread_reg_kernel(KBatch<typename Elem<S>::T> bt, int C, Dims dm, KTile kt,
@@ -1029,34 +1073,11 @@ __global__ __launch_bounds__(512) void kspread_reg_kernel(KBatch<typename Elem<S
     }
     __syncthreads();
     fetch(b0 + kSpreadBatch < un.count ? b0 + kSpreadBatch : b0);
-    // sample s + 1's parameters are read while sample s is applied
-    float4 wa = st_W[0][0], wb = st_W[0][1];
-    float w1 = stw[8 + l1], w2 = stw[12 + l2];
-    float2 y0 = st_y[cr], y1 = st_y[cr1];
-    for (int s = 0; s < nb; ++s) {
-      const float4 cwa = wa, cwb = wb;
-      const float cw12 = w1 * w2;
-      const float2 cy0 = y0, cy1 = y1;
-      {
-        const int sn = min(s + 1, nb - 1);
-        wa = st_W[sn][0];
-        wb = st_W[sn][1];
-        w1 = stw[sn * kRegW + 8 + l1];
-        w2 = stw[sn * kRegW + 12 + l2];
-        y0 = st_y[sn * C + cr];
-        y1 = st_y[sn * C + cr1];
-      }
-      const float2 v0 = make_float2(cw12 * cy0.x, cw12 * cy0.y);
-      const float2 v1 = make_float2(cw12 * cy1.x, cw12 * cy1.y);
-      const float W0[8] = {cwa.x, cwa.y, cwa.z, cwa.w, cwb.x, cwb.y, cwb.z, cwb.w};
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        a0[j].x = fmaf(W0[j], v0.x, a0[j].x);
-        a0[j].y = fmaf(W0[j], v0.y, a0[j].y);
-        a1[j].x = fmaf(W0[j], v1.x, a1[j].x);
-        a1[j].y = fmaf(W0[j], v1.y, a1[j].y);
-      }
-    }
+    // the batch's samples in the unit's row classes (uniform bounds)
+    const int e0 = min(max(un.lo - b0, 0), nb), e1 = min(max(un.lohi - b0, 0), nb);
+    kspread_reg_run<0, 4>(0, e0, st_W, stw, st_y, C, l1, l2, cr, cr1, a0, a1);
+    kspread_reg_run<4, 8>(e0, e1, st_W, stw, st_y, C, l1, l2, cr, cr1, a0, a1);
+    kspread_reg_run<0, 8>(e1, nb, st_W, stw, st_y, C, l1, l2, cr, cr1, a0, a1);
   }
   // registers straight to memory (each wave writes a strided third of every
   // tile row; the L2 merges the rows before they reach HBM)

@@ -297,7 +297,8 @@ struct isg_traj {
   float* k = nullptr;             // [M][ndim] the trajectory (cycles/voxel), for the translation phases
   float2* phase = nullptr;        // [M] exp(-2 pi i k_j . t_j) of a bulk translation, or null
   std::vector<int> tile_first;    // host: tile-sorted visits of tile t are tile_first[t] .. tile_first[t+1]
-  std::vector<KTap> taps_h;       // host copy of taps (re-binning for another tile shape)
+  std::vector<KTap> taps_h;
+  std::vector<int> tile_rows;      // per tile: visits reaching rows 0-3 only, rows 4-7 only (register spread)       // host copy of taps (re-binning for another tile shape)
 };
 
 static bool tiled_adjoint(const isg_plan* pl);
@@ -1956,22 +1957,32 @@ static void build_units(isg_plan* pl, isg_traj* tr) {
   std::vector<KUnit> units;
   std::vector<KSplit> splits;
   int slots = 0;
+  const bool rows = tr->tile_rows.size() == 2 * (size_t)ntiles;
+  // a unit covering visits [off, off + n) of its tile: its row-class bounds
+  auto unit = [&](int t, int off, int n, int slot, int gs) {
+    KUnit u{t, cnt[t] + off, n, slot, gs, 0, 0};
+    if (rows) {
+      const int lo = tr->tile_rows[2 * t], hi = tr->tile_rows[2 * t + 1];
+      u.lo = std::min(std::max(lo - off, 0), n);
+      u.lohi = std::min(std::max(lo + hi - off, 0), n);
+    }
+    return u;
+  };
   for (int t = 0; t < ntiles; ++t) {
-    const int beg = cnt[t], c = cnt[t + 1] - cnt[t];
+    const int c = cnt[t + 1] - cnt[t];
     if (c == 0 && masked) continue;
     const int gs = c > 0 ? tile_gslot(pl, tr, t) : -1;
     if (c <= chunk) {
-      units.push_back(KUnit{t, beg, c, -1, gs});
+      units.push_back(unit(t, 0, c, -1, gs));
     } else {
       const int nch = (c + chunk - 1) / chunk;
       splits.push_back(KSplit{t, slots, nch, gs});
-      for (int q = 0; q < nch; ++q)
-        units.push_back(KUnit{t, beg + q * chunk, std::min(chunk, c - q * chunk), slots + q, gs});
+      for (int q = 0; q < nch; ++q) units.push_back(unit(t, q * chunk, std::min(chunk, c - q * chunk), slots + q, gs));
       slots += nch;
     }
   }
   std::stable_sort(units.begin(), units.end(), [](const KUnit& a, const KUnit& b) { return a.count > b.count; });
-  if (units.empty()) units.push_back(KUnit{0, 0, 0, -1, -1});  // keep the launch non-empty
+  if (units.empty()) units.push_back(KUnit{0, 0, 0, -1, -1, 0, 0});  // keep the launch non-empty
   HIP_OK(hipStreamSynchronize(pl->stream));
   pl->generation++;
   HIP_OK(dfree(pl, tr->units));
@@ -2038,6 +2049,34 @@ static void bin_traj(isg_plan* pl, isg_traj* tr) {
   std::vector<int> pos(cnt.begin(), cnt.end() - 1);
   std::vector<int> order(std::max(1, cnt[ntiles]));
   for (int64_t j = 0; j < M; ++j) visit(j, [&](int t) { order[pos[t]++] = (int)j; });
+  // for the register spread (8 x 4 x 8 tiles): each tile's visits by the
+  // rows of the tile their axis-0 taps reach (0-3 only, 4-7 only, both),
+  // sample order within a class; the row of the first tap is formed as the
+  // spread forms it (periodic offset from the tile origin)
+  tr->tile_rows.clear();
+  if (nd == 3 && pl->ktile.TS[0] == 8 && pl->ktile.TS[1] == 4 && pl->ktile.TS[2] == 8) {
+    tr->tile_rows.assign(2 * (size_t)ntiles, 0);
+    const int plane = pl->ktile.nt[1] * pl->ktile.nt[2], G0 = pl->G[0];
+    std::vector<int> part;
+    for (int t = 0; t < ntiles; ++t) {
+      const int beg = cnt[t], n = cnt[t + 1] - cnt[t];
+      if (n == 0) continue;
+      part.assign(order.begin() + beg, order.begin() + beg + n);
+      auto cls = [&](int j) {
+        int o = (int)(taps[j].base & 1023) - (t / plane) * 8;
+        if (o > G0 / 2) o -= G0;
+        if (o < -G0 / 2) o += G0;
+        return o <= 0 ? 0 : (o >= 4 ? 1 : 2);
+      };
+      int w = beg;
+      for (int c = 0; c < 3; ++c) {
+        const int w0 = w;
+        for (int j : part)
+          if (cls(j) == c) order[w++] = j;
+        if (c < 2) tr->tile_rows[2 * (size_t)t + c] = w - w0;
+      }
+    }
+  }
   tr->ntouched = 0;
   for (int t = 0; t < ntiles; ++t)
     if (cnt[t + 1] > cnt[t]) tr->ntouched++;
