@@ -297,8 +297,8 @@ struct isg_traj {
   float* k = nullptr;             // [M][ndim] the trajectory (cycles/voxel), for the translation phases
   float2* phase = nullptr;        // [M] exp(-2 pi i k_j . t_j) of a bulk translation, or null
   std::vector<int> tile_first;    // host: tile-sorted visits of tile t are tile_first[t] .. tile_first[t+1]
-  std::vector<KTap> taps_h;
-  std::vector<int> tile_rows;      // per tile: visits reaching rows 0-3 only, rows 4-7 only (register spread)       // host copy of taps (re-binning for another tile shape)
+  std::vector<KTap> taps_h;        // host copy of taps (re-binning for another tile shape)
+  std::vector<int> tile_rows;      // per tile: visits reaching rows 0-3 only, rows 4-7 only (register spread)
 };
 
 static bool tiled_adjoint(const isg_plan* pl);
@@ -3067,6 +3067,7 @@ isg_status isg_plan_destroy(isg_plan* pl) {
   if (pl->tune_out.p) (void)hipFree(pl->tune_out.p);
   if (pl->sol.p) (void)hipFree(pl->sol.p);
   if (pl->sol_part.p) (void)hipFree(pl->sol_part.p);
+  if (pl->bin.p) (void)hipFree(pl->bin.p);
   if (pl->own_stream) (void)hipStreamDestroy(pl->own_stream);
   for (auto& p : pl->pending) {
     (void)hipEventDestroy(p.a);

@@ -5,16 +5,19 @@ tests/test_gpu_mixed128.py to state the error of the FP32, FP16 and BF16
 grid forms of the GPU solve against FP64.
 
 Problem: (sum_p A_p^H A_p + lambda I) x = sum_p A_p^H y_p (l2 form of Eq. 11),
-lambda = 1e-3, x0 = 0, 30 Hestenes-Stiefel iterations (oracle.cg), with y the
-seeded complex noise of synth (all states packed, [sum_p M_p][C]).  Stored:
-the residual norms ||r_0|| .. ||r_30||, the iterate x_30 at 4096 seeded
-voxels and its norm, and sum_p A_p^H y_p at the same voxels.
+x0 = 0, 30 Hestenes-Stiefel iterations (oracle.cg), with y the seeded complex
+noise of synth (all states packed, [sum_p M_p][C]).  lambda = 1e-3 (the
+workload's; CG does not converge in 30 iterations there, a stress case) is
+written to mixed128_cg.json, lambda = 0.5 (--lam 0.5) to
+mixed128_cg_lam0.5.json.  Stored: the residual norms ||r_0|| .. ||r_30||, the
+iterate x_30 at 4096 seeded voxels and its norm, and sum_p A_p^H y_p at the
+same voxels.
 
 It calls only oracle/ and synth/; the states of every normal-operator
 application run in parallel worker processes (one per state, single-threaded
 FFTs, about 2 GB each):
 
-    python tests/golden/make_mixed128_cg_reference.py [--workers 8]
+    python tests/golden/make_mixed128_cg_reference.py [--workers 8] [--lam 0.5]
 """
 import argparse
 import json
@@ -76,7 +79,10 @@ def _normal_state(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--lam", type=float, default=W.lam)
     args = ap.parse_args()
+    lam = args.lam
+    out_path = OUT if lam == W.lam else OUT.replace(".json", f"_lam{lam:g}.json")
     t0 = time.time()
     vs = selections(int(np.prod(W.shape)))
     with get_context("spawn").Pool(args.workers, initializer=_init) as pool:
@@ -87,7 +93,7 @@ def main():
         count = [0]
 
         def normal(v):
-            out = W.lam * v
+            out = lam * v
             for a in pool.map(_normal_state, [(p, v) for p in range(W.nphases)]):
                 out = out + a
             count[0] += 1
@@ -97,7 +103,7 @@ def main():
         x, hist = oracle.cg.cg(normal, b, W.cg_iters)
     rec = {
         "workload": W.name,
-        "lambda": W.lam,
+        "lambda": lam,
         "iters": W.cg_iters,
         "note": "FP64 oracle CG written by tests/golden/make_mixed128_cg_reference.py",
         "voxels": vs.tolist(),
@@ -106,9 +112,9 @@ def main():
         "b": [[float(z.real), float(z.imag)] for z in b.reshape(-1)[vs]],
         "norms": {"x_final": float(np.linalg.norm(x)), "b": float(np.linalg.norm(b))},
     }
-    with open(OUT, "w") as f:
+    with open(out_path, "w") as f:
         json.dump(rec, f)
-    print(f"wrote {OUT} in {time.time() - t0:.0f}s", flush=True)
+    print(f"wrote {out_path} in {time.time() - t0:.0f}s", flush=True)
 
 
 if __name__ == "__main__":
