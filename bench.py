@@ -215,10 +215,12 @@ def main():
     per_launch = stage_bytes(dominant, w.shape, G, w.ncoils, es)
     infos = [t.info() for t in trs]
     if dominant in ("fft_coil_fwd_ax0", "fft_coil_adj_ax0"):
-        # these passes move only the 8-cell runs along axis 0 that some
-        # sample's taps reach (the touched cells), one state per launch
-        tot = sum(i["touched_cells"] * w.ncoils * es for i in infos)
-        per_launch = tot // len(trs) + w.shape[0] * G[1] * G[2] * w.ncoils * es
+        # these passes transform only the grid columns along axis 0 that hold
+        # a run of cells some sample's taps reach, and of those move only the
+        # touched runs on the k-space side and n0 cells on the image side, one
+        # state per launch
+        tot = sum((i["touched_cells"] + w.shape[0] * i["active_columns"]) * w.ncoils * es for i in infos)
+        per_launch = tot // len(trs)
     if per_launch is None and dominant in ("kspread", "kgather"):
         # one state per launch unless batched: bytes of all states / launches
         per_launch = sum(kspace_bytes(dominant, i, k.shape[0], w.ncoils, es) for i, k in zip(infos, inp["k"]))

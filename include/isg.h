@@ -254,6 +254,10 @@ isg_status isg_traj_info(const isg_traj* traj, int64_t* nvisits, int64_t* ntiles
  * tile extent along axis 0) that some sample's taps reach, per grid column;
  * 0 when the path keeps no such masks (every cell is then touched). */
 isg_status isg_traj_touched_cells(const isg_traj* traj, int64_t* cells);
+/* Grid columns (i1, i2) along axis 0 that hold at least one touched run: the
+ * lines the axis-0 passes transform (all others are skipped); 0 when the
+ * path keeps no such masks. */
+isg_status isg_traj_active_columns(const isg_traj* traj, int64_t* cols);
 
 /* y = T_d x, forward image-space gridding (Eq. 9).  x, y: device complex64
  * images; out-of-place (x != y). */

@@ -40,6 +40,7 @@ SIGNATURES = {
     "isg_traj_count": (C.c_int, [_p, C.POINTER(_i64)]),
     "isg_traj_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)]),
     "isg_traj_touched_cells": (C.c_int, [_p, C.POINTER(_i64)]),
+    "isg_traj_active_columns": (C.c_int, [_p, C.POINTER(_i64)]),
     "isg_warp": (C.c_int, [_p, _p, _p, _p]),
     "isg_warp_adjoint": (C.c_int, [_p, _p, _p, _p]),
     "isg_warp_adjoint_noalloc": (C.c_int, [_p, _p, _p, _p]),

@@ -275,6 +275,7 @@ struct isg_traj {
   uint64_t* cact = nullptr;     // 3D: bit i1 of word [i2][i1 / 64] set where fmask[(i1, i2)] != 0 (G1 <= 512)
   int cact_w = 0;               // words per i2
   int64_t fine_cells = 0;       // grid cells in the touched runs
+  int64_t active_cols = 0;      // grid columns (i1, i2) holding a touched run
   int* colbase = nullptr;       // tile-major spread output: first slot of each tile column
   std::vector<uint64_t> colmask_h;
   std::vector<int> colbase_h;
@@ -2023,6 +2024,7 @@ static void bin_traj(isg_plan* pl, isg_traj* tr) {
     traj_free(pl, *q);
   tr->cact_w = 0;
   tr->fine_cells = 0;
+  tr->active_cols = 0;
   tr->colmask_h.clear();
   tr->colbase_h.clear();
   int ntiles = 1;
@@ -2122,7 +2124,10 @@ static void bin_traj(isg_plan* pl, isg_traj* tr) {
       }
     }
     int64_t runs = 0;
-    for (uint64_t m : fm) runs += __builtin_popcountll(m);
+    for (uint64_t m : fm) {
+      runs += __builtin_popcountll(m);
+      tr->active_cols += m != 0;
+    }
     tr->fine_cells = runs * (1 << lg);  // ragged last runs counted whole
     tr->fmask = (uint64_t*)dmalloc(pl, sizeof(uint64_t) * fm.size());
     HIP_OK(hipMemcpy(tr->fmask, fm.data(), sizeof(uint64_t) * fm.size(), hipMemcpyHostToDevice));
@@ -3199,6 +3204,12 @@ isg_status isg_traj_info(const isg_traj* tr, int64_t* nvisits, int64_t* ntiles, 
 isg_status isg_traj_touched_cells(const isg_traj* tr, int64_t* cells) {
   if (!tr || !cells) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
   *cells = tr->fine_cells;
+  return ISG_OK;
+}
+
+isg_status isg_traj_active_columns(const isg_traj* tr, int64_t* cols) {
+  if (!tr || !cols) return fail(ISG_ERR_INVALID_ARG, "NULL argument");
+  *cols = tr->active_cols;
   return ISG_OK;
 }
 

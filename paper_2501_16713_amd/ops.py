@@ -85,11 +85,14 @@ class Traj:
     def info(self) -> dict:
         """{"visits": (sample, tile) spread visits, "tiles": touched spread
         tiles, "tile_points": grid points per tile, "touched_cells": grid
-        cells of the touched runs the axis-0 passes move}"""
-        a, b, c, f = C.c_int64(0), C.c_int64(0), C.c_int64(0), C.c_int64(0)
+        cells of the touched runs the axis-0 passes move, "active_columns":
+        grid columns along axis 0 holding such a run}"""
+        a, b, c, f, g = (C.c_int64(0) for _ in range(5))
         check(self.plan.lib.isg_traj_info(self.handle, C.byref(a), C.byref(b), C.byref(c)))
         check(self.plan.lib.isg_traj_touched_cells(self.handle, C.byref(f)))
-        return {"visits": a.value, "tiles": b.value, "tile_points": c.value, "touched_cells": f.value}
+        check(self.plan.lib.isg_traj_active_columns(self.handle, C.byref(g)))
+        return {"visits": a.value, "tiles": b.value, "tile_points": c.value, "touched_cells": f.value,
+                "active_columns": g.value}
 
     def set_shift(self, t: torch.Tensor | None) -> None:
         """Translate the object by t (float32 [M][ndim], voxels) during the

@@ -172,6 +172,32 @@ def test_ktile_extent(setup):
     assert rel(res[4], want) < 1e-5
 
 
+def test_touched_runs_and_columns(setup):
+    """the bookkeeping behind the axis-0 passes' tile skipping and their
+    algorithmic bytes, bit-exact against the taps the oracle's interpolation
+    uses (W = 4 per axis around G k): the grid cells in touched 8-cell runs
+    along axis 0 (the k-space tile extent there) and the grid columns (i1, i2)
+    holding at least one such run"""
+    isg = setup[0]
+    w = small_workload(shape=(32, 40, 48), ncoils=2, nphases=2, spokes=(25, 70), cfg=143)
+    inp = make_inputs(w)
+    plan = isg.Plan(w.shape, ncoils=w.ncoils, nphases=w.nphases)
+    G = tuple(2 * n for n in w.shape)
+    for k in inp["k"]:
+        say(f"touched runs, {k.shape[0]} samples")
+        info = plan.traj(to_dev(k)).info()
+        kap = oracle.kspace.grid_coords(k, G)
+        idx = [oracle.grid.taps_1d(kap[:, a], G[a])[0] for a in range(3)]
+        runs = np.zeros((G[1], G[2], G[0] // 8), dtype=bool)
+        for t0 in range(4):
+            for t1 in range(4):
+                for t2 in range(4):
+                    runs[idx[1][t1], idx[2][t2], idx[0][t0] // 8] = True
+        assert info["touched_cells"] == 8 * int(runs.sum())
+        assert info["active_columns"] == int(runs.any(axis=2).sum())
+        assert 0 < info["active_columns"] < G[1] * G[2]
+
+
 def test_kspace_blocking_is_bit_exact(setup):
     """row-blocked internal k-space arrays (32 x 40 x 48: register-FFT path)"""
     import torch
