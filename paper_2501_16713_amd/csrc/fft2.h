@@ -192,9 +192,14 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
   constexpr int L = L1 * L2;
   constexpr bool kGapIn = (GAP & 1) && L1 % 4 == 0;
   constexpr bool kGapOut = (GAP & 2) && L2 % 4 == 0;
+  // Without an LDS epilogue the lines go through LDS as real parts, then
+  // imaginary parts, in one float buffer: half the LDS per line, so twice
+  // the workgroups fit a CU (two more barriers per tile).
+  constexpr bool kSplit = !St::kEpilogue;
   extern __shared__ float2 smem[];
   float2* tw = smem;           // exp(-2 pi i q / L)
   float2* lines = smem + L;
+  float* linesf = reinterpret_cast<float*>(smem + L);
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
 
@@ -233,7 +238,8 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
       return;
     }
   }
-  uint32_t* table = reinterpret_cast<uint32_t*>(lines + (size_t)nl * g.LS);
+  uint32_t* table = kSplit ? reinterpret_cast<uint32_t*>(linesf + (size_t)nl * g.LS)
+                          : reinterpret_cast<uint32_t*>(lines + (size_t)nl * g.LS);
   if constexpr (Ld::kPrologue) ld.prologue(table, a0, b0, g);
   for (int i = tid; i < L; i += nthreads) tw[i] = ld.tw[i];
   if constexpr (Ld::kPrologue) __syncthreads();  // the loader's table
@@ -253,27 +259,59 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
     reg_dft<L1, S>(v);
   }
   __syncthreads();  // twiddle table in LDS
-  if (act1) {
-    float2* dst = lines + (al * g.nb + bl) * g.LS;
-#pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) {
-      float2 w = tw[n2 * k1];  // n2 k1 <= (L2 - 1)(L1 - 1) < L
-      w.y *= -(float)S;  // conjugate the table entry for the inverse sign
-      dst[slot<L1, L2>(k1, n2)] = k1 == 0 ? v[0] : cmul(v[k1], w);
-    }
-  }
-  __syncthreads();
-
-  // ---- step 2 ----
   const bool act2 = tid < nl * L1;
   int bl2 = 0, k1 = 0, al2 = 0;
   float2 u[L2];
-  if (act2) {
-    decode<MAP2>(tid, g.nb, L1, bl2, k1, al2);
-    const float2* src = lines + (al2 * g.nb + bl2) * g.LS;
+  if (act2) decode<MAP2>(tid, g.nb, L1, bl2, k1, al2);
+  if constexpr (kSplit) {
+    if (act1) {
 #pragma unroll
-    for (int n2 = 0; n2 < L2; ++n2) u[n2] = src[slot<L1, L2>(k1, n2)];
-    reg_dft<L2, S>(u);
+      for (int j = 1; j < L1; ++j) {
+        float2 w = tw[n2 * j];  // n2 j <= (L2 - 1)(L1 - 1) < L
+        w.y *= -(float)S;       // conjugate the table entry for the inverse sign
+        v[j] = cmul(v[j], w);
+      }
+      float* dst = linesf + (al * g.nb + bl) * g.LS;
+#pragma unroll
+      for (int j = 0; j < L1; ++j) dst[slot<L1, L2>(j, n2)] = v[j].x;
+    }
+    __syncthreads();
+    const float* src = linesf + (al2 * g.nb + bl2) * g.LS;
+    if (act2) {
+#pragma unroll
+      for (int m = 0; m < L2; ++m) u[m].x = src[slot<L1, L2>(k1, m)];
+    }
+    __syncthreads();
+    if (act1) {
+      float* dst = linesf + (al * g.nb + bl) * g.LS;
+#pragma unroll
+      for (int j = 0; j < L1; ++j) dst[slot<L1, L2>(j, n2)] = v[j].y;
+    }
+    __syncthreads();
+    if (act2) {
+#pragma unroll
+      for (int m = 0; m < L2; ++m) u[m].y = src[slot<L1, L2>(k1, m)];
+      reg_dft<L2, S>(u);
+    }
+  } else {
+    if (act1) {
+      float2* dst = lines + (al * g.nb + bl) * g.LS;
+#pragma unroll
+      for (int j = 0; j < L1; ++j) {
+        float2 w = tw[n2 * j];  // n2 j <= (L2 - 1)(L1 - 1) < L
+        w.y *= -(float)S;       // conjugate the table entry for the inverse sign
+        dst[slot<L1, L2>(j, n2)] = j == 0 ? v[0] : cmul(v[j], w);
+      }
+    }
+    __syncthreads();
+
+    // ---- step 2 ----
+    if (act2) {
+      const float2* src = lines + (al2 * g.nb + bl2) * g.LS;
+#pragma unroll
+      for (int m = 0; m < L2; ++m) u[m] = src[slot<L1, L2>(k1, m)];
+      reg_dft<L2, S>(u);
+    }
   }
   if constexpr (St::kEpilogue) {
     // results go back to LDS in natural order for a cross-line epilogue
