@@ -171,7 +171,10 @@ __device__ __forceinline__ int slot(int k1, int n2) {
 // positions k1 + L1 k2, k2 = 0..L2-1.  Loaders and stores see the tile origin
 // and the thread's place in it separately, so that the part of an address
 // shared by the tile (and by an element index) can stay in scalar registers.
-// St may request an LDS epilogue (coil reduction) through St::kEpilogue; Ld
+// St may request an LDS epilogue (coil reduction) through St::kEpilogue: it
+// then sees the lines in natural order twice, real parts, then imaginary
+// parts (epilogue_part, accumulating up to St::kMaxPerThread outputs per
+// thread), and stores (epilogue_store); Ld
 // may fill a table in LDS before any load through Ld::kPrologue (its size:
 // lds_extra(ld) on the host).
 // GAP bit 0: the loads zero-pad L/2 stored values, so positions [L/4, 3L/4)
@@ -192,13 +195,11 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
   constexpr int L = L1 * L2;
   constexpr bool kGapIn = (GAP & 1) && L1 % 4 == 0;
   constexpr bool kGapOut = (GAP & 2) && L2 % 4 == 0;
-  // Without an LDS epilogue the lines go through LDS as real parts, then
-  // imaginary parts, in one float buffer: half the LDS per line, so twice
-  // the workgroups fit a CU (two more barriers per tile).
-  constexpr bool kSplit = !St::kEpilogue;
+  // The lines go through LDS as real parts, then imaginary parts, in one
+  // float buffer (as does the epilogue's input): half the LDS per line, so
+  // twice the workgroups fit a CU, for two more barriers per tile.
   extern __shared__ float2 smem[];
-  float2* tw = smem;           // exp(-2 pi i q / L)
-  float2* lines = smem + L;
+  float2* tw = smem;  // exp(-2 pi i q / L)
   float* linesf = reinterpret_cast<float*>(smem + L);
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
@@ -238,8 +239,7 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
       return;
     }
   }
-  uint32_t* table = kSplit ? reinterpret_cast<uint32_t*>(linesf + (size_t)nl * g.LS)
-                          : reinterpret_cast<uint32_t*>(lines + (size_t)nl * g.LS);
+  uint32_t* table = reinterpret_cast<uint32_t*>(linesf + (size_t)nl * g.LS);
   if constexpr (Ld::kPrologue) ld.prologue(table, a0, b0, g);
   for (int i = tid; i < L; i += nthreads) tw[i] = ld.tw[i];
   if constexpr (Ld::kPrologue) __syncthreads();  // the loader's table
@@ -263,67 +263,55 @@ __global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
   int bl2 = 0, k1 = 0, al2 = 0;
   float2 u[L2];
   if (act2) decode<MAP2>(tid, g.nb, L1, bl2, k1, al2);
-  if constexpr (kSplit) {
-    if (act1) {
+  if (act1) {
 #pragma unroll
-      for (int j = 1; j < L1; ++j) {
-        float2 w = tw[n2 * j];  // n2 j <= (L2 - 1)(L1 - 1) < L
-        w.y *= -(float)S;       // conjugate the table entry for the inverse sign
-        v[j] = cmul(v[j], w);
-      }
-      float* dst = linesf + (al * g.nb + bl) * g.LS;
-#pragma unroll
-      for (int j = 0; j < L1; ++j) dst[slot<L1, L2>(j, n2)] = v[j].x;
+    for (int j = 1; j < L1; ++j) {
+      float2 w = tw[n2 * j];  // n2 j <= (L2 - 1)(L1 - 1) < L
+      w.y *= -(float)S;       // conjugate the table entry for the inverse sign
+      v[j] = cmul(v[j], w);
     }
-    __syncthreads();
-    const float* src = linesf + (al2 * g.nb + bl2) * g.LS;
-    if (act2) {
+    float* dst = linesf + (al * g.nb + bl) * g.LS;
 #pragma unroll
-      for (int m = 0; m < L2; ++m) u[m].x = src[slot<L1, L2>(k1, m)];
-    }
-    __syncthreads();
-    if (act1) {
-      float* dst = linesf + (al * g.nb + bl) * g.LS;
-#pragma unroll
-      for (int j = 0; j < L1; ++j) dst[slot<L1, L2>(j, n2)] = v[j].y;
-    }
-    __syncthreads();
-    if (act2) {
-#pragma unroll
-      for (int m = 0; m < L2; ++m) u[m].y = src[slot<L1, L2>(k1, m)];
-      reg_dft<L2, S>(u);
-    }
-  } else {
-    if (act1) {
-      float2* dst = lines + (al * g.nb + bl) * g.LS;
-#pragma unroll
-      for (int j = 0; j < L1; ++j) {
-        float2 w = tw[n2 * j];  // n2 j <= (L2 - 1)(L1 - 1) < L
-        w.y *= -(float)S;       // conjugate the table entry for the inverse sign
-        dst[slot<L1, L2>(j, n2)] = j == 0 ? v[0] : cmul(v[j], w);
-      }
-    }
-    __syncthreads();
-
-    // ---- step 2 ----
-    if (act2) {
-      const float2* src = lines + (al2 * g.nb + bl2) * g.LS;
-#pragma unroll
-      for (int m = 0; m < L2; ++m) u[m] = src[slot<L1, L2>(k1, m)];
-      reg_dft<L2, S>(u);
-    }
+    for (int j = 0; j < L1; ++j) dst[slot<L1, L2>(j, n2)] = v[j].x;
   }
-  if constexpr (St::kEpilogue) {
-    // results go back to LDS in natural order for a cross-line epilogue
-    __syncthreads();
-    if (act2) {
-      float2* dstl = lines + (al2 * g.nb + bl2) * g.LS;
+  __syncthreads();
+  const float* src = linesf + (al2 * g.nb + bl2) * g.LS;
+  if (act2) {
 #pragma unroll
-      for (int k2 = 0; k2 < L2; ++k2)
-        if (!(kGapOut && k2 >= L2 / 4 && k2 < 3 * L2 / 4)) dstl[k1 + L1 * k2] = u[k2];
+    for (int m = 0; m < L2; ++m) u[m].x = src[slot<L1, L2>(k1, m)];
+  }
+  __syncthreads();
+  if (act1) {
+    float* dst = linesf + (al * g.nb + bl) * g.LS;
+#pragma unroll
+    for (int j = 0; j < L1; ++j) dst[slot<L1, L2>(j, n2)] = v[j].y;
+  }
+  __syncthreads();
+  if (act2) {
+#pragma unroll
+    for (int m = 0; m < L2; ++m) u[m].y = src[slot<L1, L2>(k1, m)];
+    reg_dft<L2, S>(u);
+  }
+
+  if constexpr (St::kEpilogue) {
+    // results go back to LDS in natural order for a cross-line epilogue,
+    // real parts, then imaginary parts
+    float2 acc[St::kMaxPerThread];
+#pragma unroll
+    for (int i = 0; i < St::kMaxPerThread; ++i) acc[i] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      __syncthreads();  // the previous reads of the buffer are done
+      if (act2) {
+        float* dstl = linesf + (al2 * g.nb + bl2) * g.LS;
+#pragma unroll
+        for (int k2 = 0; k2 < L2; ++k2)
+          if (!(kGapOut && k2 >= L2 / 4 && k2 < 3 * L2 / 4)) dstl[k1 + L1 * k2] = part ? u[k2].y : u[k2].x;
+      }
+      __syncthreads();
+      st.epilogue_part(linesf, g, a0, part, acc);
     }
-    __syncthreads();
-    st.epilogue(lines, g, a0, b0);
+    st.epilogue_store(g, a0, acc);
   } else {
     if (act2) {
       const bool valid = a0 + al2 < g.A && b0 + bl2 < g.B;
@@ -1014,10 +1002,45 @@ struct St2CoilReduce {
   int n, L, C;
   int n1;
   struct Line {};
-  __device__ void epilogue(const float2* lines, const Tile2& g, int64_t a0, int64_t) const {
+  // output elements per thread: total = na n = na L / 2 and the workgroup
+  // has at least na C L2 threads, so at most L1 / (2 C) <= 8 (L1 <= 16)
+  static constexpr int kMaxPerThread = 8;
+  // part 0: lines hold the real parts u.x of the transformed lines, part 1
+  // the imaginary parts u.y; conj(S) u = (S.x u.x + S.y u.y) + i (S.x u.y - S.y u.x)
+  __device__ void epilogue_part(const float* lines, const Tile2& g, int64_t a0, int part,
+                                float2 (&acc)[kMaxPerThread]) const {
+    const int total = g.na * n;
+#pragma unroll
+    for (int i = 0; i < kMaxPerThread; ++i) {
+      const int e = (int)threadIdx.x + i * (int)blockDim.x;
+      if (e >= total) break;
+      const int al = e / n;
+      const int j = e - al * n;
+      if (a0 + al >= g.A) continue;
+      const int64_t off = (a0 + al) * n + j;
+      const int pos = j < n / 2 ? j + L - n / 2 : j - n / 2;
+      float2 a = acc[i];
+      for (int c = 0; c < C; ++c) {
+        const float2 sv = S[(int64_t)c * N + off];
+        const float v = lines[(al * C + c) * g.LS + pos];
+        if (part == 0) {
+          a.x = fmaf(sv.x, v, a.x);
+          a.y = fmaf(-sv.y, v, a.y);
+        } else {
+          a.x = fmaf(sv.y, v, a.x);
+          a.y = fmaf(sv.x, v, a.y);
+        }
+      }
+      acc[i] = a;
+    }
+  }
+  __device__ void epilogue_store(const Tile2& g, int64_t a0, const float2 (&acc)[kMaxPerThread]) const {
     const int total = g.na * n;
     const float hs = scale * undo.factor();
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < kMaxPerThread; ++i) {
+      const int e = (int)threadIdx.x + i * (int)blockDim.x;
+      if (e >= total) break;
       const int al = e / n;
       const int j = e - al * n;
       const int64_t a = a0 + al;
@@ -1029,12 +1052,7 @@ struct St2CoilReduce {
       } else {
         f *= dx.t[0][a];
       }
-      const int64_t off = a * n + j;
-      const int pos = j < n / 2 ? j + L - n / 2 : j - n / 2;
-      float2 acc = make_float2(0.f, 0.f);
-      for (int c = 0; c < C; ++c)
-        acc = cadd(acc, cmulc(S[(int64_t)c * N + off], lines[(al * C + c) * g.LS + pos]));
-      out[off] = cscale(acc, f);
+      out[a * n + j] = cscale(acc[i], f);
     }
   }
 };

@@ -505,9 +505,12 @@ static void launch_fft2(isg_plan* pl, const char* tag, const Ld& ld, const St& s
   const int threads = ((nl * L2 + 63) / 64) * 64;
   if (threads > 512 || nl * L1 > threads)
     throw HipError{hipErrorInvalidConfiguration, "fft2 tile does not fit one workgroup"};
-  // lines exchanged as float parts unless the store has an LDS epilogue (see fft2_kernel)
-  const size_t lds = sizeof(float2) * (size_t)L + (St::kEpilogue ? sizeof(float2) : sizeof(float)) * (size_t)nl * g.LS +
-                     lds_extra(ld);
+  if constexpr (St::kEpilogue) {
+    if ((int64_t)g.na * st.n > (int64_t)St::kMaxPerThread * threads)
+      throw HipError{hipErrorInvalidConfiguration, "fft2 epilogue outputs exceed the per-thread accumulators"};
+  }
+  // lines exchanged as float parts (see fft2_kernel)
+  const size_t lds = sizeof(float2) * (size_t)L + sizeof(float) * (size_t)nl * g.LS + lds_extra(ld);
   if (((GAP & 1) && !half_gap(ld, L)) || ((GAP & 2) && !half_gap(st, L)))
     throw HipError{hipErrorInvalidConfiguration, "fft2 gap flags do not match the line maps"};
   auto kern = fft2_kernel<L1, L2, SG, M1, M2, Ld, St, GAP>;
