@@ -138,7 +138,7 @@ struct Tile2 {
   int64_t A, B;     // outer count, inner extent
   int na, nb;       // lines per tile: na outer x nb inner
   int64_t tiles_b;  // ceil(B / nb)
-  int LS;           // LDS line stride (float2)
+  int LS;           // LDS line stride (floats)
   int64_t tiles;    // > 0: total tiles, launched as 8 ceil(tiles / 8) workgroups in XCD-contiguous
                     // order; 0: plain order (host: < 0 requests XCD order)
 };
