@@ -191,7 +191,7 @@ template <class T>
 struct tile_skip<T, std::void_t<decltype(T::kTileSkip)>> : std::bool_constant<T::kTileSkip> {};
 
 template <int L1, int L2, int S, int MAP1, int MAP2, class Ld, class St, int GAP = 0>
-__global__ __launch_bounds__(512) void fft2_kernel(Ld ld, St st, Tile2 g) {
+__global__ __launch_bounds__(1024) void fft2_kernel(Ld ld, St st, Tile2 g) {
   constexpr int L = L1 * L2;
   constexpr bool kGapIn = (GAP & 1) && L1 % 4 == 0;
   constexpr bool kGapOut = (GAP & 2) && L2 % 4 == 0;
