@@ -458,7 +458,8 @@ static bool fft2_supported(int L) {
 }
 
 // the same tile with XCD-contiguous workgroup order (measured faster for the
-// axis-1 passes, whose lines are 30 KB apart; slower for the axis-0 passes)
+// adjoint axis-1 pass, whose lines are 30 KB apart; slower for the axis-0
+// passes, the last-axis passes and the 32-line forward axis-1 pass)
 static Tile2 xcd_order(Tile2 g) {
   g.tiles = -1;
   return g;
@@ -1273,7 +1274,7 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
     fft2_pass<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax1", G1,
                                      ld2<kFP32>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
                                      st2_axis1<kFP32>(pl->k2buf, pl->blk_k2, kDense, 1.f),
-                                     xcd_order(make_tile2(n0, (int64_t)G2 * C, G1, -32)));  // 32 lines measured faster here
+                                     make_tile2(n0, (int64_t)G2 * C, G1, -32));  // 32 lines, plain order: measured faster
     // centred pad, F along axis 0
     fft2_pass<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2_rows<kFP32>(pl, pl->k2buf, pl->blk_k2, kCentred, G0),
                                  st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), 1.f),
