@@ -838,9 +838,11 @@ struct Ld2TilesF {
     uint32_t coff;        // the lane's coil, bytes
   };
   // grid columns and tile columns are below 2^31 (checked on the host)
+  // (uniform: read into a scalar register, so that the buffer descriptor
+  // built from it stays scalar and each load is a single instruction)
   __device__ int64_t row_base(uint32_t q0) const {  // first tile slot of q0's tile row, elements
     const uint32_t i1 = q0 / (uint32_t)G2;
-    return (int64_t)colbase[(i1 / (uint32_t)ts1) * nt2] * volC;
+    return (int64_t)__builtin_amdgcn_readfirstlane(colbase[(i1 / (uint32_t)ts1) * nt2]) * volC;
   }
   __device__ void prologue(uint32_t* table, int64_t, int64_t b0, const Tile2&) const {
     const uint32_t q0 = (uint32_t)b0 / (uint32_t)C;
