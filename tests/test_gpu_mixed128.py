@@ -11,13 +11,23 @@ FP32, FP16 and BF16 grid storage with the options bench.py times:
   ||r_0|| .. ||r_30|| (l2 form of Eq. 11, x_0 = 0), at two lambdas:
   - lambda = 1e-3 (the workload's) on noise data is a stress case: the FP64
     solve itself has not converged after 30 iterations (||r_30|| / ||r_0|| =
-    1.38, after a jump to 6.8 at the first step), and CG amplifies any
-    rounding difference by up to the condition number; measured x_30 errors
+    1.38, after a jump to 6.8 at the first step); measured x_30 errors
     0.10 (FP32), 0.15 (FP16), 0.19 (BF16).  The test states them and bounds
     them at about three times that, and the final residual ratio within a
     factor 2 of FP64's;
-  - lambda = 0.5 (a well-conditioned system that CG nearly solves in 30
-    iterations) holds the iterate to bounds a few times the measured error.
+  - lambda = 0.5 is no better conditioned at this data scale: the FP64 solve
+    ends at ||r_30|| / ||r_0|| = 0.93 (after 6.8 at the first step); measured
+    x_30 errors 0.078 (FP32), 0.11 (FP16), 0.14 (BF16), bounded at about three
+    times that.
+  Both solves are followed step by step at first: the residual norms of the
+  first five iterations agree with FP64's to 1e-5 for FP32 (measured 1.3e-7;
+  FP16 4.5e-5 and BF16 2e-4, bounded at 5e-4 and 2e-3),
+  so the later drift of the iterate comes from the solve itself, which does
+  not converge and carries the operator's FP32 difference from FP64
+  (5e-7 per application) into the slow components of x.  For FP32 the test
+  also solves again with another k-space tile extent, which changes only
+  the order of the spread's sums: the two FP32 iterates agree to 1e-3
+  (measured 1e-5 and 4e-5).
 """
 import json
 import os
@@ -43,7 +53,9 @@ ADJ_BAR = {"fp32": 1e-5, "fp16": 1e-3, "bf16": 1e-3}
 # voxels); every case also keeps the final residual ratio within a factor 2
 # of FP64's
 X_BAR = {1e-3: {"fp32": 0.3, "fp16": 0.45, "bf16": 0.6},
-         0.5: {"fp32": 1e-4, "fp16": 1e-2, "bf16": 3e-2}}
+         0.5: {"fp32": 0.25, "fp16": 0.35, "bf16": 0.45}}
+# residual norms of the first five iterations against FP64's (relative)
+EARLY_BAR = {"fp32": 1e-5, "fp16": 5e-4, "bf16": 2e-3}
 GOLDENS = {1e-3: GOLDEN, 0.5: GOLDEN.replace(".json", "_lam0.5.json")}
 
 
@@ -101,10 +113,22 @@ def test_mixed128_cg_against_fp64(inputs, storage, lam):
     hist = np.array(hist)
     eb, ex = _err(b, b_ref), _err(xs, x_ref)
     eh = float(np.max(np.abs(hist - hist_ref) / hist_ref))
-    say(f"  {storage}: A^H y {eb:.2e}, x_30 {ex:.2e}, residual history {eh:.2e} "
+    e5 = float(np.max(np.abs(hist[:6] - hist_ref[:6]) / hist_ref[:6]))
+    say(f"  {storage}: A^H y {eb:.2e}, x_30 {ex:.2e}, residual history {eh:.2e}, first five {e5:.2e} "
         f"(||r_30||/||r_0|| {hist[-1] / hist[0]:.3e} vs FP64 {hist_ref[-1] / hist_ref[0]:.3e})")
     assert eb < ADJ_BAR[storage]
+    assert e5 < EARLY_BAR[storage]
     assert np.all(np.isfinite(hist)) and np.isfinite(ex)
     assert ex < X_BAR[lam][storage]
     ratio = (hist[-1] / hist[0]) / (hist_ref[-1] / hist_ref[0])
     assert 0.5 < ratio < 2.0
+    if storage == "fp32":
+        # the same solve with the k-space spread's sums in another order
+        # (8 x 8 x 8 tiles instead of 8 x 4 x 8; trajectories binned anew)
+        plan.set_option("ktile_t1", 8)
+        trs2 = [plan.traj(to_dev(k)) for k in inp["k"]]
+        x2, _ = plan.cg_solve(yd, mots, S, trs2, lam, w.cg_iters)
+        xs2 = x2.reshape(-1)[idx].cpu().numpy()
+        d_order = _err(xs2, xs)
+        say(f"  fp32 with another spread summation order: x_30 {d_order:.2e} from the first FP32 solve")
+        assert d_order < 1e-3
