@@ -1278,7 +1278,9 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
     // centred pad, F along axis 0
     fft2_pass<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2_rows<kFP32>(pl, pl->k2buf, pl->blk_k2, kCentred, G0),
                                  st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), 1.f),
-                                 make_tile2(1, (int64_t)G1 * G2 * C, G0, -48));  // 48 lines measured faster here
+                                 make_tile2(1, (int64_t)G1 * G2 * C, G0, pl->blk_k2.tlog < 30 ? -32 : -48));
+    // (lines per workgroup measured at 160^3: 32 with the row-blocked k2
+    // layout, 48 with the plain one)
   } else if (pl->ndim == 2 && fft2_supported(G0) && fft2_supported(G1)) {
     fft2_pass<-1, kJFast, kBFast, 1>(pl, "fft_coil_fwd_last", G1, ld2_expand(pl, m, Sm, n1, 0, G1),
                                  st2<kFP32>(pl->k1buf, (int64_t)G1 * C, C, kDense), make_tile2(n0, C, G1, C));
