@@ -189,6 +189,19 @@ template <class T, class = void>
 struct tile_skip : std::false_type {};
 template <class T>
 struct tile_skip<T, std::void_t<decltype(T::kTileSkip)>> : std::bool_constant<T::kTileSkip> {};
+// A store may read per-line data before the loads (T::Early, T::early(),
+// then T::setup(early, ...)), so that its latency overlaps theirs.
+struct NoEarly {};
+template <class T, class = void>
+struct EarlyOf {
+  using type = NoEarly;
+  static constexpr bool value = false;
+};
+template <class T>
+struct EarlyOf<T, std::void_t<typename T::Early>> {
+  using type = typename T::Early;
+  static constexpr bool value = true;
+};
 
 template <int L1, int L2, int S, int MAP1, int MAP2, class Ld, class St, int GAP = 0>
 __global__ __launch_bounds__(1024) void fft2_kernel(Ld ld, St st, Tile2 g) {
@@ -246,6 +259,14 @@ __global__ __launch_bounds__(1024) void fft2_kernel(Ld ld, St st, Tile2 g) {
 
   // ---- step 1: loads and the L1-point DFTs overlap the twiddle copy ----
   const bool act1 = tid < nl * L2;
+  [[maybe_unused]] typename EarlyOf<St>::type pre{};
+  if constexpr (EarlyOf<St>::value) {
+    if (tid < nl * L1) {
+      int be, ke, ae;
+      decode<MAP2>(tid, g.nb, L1, be, ke, ae);
+      pre = st.early(a0, b0, ae, be, ke, a0 + ae < g.A && b0 + be < g.B);
+    }
+  }
   int bl = 0, n2 = 0, al = 0;
   float2 v[L1];
   if (act1) {
@@ -315,7 +336,12 @@ __global__ __launch_bounds__(1024) void fft2_kernel(Ld ld, St st, Tile2 g) {
   } else {
     if (act2) {
       const bool valid = a0 + al2 < g.A && b0 + bl2 < g.B;
-      auto line = st.setup(a0, b0, al2, bl2, k1, valid);
+      auto line = [&] {
+        if constexpr (EarlyOf<St>::value)
+          return st.setup(pre, a0, b0, al2, bl2, k1, valid);
+        else
+          return st.setup(a0, b0, al2, bl2, k1, valid);
+      }();
 #pragma unroll
       for (int k2 = 0; k2 < L2; ++k2)
         if (!(kGapOut && k2 >= L2 / 4 && k2 < 3 * L2 / 4)) st.template put<L1, L2>(line, k2, u[k2]);
@@ -915,6 +941,49 @@ struct Ld2StridedM : Ld2StridedF<S> {
     typename Ld2StridedF<S>::Line f = ln.f;
     f.off = on ? f.off : kOOB;
     return Ld2StridedF<S>::template get<L1, L2>(f, n1);
+  }
+};
+
+// axis-1 store of the forward pass restricted to a trajectory's touched grid
+// columns (cm as in Ld2StridedM): the axis-0 pass after it transforms only
+// tiles of lines holding a touched column and stores only touched runs, so
+// the other columns are never read into a result.  The column words are
+// read before the loads (Early).
+template <int S>
+struct St2StridedMF : St2StridedF<S> {
+  const uint64_t* cm;
+  int cmC, cmW;
+  struct Early {
+    uint64_t m[kColWords];
+  };
+  struct Line {
+    typename St2StridedF<S>::Line f;
+    uint64_t m[kColWords];
+  };
+  __device__ Early early(int64_t, int64_t b0, int, int bl, int, bool valid) const {
+    Early e;
+    const uint64_t* c = cm + (int64_t)((uint32_t)(b0 + bl) / (uint32_t)cmC) * cmW;
+#pragma unroll
+    for (int w = 0; w < kColWords; ++w) e.m[w] = w < cmW && valid ? c[w] : 0ull;
+    return e;
+  }
+  __device__ Line setup(const Early& e, int64_t a0, int64_t b0, int al, int bl, int k1, bool valid) const {
+    Line ln;
+    ln.f = St2StridedF<S>::setup(a0, b0, al, bl, k1, valid);
+#pragma unroll
+    for (int w = 0; w < kColWords; ++w) {
+      const uint64_t lo = e.m[w], hi = w + 1 < kColWords ? e.m[w + 1] : 0ull;
+      ln.m[w] = k1 == 0 ? lo : (lo >> k1) | (hi << (64 - k1));  // k1 < 64
+    }
+    return ln;
+  }
+  template <int L1, int L2>
+  __device__ void put(const Line& ln, int k2, float2 v) const {
+    const int bit = L1 * k2;  // position k1 + L1 k2 after the lane's shift (dense map)
+    const bool on = (ln.m[bit >> 6] >> (bit & 63)) & 1ull;
+    typename St2StridedF<S>::Line f = ln.f;
+    f.off = on ? f.off : kOOB;
+    St2StridedF<S>::template put<L1, L2>(f, k2, v);
   }
 };
 

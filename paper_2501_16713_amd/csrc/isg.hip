@@ -823,6 +823,34 @@ static bool ax1_masked(const isg_plan* pl, const isg_traj* tr) {
   return strided_fast_ok(l, pl->G[1], g, true, sizeof(float2));
 }
 
+// the forward axis-1 store restricted to the trajectory's touched grid
+// columns, where the buffer-addressed form runs (else null: plain store)
+static bool fwd_ax1_masked(const isg_plan* pl, const isg_traj* tr, const Tile2& g) {
+  if (!ax1_masked(pl, tr)) return false;
+  St2Strided<kFP32> s;
+  s.sa = pl->blk_k2.rs;
+  s.sj = pl->blk_k2.g2c;
+  s.tlog = pl->blk_k2.tlog;
+  s.bs = pl->blk_k2.bs;
+  s.map = kDense;
+  Ld2Strided<kFP32> l;
+  l.sa = (int64_t)pl->n[1] * pl->G[2] * pl->C;
+  l.sj = (int64_t)pl->G[2] * pl->C;
+  l.tlog = 30;
+  l.bs = 0;
+  l.map = kCentred;
+  return strided_fast_ok(s, pl->G[1], g, false, sizeof(float2)) && strided_fast_ok(l, pl->G[1], g, true, sizeof(float2));
+}
+
+static St2StridedMF<kFP32> st2_axis1_masked(const isg_plan* pl, void* p, const Blk& blk, const isg_traj* tr, int L) {
+  St2StridedMF<kFP32> s;
+  static_cast<St2StridedF<kFP32>&>(s) = to_fast(st2_axis1<kFP32>(p, blk, kDense, 1.f), L, Tile2{});
+  s.cm = tr->cact;
+  s.cmC = pl->C;
+  s.cmW = tr->cact_w;
+  return s;
+}
+
 static Ld2StridedM<kFP32> ld2_axis1_masked(const isg_plan* pl, const void* p, const Blk& blk, const isg_traj* tr,
                                            int L) {
   Ld2StridedM<kFP32> l;
@@ -1267,14 +1295,19 @@ static void coil_forward_t(isg_plan* pl, const float2* m, const float2* Sm, void
     fft2_pass<-1, kJFast, kBFast, 1>(pl, "fft_coil_fwd_last", G2, ld2_expand(pl, m, Sm, n2, n1, G2),
                                  st2<kFP32>(pl->k1buf, (int64_t)G2 * C, C, kDense),
                                  make_tile2((int64_t)n0 * n1, C, G2, C));
-    // centred pad, F along axis 1 (into the row-blocked k2buf).  Storing the
-    // touched grid columns only (a column-masked store like Ld2StridedM)
-    // measured slower: its column bits are loaded after the exchange, on the
-    // store path.
-    fft2_pass<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax1", G1,
-                                     ld2<kFP32>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
-                                     st2_axis1<kFP32>(pl->k2buf, pl->blk_k2, kDense, 1.f),
-                                     make_tile2(n0, (int64_t)G2 * C, G1, -32));  // 32 lines, plain order: measured faster
+    // centred pad, F along axis 1 (into the row-blocked k2buf), storing only
+    // the trajectory's touched grid columns where the buffer form runs (their
+    // column words are read before the loads; read on the store path they
+    // cost more than the stores they save)
+    const Tile2 g1 = make_tile2(n0, (int64_t)G2 * C, G1, -32);  // 32 lines, plain order: measured faster
+    if (tr && fwd_ax1_masked(pl, tr, g1))
+      fft2_pass_fast<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax1", G1,
+                                            ld2<kFP32>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
+                                            st2_axis1_masked(pl, pl->k2buf, pl->blk_k2, tr, G1), g1);
+    else
+      fft2_pass<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax1", G1,
+                                       ld2<kFP32>(pl, pl->k1buf, (int64_t)n1 * G2 * C, (int64_t)G2 * C, kCentred, G1),
+                                       st2_axis1<kFP32>(pl->k2buf, pl->blk_k2, kDense, 1.f), g1);
     // centred pad, F along axis 0
     fft2_pass<-1, kBFast, kBFast, 1>(pl, "fft_coil_fwd_ax0", G0, ld2_rows<kFP32>(pl, pl->k2buf, pl->blk_k2, kCentred, G0),
                                  st2_masked<S>(grid, pl->blk_grid, tile_mask(pl, tr), 1.f),
