@@ -101,11 +101,14 @@ def test_handles_outlive_their_plan():
     assert mo.handle is None and tr.handle is None
 
 
-@pytest.mark.parametrize("shape,C", [((16, 20, 24), 1), ((24, 16, 20), 3), ((20, 24, 16), 5), ((16, 16, 32), 12)])
+@pytest.mark.parametrize("shape,C", [((16, 20, 24), 1), ((24, 16, 20), 3), ((20, 24, 16), 5), ((16, 16, 32), 12),
+                                     ((16, 16, 160), 1)])
 def test_register_spread_coil_counts(shape, C):
     """k-space tiles of 8 x 4 x 8 (the register-accumulating spread) with odd
     and even coil counts, one of them a single coil, against the oracle's
-    adjoint; several states so the tile-major output holds split tiles too"""
+    adjoint; several states so the tile-major output holds split tiles too.
+    One coil along a last axis of 160 (lines of 320 = 16 x 20) gives the
+    coil-reduction epilogue its most outputs per thread (8)."""
     import paper_2501_16713_amd as isg
     say(f"register spread {shape} C={C}")
     g = np.random.default_rng(C)
