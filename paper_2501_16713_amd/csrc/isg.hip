@@ -498,12 +498,17 @@ static Tile2 make_tile2(int64_t A, int64_t B, int L, int nb_fixed, int budget = 
     g.na = 1;
   }
   g.tiles_b = (B + g.nb - 1) / g.nb;
-  // line stride in the float exchange buffer: 2 mod 4 keeps the step-1
-  // stores and step-2 loads of a wavefront on distinct LDS banks within each
-  // half-wavefront for every factorization above (an odd stride, right for
-  // 8-byte elements, costs two-way conflicts with 4-byte ones)
+  // line stride in the float exchange buffer: with up to 16 lines along the
+  // inner extent, 2 mod 4 keeps the step-1 stores and step-2 loads of a
+  // wavefront on distinct LDS banks within each half-wavefront for every
+  // factorization above; with 32 or more, an odd stride does (a bank model
+  // of 32 four-byte banks per half-wavefront, and measured)
   int LS = L1 * (L2 + 1);
-  while (LS % 4 != 2) ++LS;
+  if (g.nb >= 32) {
+    if (!(LS & 1)) ++LS;
+  } else {
+    while (LS % 4 != 2) ++LS;
+  }
   g.LS = LS;
   g.tiles = 0;
   return g;
