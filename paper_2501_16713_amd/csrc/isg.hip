@@ -2469,7 +2469,7 @@ static isg_status tune(isg_plan* pl, int P, const float2* x, const isg_motion* c
   const std::vector<int> t1s = pl->ndim == 3 ? std::vector<int>{8, 4} : std::vector<int>{16, 8};
   int best_kb = 0, best_t1 = t1s[0], best_chunk = 512, best_batch = 1, best_graph = 0;
   double best = 1e30;
-  const std::vector<int> kbs = pl->ndim == 3 ? std::vector<int>{3, 2, 4, 0} : std::vector<int>{0};
+  const std::vector<int> kbs = pl->ndim == 3 ? std::vector<int>{3, 2, 1, 4, 0} : std::vector<int>{0};
   for (int kb : kbs) {
     const double ms = measure(kb, t1s[0], 512, 1, 0);
     if (ms < best) {

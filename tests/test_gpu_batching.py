@@ -209,7 +209,7 @@ def test_kspace_blocking_is_bit_exact(setup):
     y = to_dev((np.random.default_rng(6).standard_normal((M, w.ncoils, 2)) @ [1, 1j]).astype(np.complex64))
     plan, S, mots, trs = _plan(isg, w, inp)
     ref = None
-    for kb in (0, 3, 2, 4):
+    for kb in (0, 3, 2, 1, 4):
         say(f"k-space blocking {kb}")
         plan.set_option("kblock", kb)
         assert plan.get_option("kblock") == kb
@@ -226,7 +226,7 @@ def test_kspace_blocking_is_bit_exact(setup):
 
 
 @pytest.mark.parametrize("shape,storage,kblocks", [
-    ((16, 32, 48), "fp32", (0, 2)),   # every length has a buffer-addressed form (G = 32, 64, 96)
+    ((16, 32, 48), "fp32", (0, 1, 2)),  # every length has a buffer-addressed form (G = 32, 64, 96)
     ((32, 48, 64), "fp16", (2, 3)),   # half-precision grids; blocks of 8 rows fail 8 | 12 on axis 1
     ((20, 24, 16), "fp32", (2,)),     # G = 40, 48 have none, G = 32 has: mixed passes
     ((48, 40), "bf16", (0,)),         # 2D
