@@ -216,7 +216,8 @@ isg_status isg_plan_get_option(const isg_plan* plan, isg_option option, int64_t*
  * given inputs for candidate k-space array blockings, k-space tile extents,
  * spread chunk sizes, phase
  * batch sizes and graph replay (a coordinate search, each candidate the best
- * of `reps` timed applications after one warm-up), keeps the fastest setting
+ * of `reps` timed applications after one warm-up, ending with the blockings
+ * next to the chosen one under the other chosen options), keeps the fastest setting
  * in the plan and re-prepares the given trajectories for it (others prepared
  * on this plan must be re-created if the tile extent changed).  Candidates that do not
  * fit in device memory are skipped.  report (host, may be NULL) receives a

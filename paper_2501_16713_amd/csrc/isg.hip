@@ -2511,6 +2511,19 @@ static isg_status tune(isg_plan* pl, int P, const float2* x, const isg_motion* c
       best_graph = 1;
     }
   }
+  // the blockings next to the chosen one again, with the other options
+  // chosen (the first comparison ran with the defaults)
+  if (pl->ndim == 3 && best_kb > 0) {
+    const int kb0 = best_kb;
+    for (int kb : {kb0 - 1, kb0 + 1}) {
+      if (kb < 1 || kb > 4) continue;
+      const double ms = measure(kb, best_t1, best_chunk, best_batch, best_graph);
+      if (ms < best) {
+        best = ms;
+        best_kb = kb;
+      }
+    }
+  }
   apply(best_kb, best_t1, best_chunk, best_batch, best_graph);
   drop_normal_graph(pl);
   HIP_OK(hipStreamSynchronize(pl->stream));
